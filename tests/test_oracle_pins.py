@@ -1,0 +1,512 @@
+"""Pins of the CPU oracle against things other than itself.
+
+Each test checks the oracle against a fact the paper or mathematics fixes, or
+against an independent implementation (numpy's padding, published Philox
+vectors, PyTorch's open-source Philox header, scipy's Laplace distribution,
+brute force, torch fp64 autograd).  A plausible slip in the oracle — a dropped
+term, a wrong sign or index, a transposed operand, b instead of b^2 — makes at
+least one of them fail.
+"""
+import math
+import os
+import subprocess
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import Params, INF
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+# --------------------------------------------------------------------------
+# Mirror padding (Alg. 2 step 4, Alg. 3 step 3): numpy's pad modes
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("mode,npmode", [(oracle.PAD_SYMMETRIC, "symmetric"), (oracle.PAD_REFLECT, "reflect")])
+def test_fold_matches_numpy_pad(mode, npmode):
+    for L in range(1, 9):
+        for P in range(0, 40):
+            if npmode == "reflect" and L == 1:
+                want = np.zeros(L + P, np.int64)   # numpy repeats the only pixel
+            else:
+                want = np.pad(np.arange(L), (0, P), mode=npmode)
+            got = [oracle.fold(x, L, mode) for x in range(L + P)]
+            assert list(want) == got, (L, P)
+
+
+# --------------------------------------------------------------------------
+# Philox4x32-10: published known answers and PyTorch's independent engine
+# --------------------------------------------------------------------------
+def _kat():
+    rows = []
+    with open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                v = [int(x, 16) for x in line.split()]
+                rows.append((v[0:4], v[4:6], tuple(v[6:10])))
+    return rows
+
+
+def test_philox_known_answers():
+    rows = _kat()
+    assert len(rows) == 3
+    for ctr, key, want in rows:
+        assert oracle.philox4x32_10(ctr, key) == want
+
+
+TORCH_PHILOX_PROG = r"""
+#include <ATen/core/PhiloxRNGEngine.h>
+#include <cstdio>
+#include <cstdlib>
+int main() {
+  unsigned c0, c1, c2, c3, k0, k1;
+  while (scanf("%x %x %x %x %x %x", &c0, &c1, &c2, &c3, &k0, &k1) == 6) {
+    uint64_t seed = (uint64_t)k0 | ((uint64_t)k1 << 32);
+    uint64_t sub = (uint64_t)c2 | ((uint64_t)c3 << 32);
+    uint64_t off = (uint64_t)c0 | ((uint64_t)c1 << 32);
+    at::philox_engine e(seed, sub, off);
+    unsigned a = e(), b = e(), c = e(), d = e();
+    printf("%08x %08x %08x %08x\n", a, b, c, d);
+  }
+  return 0;
+}
+"""
+
+
+def test_philox_matches_torch_engine(tmp_path):
+    torch = pytest.importorskip("torch")
+    inc = os.path.join(os.path.dirname(torch.__file__), "include")
+    if not os.path.exists(os.path.join(inc, "ATen", "core", "PhiloxRNGEngine.h")):
+        pytest.skip("torch Philox header not shipped")
+    src = tmp_path / "phx.cpp"
+    src.write_text(TORCH_PHILOX_PROG)
+    exe = tmp_path / "phx"
+    subprocess.check_call(["g++", "-O1", "-std=c++17", "-I", inc, str(src), "-o", str(exe)])
+    r = rng(7)
+    cases = [tuple(int(x) for x in r.integers(0, 2**32, size=6, dtype=np.uint64)) for _ in range(300)]
+    cases += [(i, 0, 0, 0, 0, 0) for i in range(20)] + [(0, 0, 0, 0, i, 2**32 - 1 - i) for i in range(20)]
+    inp = "".join("%x %x %x %x %x %x\n" % c for c in cases)
+    out = subprocess.run([str(exe)], input=inp, capture_output=True, text=True, check=True).stdout.split("\n")
+    for c, line in zip(cases, out):
+        want = tuple(int(x, 16) for x in line.split())
+        assert oracle.philox4x32_10(c[:4], c[4:]) == want, c
+
+
+def test_noise_counter_layout():
+    # ctr = (id, ch | level<<8, frame_lo, frame_hi); key = (seed_lo, seed_hi)
+    seed, fi = 0x0123456789ABCDEF, 0xFEDCBA9876543210
+    for cid, ch, lvl in [(0, 0, 0), (77, 2, 1), (2**32 - 1, 3, 1)]:
+        want = oracle.philox4x32_10([cid, ch | (lvl << 8), fi & 0xFFFFFFFF, fi >> 32],
+                                    [seed & 0xFFFFFFFF, seed >> 32])
+        assert oracle.noise_words(seed, fi, cid, ch, lvl) == want
+
+
+# --------------------------------------------------------------------------
+# Uniform and Laplace transforms
+# --------------------------------------------------------------------------
+def test_uniform_exact_grid():
+    for w0, w1 in [(0, 0), (0xFFFFFFFF, 0xFFFFFFFF), (0x12345678, 0x9ABCDEF0), (0xFFF, 0), (0x1000, 0)]:
+        x = (w1 << 32) | w0
+        k = x >> 12
+        u = oracle.uniform(w0, w1)
+        assert 0.0 < u < 1.0
+        # exact value (2k+1)/2^53, checked with integer arithmetic
+        assert u.as_integer_ratio() == ((2 * k + 1) // math.gcd(2 * k + 1, 2**53), 2**53 // math.gcd(2 * k + 1, 2**53))
+    assert oracle.uniform(0, 0) == 2.0**-53
+    assert oracle.uniform(0xFFFFFFFF, 0xFFFFFFFF) == 1.0 - 2.0**-53
+
+
+def test_laplace_inverse_cdf_closed_form():
+    # F(eta) must return u: F(x) = exp(x/s)/2 (x<0), 1 - exp(-x/s)/2 (x>=0)
+    s = 3.7
+    for u in [2.0**-53, 1e-9, 0.1, 0.25, 0.4999, 0.5, 0.75, 0.9, 1 - 2.0**-53]:
+        eta = oracle.laplace(u, s)
+        F = 0.5 * math.exp(eta / s) if eta < 0 else 1.0 - 0.5 * math.exp(-eta / s)
+        assert F == pytest.approx(u, rel=1e-12, abs=1e-15)
+    assert oracle.laplace(0.5, s) == 0.0
+    assert oracle.laplace(0.25, s) == pytest.approx(-s * math.log(2.0), rel=1e-15)
+    assert oracle.laplace(0.75, s) == pytest.approx(s * math.log(2.0), rel=1e-15)
+
+
+# --------------------------------------------------------------------------
+# Sensitivity and noise scale (Eq. 11, Eq. 17)
+# --------------------------------------------------------------------------
+def test_sigma_closed_forms():
+    assert oracle.sigma(16, 16, 0.5) == 31.875            # 255*16/(256*0.5)
+    assert oracle.sigma(32, 16, 1.0) == 3.984375          # 255*16/1024
+    assert oracle.sigma(8, 16, 0.3) == pytest.approx(212.5, rel=1e-15)
+    assert oracle.sigma(2, 1, 100.0) == pytest.approx(0.6375, rel=1e-15)
+    assert oracle.sigma(1, 1, 1.0) == 255.0
+    assert oracle.sigma(16, 16, INF) == 0.0
+    # Eq. (17): Delta = Delta_s / n^2 for b = n * s_b
+    for sb, n in [(2, 2), (4, 4), (8, 4), (3, 5)]:
+        assert oracle.sigma(n * sb, 7, 1.0) * n * n == pytest.approx(oracle.sigma(sb, 7, 1.0), rel=1e-14)
+
+
+def test_laplace_moments_and_ks():
+    """2048x2048 constant 128, b=2, m=1, eps=100: 1,048,576 noisy means with
+    sigma = 0.6375, none clipped; mean 0, variance 2 sigma^2, E|eta| = sigma."""
+    scipy_stats = pytest.importorskip("scipy.stats")
+    H = W = 2048
+    p = Params(H, W, 1, b=2, sb=2, m=1, eps_simple=100.0, eps_complex=100.0, seed=12345, frame_index=3)
+    img = np.full((H, W, 1), 128, np.uint8)
+    o = oracle.forward(img, None, p)
+    eta = o["bg"][:, 0].astype(np.float64) - 128.0
+    n = eta.size
+    assert n == 1024 * 1024
+    s = 0.6375
+    assert abs(eta.mean()) < 5 * math.sqrt(2) * s / math.sqrt(n)
+    var = eta.var()
+    # Var of the sample variance of Laplace: (mu4 - sigma^4)/n with mu4 = 24 s^4, var = 2 s^2
+    assert abs(var - 2 * s * s) < 5 * math.sqrt((24 - 4) * s**4 / n)
+    assert abs(np.abs(eta).mean() - s) < 5 * s / math.sqrt(n)
+    ks = scipy_stats.kstest(eta, scipy_stats.laplace(scale=s).cdf)
+    assert ks.pvalue > 1e-3
+    # the fp32 store is the only rounding: recovered eta is within fp32 ulp of 128
+    assert (o["pass_bg"] == 1).all()
+
+
+# --------------------------------------------------------------------------
+# Sums and means: brute force, closed forms, reshape-based block means
+# --------------------------------------------------------------------------
+def _padded(img, b, mode):
+    M, N = img.shape[:2]
+    GR, GC = -(-M // b), -(-N // b)
+    npmode = "symmetric" if mode == oracle.PAD_SYMMETRIC else "reflect"
+    if npmode == "reflect" and (M == 1 or N == 1):
+        pytest.skip("numpy reflect is undefined for a single row/column")
+    pad = ((0, GR * b - M), (0, GC * b - N)) + ((0, 0),) * (img.ndim - 2)
+    return np.pad(img, pad, mode=npmode), GR, GC
+
+
+def _block_sum(x, b):
+    """(H, W, C) with H, W multiples of b -> (H/b, W/b, C) sums via reshape."""
+    H, W, C = x.shape
+    return x.reshape(H // b, b, W // b, b, C).sum(axis=(1, 3))
+
+
+@pytest.mark.parametrize("M,N,C,b,sb,mode", [
+    (16, 16, 1, 4, 2, 0), (13, 17, 3, 4, 2, 0), (13, 17, 3, 4, 2, 1), (5, 3, 1, 8, 2, 0),
+    (1, 1, 1, 4, 1, 0), (7, 30, 3, 6, 3, 0), (37, 20, 2, 12, 4, 1), (3, 3, 3, 16, 8, 0),
+])
+def test_sums_brute_force(M, N, C, b, sb, mode):
+    r = rng(M * 1000 + N)
+    img = r.integers(0, 256, (M, N, C)).astype(np.uint8)
+    mk = (r.random((M, N)) < 0.2).astype(np.uint8)
+    p = Params(M, N, C, b=b, sb=sb, m=3, eps_simple=INF, eps_complex=INF, tau=1, pad_mode=mode)
+    o = oracle.forward(img, mk, p, sums=True)
+    xp, GR, GC = _padded(img.astype(np.int64), b, mode)
+    # brute force: python loops over every padded position
+    cs = np.zeros((GR, GC, C), np.int64)
+    for i in range(GR * b):
+        for j in range(GC * b):
+            cs[i // b, j // b] += xp[i, j]
+    assert np.array_equal(o["coarse_sum"], cs)
+    assert np.array_equal(o["fine_sum"], _block_sum(xp, sb))
+    # coarse sum = sum of its n^2 fine sums
+    n = b // sb
+    fs = o["fine_sum"].reshape(GR, n, GC, n, C).sum(axis=(1, 3))
+    assert np.array_equal(fs, o["coarse_sum"])
+
+
+def test_constant_and_ramp_closed_forms():
+    # constant image v: every sum = v * area, every noise-free stat = v
+    p = Params(40, 56, 3, b=8, sb=4, m=2, eps_simple=INF, eps_complex=INF, tau=1)
+    img = np.full((40, 56, 3), 77, np.uint8)
+    mk = np.zeros((40, 56), np.uint8)
+    mk[8:20, 16:40] = 1
+    o = oracle.forward(img, mk, p, sums=True)
+    assert (o["coarse_sum"] == 77 * 64).all() and (o["fine_sum"] == 77 * 16).all()
+    assert (o["bg"] == 77).all() and (o["fg"] == 77).all() and (o["recon_u8"] == 77).all()
+    # ramp I(i,j) = i + j on cells inside the image: S = b^3 (r + c) + b^2 (b - 1)
+    b = 8
+    i, j = np.meshgrid(np.arange(64), np.arange(96), indexing="ij")
+    ramp = (i + j).astype(np.float64)[:, :, None]
+    p = Params(64, 96, 1, b=b, sb=b, m=1, eps_simple=INF, eps_complex=INF)
+    o = oracle.forward(ramp, None, p, sums=True)
+    r, c = np.meshgrid(np.arange(8), np.arange(12), indexing="ij")
+    assert np.array_equal(o["coarse_sum"][:, :, 0], b**3 * (r + c) + b * b * (b - 1))
+    # a mean is exact: (b^3 (r+c) + b^2 (b-1)) / b^2 = b (r+c) + (b-1)
+    assert np.array_equal(o["bg"][:, 0].reshape(8, 12), (b * (r + c) + b - 1).astype(np.float32))
+
+
+def test_b1_noise_off_is_identity():
+    r = rng(3)
+    for (M, N, C) in [(1, 1, 1), (31, 17, 3), (64, 64, 1)]:
+        img = r.integers(0, 256, (M, N, C)).astype(np.uint8)
+        p = Params(M, N, C, b=1, sb=1, m=1, eps_simple=INF, eps_complex=INF)
+        o = oracle.forward(img, None, p)
+        assert np.array_equal(o["recon_u8"], img)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_noise_off_is_block_mean_alg3(mode):
+    """Noise-free Alg. 3 equals block means over the mirror-padded image:
+    coarse b x b for simple cells and s_b x s_b for complex ones, computed here
+    with numpy padding and reshape."""
+    r = rng(11)
+    M, N, C, b, sb = 45, 70, 3, 16, 4
+    img = r.integers(0, 256, (M, N, C)).astype(np.uint8)
+    mk = np.zeros((M, N), np.uint8)
+    mk[10:30, 20:45] = 1
+    p = Params(M, N, C, b=b, sb=sb, m=16, eps_simple=INF, eps_complex=INF, tau=1, pad_mode=mode)
+    o = oracle.forward(img, mk, p)
+    xp, GR, GC = _padded(img.astype(np.float64), b, mode)
+    mp, _, _ = _padded(mk.astype(np.int64)[:, :, None], b, mode)
+    n = b // sb
+    coarse = _block_sum(xp, b) / (b * b)
+    fine = _block_sum(xp, sb) / (sb * sb)
+    cnt = _block_sum(mp, b)[:, :, 0]
+    flags = (cnt >= 1).astype(np.uint8)
+    assert np.array_equal(o["flags"], flags)
+    assert np.array_equal(o["bg"], coarse[flags == 0].astype(np.float32))
+    fine_cells = fine.reshape(GR, n, GC, n, C).transpose(0, 2, 1, 3, 4).reshape(GR, GC, n * n, C)
+    assert np.array_equal(o["fg"], fine_cells[flags == 1].astype(np.float32))
+    # assembled image, cropped: each pixel takes its cell's or subcell's value
+    want = np.where(np.kron(flags, np.ones((b, b), np.uint8))[:, :, None] == 1,
+                    np.repeat(np.repeat(fine, sb, 0), sb, 1), np.repeat(np.repeat(coarse, b, 0), b, 1))
+    want = want[:M, :N].astype(np.float32)
+    assert np.array_equal(o["recon_f32"], want)
+    assert np.array_equal(o["recon_u8"], np.rint(want).astype(np.uint8))
+
+
+def test_noise_off_alg2_and_alg1():
+    """Without a mask the method is Algorithm 2; when b divides M and N there is
+    no padding and it also equals Algorithm 1 (means over each grid's h x w
+    real pixels)."""
+    r = rng(5)
+    M, N, b = 48, 80, 16
+    img = r.integers(0, 256, (M, N, 1)).astype(np.uint8)
+    p = Params(M, N, 1, b=b, sb=b, m=16, eps_simple=INF, eps_complex=INF)
+    o = oracle.forward(img, None, p)
+    alg1 = np.zeros((M, N), np.float64)
+    for r0 in range(0, M, b):
+        for c0 in range(0, N, b):
+            h, w = min(b, M - r0), min(b, N - c0)
+            alg1[r0:r0 + h, c0:c0 + w] = img[r0:r0 + h, c0:c0 + w, 0].mean()
+    assert np.array_equal(o["recon_f32"][:, :, 0], alg1.astype(np.float32))
+    # an empty mask (all simple) gives the same store and noise as no mask
+    p = Params(M, N, 1, b=b, sb=4, m=16, eps_simple=0.5, eps_complex=0.5, seed=9)
+    a = oracle.forward(img, None, p)
+    z = oracle.forward(img, np.zeros((M, N), np.uint8), p)
+    assert np.array_equal(a["bg"], z["bg"]) and np.array_equal(a["recon_u8"], z["recon_u8"])
+
+
+@pytest.mark.parametrize("b", [2, 4, 5, 8])
+def test_default_threshold_is_papers_mask_rule(b):
+    """tau = 0 reproduces Alg. 3 steps 5-6: with the paper's simple-region mask
+    S = 1 - F, a cell is simple iff mean(S) > 0.5, complex iff <= 0.5 (ties
+    are complex)."""
+    r = rng(b)
+    M, N = 7 * b + 3, 9 * b + 1
+    for density in [0.3, 0.5, 0.7]:
+        F = (r.random((M, N)) < density).astype(np.uint8)
+        p = Params(M, N, 1, b=b, sb=b, m=1, eps_simple=INF, eps_complex=INF, tau=0)
+        o = oracle.forward(np.zeros((M, N, 1), np.uint8), F, p)
+        Sp, _, _ = _padded((1 - F).astype(np.float64)[:, :, None], b, 0)
+        mu_mask = _block_sum(Sp, b)[:, :, 0] / (b * b)
+        assert np.array_equal(o["flags"], (mu_mask <= 0.5).astype(np.uint8))
+    if b % 2 == 0:  # an exact tie is complex
+        F = np.zeros((b, b), np.uint8)
+        F[: b // 2] = 1
+        p = Params(b, b, 1, b=b, sb=b, m=1, eps_simple=INF, eps_complex=INF, tau=0)
+        assert oracle.forward(np.zeros((b, b, 1), np.uint8), F, p)["flags"][0, 0] == 1
+
+
+# --------------------------------------------------------------------------
+# Privacy: Laplace privacy loss by brute force over neighbouring images
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("m", [1, 2])
+@pytest.mark.parametrize("eps_s,eps_c", [(0.7, 0.7), (1.0, 0.3), (0.25, 2.0)])
+def test_privacy_loss_brute_force(m, eps_s, eps_c):
+    """For the Laplace mechanism the worst-case log-likelihood ratio between
+    the outputs on neighbouring images is sum_k |mu_k(I1)-mu_k(I2)| / sigma_k.
+    Over every neighbour that changes <= m pixels of an 8x8 image by the full
+    255 this must stay <= max(eps_s, eps_c) (Thm. 1 and Thm. 5), with equality
+    when the changes fall in the region of the larger budget."""
+    M = N = 8
+    b, sb = 4, 2
+    F = np.zeros((M, N), np.uint8)
+    F[0:4, 4:8] = 1          # one complex cell, three simple ones
+    off = Params(M, N, 1, b=b, sb=sb, m=m, eps_simple=INF, eps_complex=INF, tau=1)
+    base = np.zeros((M, N, 1), np.uint8)
+    o0 = oracle.forward(base, F, off)
+    s_s, s_c = oracle.sigma(b, m, eps_s), oracle.sigma(sb, m, eps_c)
+    worst = 0.0
+    pixels = list(itertools.product(range(M), range(N)))
+    for k in range(1, m + 1):
+        for sub in itertools.combinations(pixels, k):
+            img = base.copy()
+            for (i, j) in sub:
+                img[i, j, 0] = 255
+            o = oracle.forward(img, F, off)
+            loss = (np.abs(o["bg"].astype(np.float64) - o0["bg"]).sum() / s_s
+                    + np.abs(o["fg"].astype(np.float64) - o0["fg"]).sum() / s_c)
+            worst = max(worst, loss)
+    assert worst <= max(eps_s, eps_c) * (1 + 1e-12)
+    assert worst == pytest.approx(max(eps_s, eps_c), rel=1e-12)
+
+
+def test_noise_scale_per_region_matches_sigma():
+    """Empirical E|eta| of each region equals its sigma (per-region budgets)."""
+    M, N = 512, 512
+    p = Params(M, N, 1, b=8, sb=2, m=1, eps_simple=50.0, eps_complex=400.0, tau=1, seed=77)
+    img = np.full((M, N, 1), 128, np.uint8)
+    F = np.zeros((M, N), np.uint8)
+    F[:, 256:] = 1
+    o = oracle.forward(img, F, p)
+    es = o["bg"].astype(np.float64) - 128
+    ec = o["fg"].astype(np.float64) - 128
+    for eta, s in [(es, oracle.sigma(8, 1, 50.0)), (ec, oracle.sigma(2, 1, 400.0))]:
+        assert abs(np.abs(eta).mean() - s) < 5 * s / math.sqrt(eta.size)
+
+
+def test_noise_is_keyed_by_geometry_not_order():
+    """A simple cell's noise does not depend on the class of other cells, and
+    frames with different frame_index get different noise."""
+    M, N = 64, 64
+    img = np.full((M, N, 1), 100, np.uint8)
+    F1 = np.zeros((M, N), np.uint8)
+    F2 = F1.copy()
+    F2[0:16, 0:16] = 1
+    p = Params(M, N, 1, b=16, sb=4, m=1, eps_simple=1.0, eps_complex=1.0, tau=1, seed=5)
+    a, c = oracle.forward(img, F1, p), oracle.forward(img, F2, p)
+    assert np.array_equal(a["bg"][1:], c["bg"])
+    p2 = Params(M, N, 1, b=16, sb=4, m=1, eps_simple=1.0, eps_complex=1.0, tau=1, seed=5, frame_index=1)
+    d = oracle.forward(img, F1, p2)
+    assert not np.array_equal(a["bg"], d["bg"])
+
+
+# --------------------------------------------------------------------------
+# Store (Table IV) and reconstruction from it
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("M,N,C,b,sb", [(50, 70, 3, 16, 4), (9, 9, 1, 4, 1), (33, 65, 3, 32, 8)])
+def test_store_size_and_reconstruct(M, N, C, b, sb):
+    r = rng(M + N)
+    img = r.integers(0, 256, (M, N, C)).astype(np.uint8)
+    mk = (r.random((M, N)) < 0.05).astype(np.uint8)
+    p = Params(M, N, C, b=b, sb=sb, m=4, eps_simple=0.8, eps_complex=0.4, tau=1, seed=2, frame_index=9)
+    o = oracle.forward(img, mk, p)
+    GR, GC, n = o["geometry"]
+    nb, nf = o["counts"]
+    assert nb + nf == GR * GC
+    assert nf == int(o["flags"].sum())
+    assert o["bg"].size == C * nb and o["fg"].size == C * n * n * nf
+    rf, ru = oracle.reconstruct(o["flags"], o["bg"], o["fg"], p)
+    assert np.array_equal(rf, o["recon_f32"]) and np.array_equal(ru, o["recon_u8"])
+    assert (o["bg"] >= 0).all() and (o["bg"] <= 255).all() and (o["fg"] >= 0).all() and (o["fg"] <= 255).all()
+
+
+# --------------------------------------------------------------------------
+# Adjoint: fp64 finite differences and torch fp64 autograd
+# --------------------------------------------------------------------------
+
+
+@pytest.mark.parametrize("M,N,C,b,sb,mode", [(16, 16, 3, 8, 4, 0), (11, 13, 2, 4, 2, 0), (11, 13, 1, 8, 2, 1),
+                                            (5, 3, 1, 8, 4, 0)])
+def test_backward_matches_central_fd(M, N, C, b, sb, mode):
+    r = rng(M * N + C)
+    img = r.uniform(0, 255, (M, N, C))
+    mk = (r.random((M, N)) < 0.3).astype(np.uint8)
+    w = r.standard_normal((M, N, C))
+    p = Params(M, N, C, b=b, sb=sb, m=2, eps_simple=2.0, eps_complex=1.0, tau=1, pad_mode=mode, seed=4)
+    g = oracle.backward(img, mk, w, p)
+    h = 1e-3
+    f = lambda x: float((oracle.forward(x, mk, p)["recon_f64"] * w).sum())
+    for idx in itertools.product(range(M), range(N), range(C)):
+        e = np.zeros_like(img)
+        e[idx] = h
+        fd = (f(img + e) - f(img - e)) / (2 * h)
+        assert fd == pytest.approx(g[idx], abs=1e-7), idx
+
+
+def test_backward_matches_torch_autograd():
+    """torch fp64 autograd of a gather-based definition: indices of the
+    mirror-padded grid from numpy's pad, block means by reshape, the oracle's
+    noise added as a constant, clamp, crop."""
+    torch = pytest.importorskip("torch")
+    M, N, C, b, sb = 13, 19, 3, 8, 4
+    n = b // sb
+    r = rng(21)
+    img = r.uniform(0, 255, (M, N, C))
+    mk = (r.random((M, N)) < 0.25).astype(np.uint8)
+    w = r.standard_normal((M, N, C))
+    p = Params(M, N, C, b=b, sb=sb, m=2, eps_simple=1.0, eps_complex=0.5, tau=1, seed=8, frame_index=2)
+    GR, GC, _ = p.geometry()
+    rows = np.pad(np.arange(M), (0, GR * b - M), mode="symmetric")
+    cols = np.pad(np.arange(N), (0, GC * b - N), mode="symmetric")
+    o = oracle.forward(img, mk, p)
+    flags = o["flags"]
+    x = torch.tensor(img, dtype=torch.float64, requires_grad=True)
+    xp = x[torch.tensor(rows)][:, torch.tensor(cols)]                # (GR*b, GC*b, C)
+    coarse = xp.reshape(GR, b, GC, b, C).mean(dim=(1, 3))
+    fine = xp.reshape(GR * n, sb, GC * n, sb, C).mean(dim=(1, 3))
+    # noise from the oracle's counter-based stream, as constants
+    eta_c = np.zeros((GR, GC, C))
+    eta_f = np.zeros((GR * n, GC * n, C))
+    for rr in range(GR):
+        for cc in range(GC):
+            for ch in range(C):
+                if flags[rr, cc]:
+                    for i in range(n):
+                        for j in range(n):
+                            fid = (rr * n + i) * (GC * n) + (cc * n + j)
+                            wds = oracle.noise_words(p.seed, p.frame_index, fid, ch, 1)
+                            eta_f[rr * n + i, cc * n + j, ch] = oracle.laplace(oracle.uniform(wds[0], wds[1]),
+                                                                               oracle.sigma(sb, p.m, p.eps_complex))
+                else:
+                    wds = oracle.noise_words(p.seed, p.frame_index, rr * GC + cc, ch, 0)
+                    eta_c[rr, cc, ch] = oracle.laplace(oracle.uniform(wds[0], wds[1]), oracle.sigma(b, p.m, p.eps_simple))
+    vc = torch.clamp(coarse + torch.tensor(eta_c), 0, 255)
+    vf = torch.clamp(fine + torch.tensor(eta_f), 0, 255)
+    big_c = vc.repeat_interleave(b, 0).repeat_interleave(b, 1)
+    big_f = vf.repeat_interleave(sb, 0).repeat_interleave(sb, 1)
+    sel = torch.tensor(np.kron(flags, np.ones((b, b), np.uint8)).astype(bool))[:, :, None]
+    y = torch.where(sel, big_f, big_c)[:M, :N]
+    assert np.allclose(y.detach().numpy(), o["recon_f64"], rtol=0, atol=1e-9)
+    (y * torch.tensor(w)).sum().backward()
+    g = oracle.backward(img, mk, w, p)
+    assert np.allclose(x.grad.numpy(), g, rtol=0, atol=1e-12)
+
+
+def test_backward_linear_in_grad_and_zero_when_clipped():
+    M, N = 16, 16
+    p = Params(M, N, 1, b=4, sb=4, m=1, eps_simple=INF, eps_complex=INF)
+    w = np.ones((M, N, 1))
+    for v in (0.0, 255.0):            # noise off, mean on a clip boundary: pass (inclusive, as torch.clamp)
+        g = oracle.backward(np.full((M, N, 1), v), None, w, p)
+        assert np.allclose(g, 1.0)    # each pixel: (sum of 16 ones)/16
+    img = np.full((M, N, 1), 255.0)
+    p = Params(M, N, 1, b=4, sb=4, m=1, eps_simple=1e-3, eps_complex=1e-3, seed=1)  # huge noise
+    o = oracle.forward(img, None, p)
+    g = oracle.backward(img, None, w, p)
+    passed = o["pass_bg"][:, 0].reshape(4, 4)
+    assert np.allclose(g[:, :, 0], np.kron(passed, np.ones((4, 4))))
+
+
+def test_clip_bounds_and_tail_mass():
+    """clip(mu + eta, 0, 255) (Alg. 3 steps 10 and 17): noise-free extremes are
+    kept exactly, and under large noise the mass clipped to each bound is the
+    Laplace tail P(eta > 255 - mu) = exp(-(255 - mu)/sigma)/2 (resp. below -mu)."""
+    for v in (0, 255):
+        p = Params(8, 8, 1, b=4, sb=4, m=1, eps_simple=INF, eps_complex=INF)
+        o = oracle.forward(np.full((8, 8, 1), v, np.uint8), None, p)
+        assert (o["bg"] == v).all() and (o["recon_u8"] == v).all()
+    M = N = 1024
+    p = Params(M, N, 1, b=2, sb=2, m=1, eps_simple=1.0, eps_complex=1.0, seed=99)   # sigma = 63.75
+    mu = 200
+    o = oracle.forward(np.full((M, N, 1), mu, np.uint8), None, p)
+    v = o["bg"][:, 0]
+    s = oracle.sigma(2, 1, 1.0)
+    assert v.min() == 0.0 and v.max() == 255.0
+    for frac, want in [((v == 255.0).mean(), 0.5 * math.exp(-(255 - mu) / s)),
+                       ((v == 0.0).mean(), 0.5 * math.exp(-mu / s))]:
+        assert abs(frac - want) < 5 * math.sqrt(want * (1 - want) / v.size) + 1e-7
+    # pass bits: 1 exactly where the value was not clipped
+    assert np.array_equal(o["pass_bg"][:, 0] == 1, (v > 0) & (v < 255))
