@@ -1,0 +1,68 @@
+"""Differentiable DP pixelization (not in the paper): forward and a
+hand-written adjoint behind ``torch.autograd.Function``.
+
+With the noise frozen by its counter (seed, frame_index) and the mask held
+constant, the layer is piecewise linear in its input: each output pixel is its
+statistic clip(mean + noise) and the adjoint spreads the statistic's gradient
+over the padded cell, divided by the cell area, where the clip did not bind.
+"""
+from __future__ import annotations
+
+from typing import Optional, Sequence
+
+import torch
+
+from . import F32_CHW, FrameParams, Plan
+
+
+class DPPixFn(torch.autograd.Function):
+    """y = pixelize(x) for a batch x of shape (B, C, H, W), float32, on the GPU."""
+
+    @staticmethod
+    def forward(ctx, x: torch.Tensor, plan: Plan, masks: Optional[Sequence[torch.Tensor]] = None):
+        if x.dim() != 4 or x.dtype != torch.float32:
+            raise ValueError("x must be float32 (B, C, H, W)")
+        x = x.contiguous()
+        frames = [x[i] for i in range(x.shape[0])]
+        y = torch.empty_like(x)
+        outs = [y[i] for i in range(x.shape[0])]
+        clip = plan.clip_buffers()
+        plan.plan(masks)
+        plan.forward(frames, out=outs, clip=clip)
+        ctx.plan = plan
+        ctx.save_for_backward(clip[0], clip[1])
+        return y
+
+    @staticmethod
+    def backward(ctx, gy: torch.Tensor):
+        clip_bg, clip_fg = ctx.saved_tensors
+        gy = gy.contiguous()
+        gx = torch.empty_like(gy)
+        ctx.plan.backward([gy[i] for i in range(gy.shape[0])], [gx[i] for i in range(gx.shape[0])],
+                          (clip_bg, clip_fg))
+        return gx, None, None
+
+
+class DPPixLayer(torch.nn.Module):
+    """Module wrapper: one plan per batch geometry, masks given per call."""
+
+    def __init__(self, b: int = 16, sb: Optional[int] = None, m: int = 8, eps_bg: float = 1.0,
+                 eps_fg: Optional[float] = None, tau: int = 1, seed: int = 0, first_frame_index: int = 0):
+        super().__init__()
+        self.kw = dict(b=b, sb=sb, m=m, eps_bg=eps_bg, eps_fg=eps_fg, tau=tau, seed=seed)
+        self.first_frame_index = first_frame_index
+        self._plans = {}
+
+    def plan_for(self, x: torch.Tensor) -> Plan:
+        key = (tuple(x.shape), x.device)
+        p = self._plans.get(key)
+        if p is None:
+            B, C, H, W = x.shape
+            frames = [FrameParams(H, W, C, F32_CHW, frame_index=self.first_frame_index + i, **self.kw)
+                      for i in range(B)]
+            p = Plan(frames, device=x.device)
+            self._plans[key] = p
+        return p
+
+    def forward(self, x: torch.Tensor, masks: Optional[Sequence[torch.Tensor]] = None) -> torch.Tensor:
+        return DPPixFn.apply(x, self.plan_for(x), masks)

@@ -1,0 +1,641 @@
+// dppix_api.hip — host side of the libdppix C ABI: argument validation, plan
+// layout (geometry, tiles, workspace, store capacities) and kernel launches.
+#include "dppix.h"
+#include "dppix_internal.h"
+#include "dppix_tiles.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+using namespace dppix;
+
+namespace {
+
+thread_local std::string g_err;
+
+dppix_status_t fail(dppix_status_t st, const std::string& msg)
+{
+    g_err = msg;
+    return st;
+}
+
+dppix_status_t dev_fail(hipError_t e, const char* what)
+{
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return DPPIX_EDEVICE;
+}
+
+constexpr int kDefaultThreads = 256;
+constexpr int64_t kTileBytesTarget = 4096;  // padded bytes per tile row (u8)
+constexpr int64_t kTileLdsTarget = 48 * 1024;
+constexpr int64_t kTileLdsMax = 150 * 1024;
+constexpr int kMaxDim = 1 << 24;
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+struct dppix_plan {
+    std::vector<dppix_frame_desc_t> desc;
+    std::vector<FrameRec> frames;
+    std::vector<int32_t> sched_frame;
+    std::vector<int64_t> sched_base;
+    int64_t n_tiles = 0;
+    int64_t total_cells = 0;
+    int64_t total_fine = 0;
+    int64_t total_pixels = 0;
+    size_t bg_cap = 0, fg_cap = 0;
+    WsLayout ws{};
+    size_t lds[6] = {0, 0, 0, 0, 0, 0};
+    bool any_f32 = false, any_u8 = false;
+    int threads = kDefaultThreads;
+    int persistent = 0;
+    uint8_t* bound = nullptr;
+    size_t bound_bytes = 0;
+    std::vector<uint8_t> host_tables;   // frames + sched tables as uploaded
+};
+
+struct dppix_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+// Largest multiple of `unit` not above x (at least `unit` when x >= unit).
+int64_t round_down(int64_t x, int64_t unit) { return (x / unit) * unit; }
+
+dppix_status_t validate(const dppix_frame_desc_t& d, int32_t f)
+{
+    char buf[256];
+    auto bad = [&](const char* what) {
+        std::snprintf(buf, sizeof buf, "frame %d: %s", f, what);
+        return fail(DPPIX_EINVAL, buf);
+    };
+    if (d.height < 1 || d.width < 1)
+        return bad("height and width must be >= 1");
+    if (d.height > kMaxDim || d.width > kMaxDim)
+        return fail(DPPIX_ENOTSUP, "frame dimensions above 2^24");
+    if (d.channels < 1 || d.channels > 4)
+        return bad("channels must be in 1..4");
+    if (d.layout != DPPIX_U8_HWC && d.layout != DPPIX_F32_CHW)
+        return bad("unknown layout");
+    if (d.layout == DPPIX_U8_HWC && d.pitch < (int64_t)d.width * d.channels)
+        return bad("pitch must be >= width*channels bytes");
+    if (d.layout == DPPIX_F32_CHW && d.pitch < (int64_t)d.width)
+        return bad("pitch must be >= width floats");
+    if (d.pad_mode != DPPIX_PAD_SYMMETRIC && d.pad_mode != DPPIX_PAD_REFLECT)
+        return bad("unknown pad_mode");
+    if (d.b_fg < 1 || d.b_bg < d.b_fg)
+        return bad("need 1 <= b_fg <= b_bg");
+    if (d.b_bg % d.b_fg != 0)
+        return bad("b_bg must be a multiple of b_fg (b = n * s_b)");
+    if (d.b_bg > kMaxB)
+        return fail(DPPIX_ENOTSUP, "b_bg above 256");
+    if (d.m < 1)
+        return bad("m must be >= 1");
+    if (!(d.eps_bg > 0.0) || !(d.eps_fg > 0.0))
+        return bad("eps_bg and eps_fg must be > 0 (+inf disables noise)");
+    if (d.fg_min_count < 0 || (int64_t)d.fg_min_count > (int64_t)d.b_bg * d.b_bg)
+        return bad("fg_min_count must be in [0, b_bg^2]");
+    if (d.tile_cells < 0)
+        return bad("tile_cells must be >= 0");
+    const int64_t n = d.b_bg / d.b_fg;
+    const int64_t GR = (d.height + d.b_bg - 1) / d.b_bg, GC = (d.width + d.b_bg - 1) / d.b_bg;
+    if ((GR * n) * (GC * n) > (int64_t)UINT32_MAX)
+        return fail(DPPIX_ENOTSUP, "more than 2^32 subcells in one frame");
+    return DPPIX_OK;
+}
+
+double sigma_of(int b, int m, double eps)
+{
+    // Eq. (11): Delta = 255 m / b^2; Eq. (8): sigma = Delta / eps
+    const double delta = 255.0 * (double)m / ((double)b * (double)b);
+    return delta / eps;
+}
+
+// Per-kind LDS bytes of one frame with K cells per tile.
+size_t frame_lds(int kind, const FrameRec& F) { return lds_plan(kind, F.K, F.b, F.n, F.C).bytes; }
+
+int kind_fwd(const FrameRec& F) { return F.layout == DPPIX_F32_CHW ? kFwdF32 : kFwdU8; }
+int kind_rec(const FrameRec& F) { return F.layout == DPPIX_F32_CHW ? kRecF32 : kRecU8; }
+
+// Tile width: about kTileBytesTarget padded bytes per row, tiles of one band
+// balanced, u8 tiles starting on 16-byte boundaries when possible, LDS bounded.
+void choose_tiles(FrameRec& F, int32_t requested)
+{
+    const int64_t unit_bytes = (F.layout == DPPIX_F32_CHW) ? 4 * (int64_t)F.b : (int64_t)F.b * F.C;
+    int64_t align = 16 / std::gcd<int64_t>(16, unit_bytes);  // cells per 16-byte-aligned step
+    int64_t K;
+    if (requested > 0) {
+        K = std::min<int64_t>(requested, F.GC);
+    } else {
+        int64_t kmax = std::max<int64_t>(1, kTileBytesTarget / unit_bytes);
+        if (kmax >= align)
+            kmax = round_down(kmax, align);
+        const int64_t tx = (F.GC + kmax - 1) / kmax;
+        K = (F.GC + tx - 1) / tx;
+        if (K % align != 0 && ((K + align - 1) / align) * align <= kmax)
+            K = ((K + align - 1) / align) * align;
+        K = std::min<int64_t>(K, F.GC);
+    }
+    F.K = (int32_t)std::max<int64_t>(1, K);
+    // keep every tile kind of this frame within the LDS target
+    while (F.K > 1) {
+        size_t need = std::max(frame_lds(kind_fwd(F), F), frame_lds(kind_rec(F), F));
+        need = std::max(need, frame_lds(kClassify, F));
+        if (F.layout == DPPIX_F32_CHW)
+            need = std::max(need, frame_lds(kBwd, F));
+        if ((int64_t)need <= kTileLdsTarget)
+            break;
+        F.K = std::max(1, F.K / 2);
+    }
+    F.TX = (F.GC + F.K - 1) / F.K;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dp_pix_version(void) { return "dppix 0.1 (gfx950)"; }
+
+const char* dp_pix_status_string(dppix_status_t s)
+{
+    switch (s) {
+    case DPPIX_OK: return "ok";
+    case DPPIX_EINVAL: return "invalid argument";
+    case DPPIX_ENOMEM: return "out of memory";
+    case DPPIX_EDEVICE: return "device error";
+    case DPPIX_ENOTSUP: return "not supported";
+    }
+    return "unknown status";
+}
+
+const char* dp_pix_last_error(void) { return g_err.c_str(); }
+
+dppix_status_t dp_pix_plan_create(const dppix_frame_desc_t* descs, int32_t n_frames, dppix_plan_t* out)
+{
+    if (out == nullptr)
+        return fail(DPPIX_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (descs == nullptr || n_frames < 1)
+        return fail(DPPIX_EINVAL, "need at least one frame descriptor");
+    for (int32_t f = 0; f < n_frames; ++f) {
+        dppix_status_t st = validate(descs[f], f);
+        if (st != DPPIX_OK)
+            return st;
+    }
+    dppix_plan* p = new (std::nothrow) dppix_plan;
+    if (p == nullptr)
+        return fail(DPPIX_ENOMEM, "host allocation failed");
+    p->desc.assign(descs, descs + n_frames);
+    p->frames.resize(n_frames);
+    int64_t cell = 0, fine = 0, tile = 0;
+    for (int32_t f = 0; f < n_frames; ++f) {
+        const dppix_frame_desc_t& d = descs[f];
+        FrameRec& F = p->frames[f];
+        std::memset(&F, 0, sizeof F);
+        F.H = d.height;
+        F.W = d.width;
+        F.C = d.channels;
+        F.layout = d.layout;
+        F.pitch = d.pitch;
+        F.b = d.b_bg;
+        F.s = d.b_fg;
+        F.n = d.b_bg / d.b_fg;
+        F.pad = d.pad_mode;
+        F.GR = (d.height + d.b_bg - 1) / d.b_bg;   // G_R = ceil(M / b)
+        F.GC = (d.width + d.b_bg - 1) / d.b_bg;    // G_C = ceil(N / b)
+        F.tau = d.fg_min_count > 0 ? d.fg_min_count : (d.b_bg * d.b_bg + 1) / 2;
+        F.noise_bg = std::isinf(d.eps_bg) ? 0 : 1;
+        F.noise_fg = std::isinf(d.eps_fg) ? 0 : 1;
+        F.sigma_bg = F.noise_bg ? sigma_of(F.b, d.m, d.eps_bg) : 0.0;
+        F.sigma_fg = F.noise_fg ? sigma_of(F.s, d.m, d.eps_fg) : 0.0;
+        F.key0 = (uint32_t)(d.seed & 0xFFFFFFFFu);
+        F.key1 = (uint32_t)(d.seed >> 32);
+        F.fi0 = (uint32_t)(d.frame_index & 0xFFFFFFFFu);
+        F.fi1 = (uint32_t)(d.frame_index >> 32);
+        choose_tiles(F, d.tile_cells);
+        {
+            size_t need = std::max(frame_lds(kind_fwd(F), F), frame_lds(kind_rec(F), F));
+            if ((int64_t)need > kTileLdsMax) {
+                delete p;
+                return fail(DPPIX_ENOTSUP, "n*n*channels too large for one tile in LDS");
+            }
+        }
+        F.cell_base = cell;
+        F.fine_base = fine;
+        F.tile_base = tile;
+        cell += (int64_t)F.GR * F.GC;
+        fine += (int64_t)F.GR * F.n * F.GC * F.n;
+        tile += (int64_t)F.GR * F.TX;
+        p->bg_cap += (size_t)F.GR * F.GC * F.C;
+        p->fg_cap += (size_t)F.GR * F.GC * F.n * F.n * F.C;
+        p->total_pixels += (int64_t)F.H * F.W;
+        if (F.layout == DPPIX_F32_CHW)
+            p->any_f32 = true;
+        else
+            p->any_u8 = true;
+        for (int k = 0; k < 6; ++k) {
+            if (k == kBwd && F.layout != DPPIX_F32_CHW)
+                continue;
+            if ((k == kFwdU8 || k == kRecU8) && F.layout != DPPIX_U8_HWC)
+                continue;
+            if ((k == kFwdF32 || k == kRecF32) && F.layout != DPPIX_F32_CHW)
+                continue;
+            p->lds[k] = std::max(p->lds[k], frame_lds(k, F));
+        }
+    }
+    p->total_cells = cell;
+    p->total_fine = fine;
+    p->n_tiles = tile;
+    if (tile > (int64_t)INT32_MAX) {
+        delete p;
+        return fail(DPPIX_ENOTSUP, "more than 2^31 tiles");
+    }
+    // Scheduling order: frames with the heaviest tiles first (longest tiles
+    // start early, the tail is made of light ones); ties keep batch order.
+    std::vector<int32_t> order(n_frames);
+    std::iota(order.begin(), order.end(), 0);
+    auto tile_cost = [&](int32_t f) {
+        const FrameRec& F = p->frames[f];
+        const int64_t bpp = F.layout == DPPIX_F32_CHW ? 4 : 1;
+        return (int64_t)F.b * F.K * F.b * F.C * bpp;
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return tile_cost(x) > tile_cost(y); });
+    p->sched_frame = order;
+    p->sched_base.resize(n_frames + 1);
+    int64_t acc = 0;
+    for (int32_t k = 0; k < n_frames; ++k) {
+        p->sched_base[k] = acc;
+        const FrameRec& F = p->frames[order[k]];
+        acc += (int64_t)F.GR * F.TX;
+    }
+    p->sched_base[n_frames] = acc;
+
+    // Workspace layout.
+    WsLayout& w = p->ws;
+    size_t o = 0;
+    w.frames = o;      o = align256(o + sizeof(FrameRec) * n_frames);
+    w.sched_frame = o; o = align256(o + sizeof(int32_t) * n_frames);
+    w.sched_base = o;  o = align256(o + sizeof(int64_t) * (n_frames + 1));
+    w.flags = o;       o = align256(o + (size_t)p->total_cells);
+    w.tile_cnt = o;    o = align256(o + sizeof(uint32_t) * (size_t)p->n_tiles);
+    w.tile_fg = o;     o = align256(o + sizeof(uint32_t) * (size_t)p->n_tiles);
+    w.frame_tot = o;   o = align256(o + sizeof(uint64_t) * 2 * n_frames);
+    w.frame_base = o;  o = align256(o + sizeof(uint64_t) * 2 * n_frames);
+    w.counters = o;    o = align256(o + sizeof(uint32_t) * 8);
+    w.total = o;
+
+    // Host image of the static tables (frames, sched_frame, sched_base).
+    p->host_tables.assign(w.flags, 0);
+    std::memcpy(p->host_tables.data() + w.frames, p->frames.data(), sizeof(FrameRec) * n_frames);
+    std::memcpy(p->host_tables.data() + w.sched_frame, p->sched_frame.data(), sizeof(int32_t) * n_frames);
+    std::memcpy(p->host_tables.data() + w.sched_base, p->sched_base.data(), sizeof(int64_t) * (n_frames + 1));
+    *out = p;
+    return DPPIX_OK;
+}
+
+void dp_pix_plan_destroy(dppix_plan_t p) { delete p; }
+
+dppix_status_t dp_pix_plan_sizes(dppix_plan_t p, dppix_sizes_t* out)
+{
+    if (p == nullptr || out == nullptr)
+        return fail(DPPIX_EINVAL, "NULL plan or output");
+    out->workspace_bytes = p->ws.total;
+    out->bg_capacity = p->bg_cap;
+    out->fg_capacity = p->fg_cap;
+    out->flag_bytes = (size_t)p->total_cells;
+    out->clip_bytes_bg = p->bg_cap;
+    out->clip_bytes_fg = p->fg_cap;
+    out->grad_scratch_bytes = align256(4 * p->bg_cap) + align256(4 * p->fg_cap) + align256(4 * (size_t)p->total_cells);
+    out->n_tiles = p->n_tiles;
+    out->total_pixels = p->total_pixels;
+    return DPPIX_OK;
+}
+
+dppix_status_t dp_pix_plan_frame_info(dppix_plan_t p, int32_t f, dppix_frame_info_t* out)
+{
+    if (p == nullptr || out == nullptr)
+        return fail(DPPIX_EINVAL, "NULL plan or output");
+    if (f < 0 || f >= (int32_t)p->frames.size())
+        return fail(DPPIX_EINVAL, "frame index out of range");
+    const FrameRec& F = p->frames[f];
+    out->grid_rows = F.GR;
+    out->grid_cols = F.GC;
+    out->n = F.n;
+    out->pad_rows = F.GR * F.b - F.H;
+    out->pad_cols = F.GC * F.b - F.W;
+    out->tile_cells = F.K;
+    out->tiles_per_band = F.TX;
+    out->fg_min_count = F.tau;
+    out->cell_offset = F.cell_base;
+    out->fine_offset = F.fine_base;
+    out->sigma_bg = F.sigma_bg;
+    out->sigma_fg = F.sigma_fg;
+    return DPPIX_OK;
+}
+
+dppix_status_t dp_pix_plan_set_launch(dppix_plan_t p, int32_t threads, int32_t persistent)
+{
+    if (p == nullptr)
+        return fail(DPPIX_EINVAL, "NULL plan");
+    if (threads == 0)
+        threads = kDefaultThreads;
+    if (threads < 64 || threads > kMaxThreads || threads % 64 != 0)
+        return fail(DPPIX_EINVAL, "threads must be a multiple of 64 in 64..512");
+    if (persistent != 0 && persistent != 1)
+        return fail(DPPIX_EINVAL, "persistent must be 0 or 1");
+    p->threads = threads;
+    p->persistent = persistent;
+    return DPPIX_OK;
+}
+
+dppix_status_t dp_pix_plan_bind(dppix_plan_t p, void* ws, size_t bytes, dppix_stream_t stream)
+{
+    if (p == nullptr || ws == nullptr)
+        return fail(DPPIX_EINVAL, "NULL plan or workspace");
+    if (bytes < p->ws.total)
+        return fail(DPPIX_ENOMEM, "workspace smaller than workspace_bytes");
+    if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0)
+        return fail(DPPIX_EINVAL, "workspace must be 256-byte aligned");
+    hipError_t e = hipMemcpyAsync(ws, p->host_tables.data(), p->host_tables.size(), hipMemcpyHostToDevice,
+                                  reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return dev_fail(e, "uploading plan tables");
+    // tickets start at zero; the scan kernel clears them again on every plan
+    e = hipMemsetAsync(static_cast<uint8_t*>(ws) + p->ws.counters, 0, sizeof(uint32_t) * 8,
+                       reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return dev_fail(e, "clearing tickets");
+    p->bound = static_cast<uint8_t*>(ws);
+    p->bound_bytes = bytes;
+    return DPPIX_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+TileArgs base_args(dppix_plan_t p)
+{
+    TileArgs a;
+    std::memset(&a, 0, sizeof a);
+    uint8_t* w = p->bound;
+    a.frames = reinterpret_cast<const FrameRec*>(w + p->ws.frames);
+    a.sched_frame = reinterpret_cast<const int32_t*>(w + p->ws.sched_frame);
+    a.sched_base = reinterpret_cast<const int64_t*>(w + p->ws.sched_base);
+    a.n_frames = (int32_t)p->frames.size();
+    a.n_tiles = p->n_tiles;
+    a.ticket = reinterpret_cast<uint32_t*>(w + p->ws.counters);
+    a.persistent = p->persistent;
+    a.flags = w + p->ws.flags;
+    a.tile_cnt = reinterpret_cast<uint32_t*>(w + p->ws.tile_cnt);
+    a.tile_fg = reinterpret_cast<uint32_t*>(w + p->ws.tile_fg);
+    a.frame_base = reinterpret_cast<const uint64_t*>(w + p->ws.frame_base);
+    a.frame_tot = reinterpret_cast<uint64_t*>(w + p->ws.frame_tot);
+    return a;
+}
+
+dppix_status_t need_bound(dppix_plan_t p)
+{
+    if (p == nullptr)
+        return fail(DPPIX_EINVAL, "NULL plan");
+    if (p->bound == nullptr)
+        return fail(DPPIX_EINVAL, "plan has no workspace (call dp_pix_plan_bind)");
+    return DPPIX_OK;
+}
+
+dppix_status_t check_store(const dppix_store_t* s, bool need_stats)
+{
+    if (s == nullptr)
+        return fail(DPPIX_EINVAL, "NULL store");
+    if (need_stats && (s->bg == nullptr || s->fg == nullptr))
+        return fail(DPPIX_EINVAL, "store bg/fg are NULL");
+    return DPPIX_OK;
+}
+
+int grid_for(dppix_plan_t p, size_t lds)
+{
+    if (!p->persistent)
+        return (int)p->n_tiles;
+    int dev = 0, cus = 256, per_cu = 1;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            cus = prop.multiProcessorCount;
+    }
+    if (occupancy_forward(p->threads, lds, &per_cu) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    const int64_t g = std::min<int64_t>((int64_t)cus * per_cu, p->n_tiles);
+    return (int)std::max<int64_t>(1, g);
+}
+
+}  // namespace
+
+extern "C" {
+
+dppix_status_t dp_pix_plan(dppix_plan_t p, const uint8_t* const* masks, const dppix_store_t* store,
+                           dppix_stream_t stream)
+{
+    dppix_status_t st = need_bound(p);
+    if (st != DPPIX_OK)
+        return st;
+    TileArgs a = base_args(p);
+    a.masks = masks;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = launch_classify(a, p->threads, p->lds[kClassify], s);
+    if (e != hipSuccess)
+        return dev_fail(e, "classify launch");
+    e = launch_scan(a, store ? store->counts : nullptr, s);
+    if (e != hipSuccess)
+        return dev_fail(e, "scan launch");
+    return DPPIX_OK;
+}
+
+dppix_status_t dp_pix_forward(dppix_plan_t p, const void* const* images, const dppix_store_t* store,
+                              uint8_t* clip_bg, uint8_t* clip_fg, void* const* fused_out, dppix_stream_t stream)
+{
+    dppix_status_t st = need_bound(p);
+    if (st != DPPIX_OK)
+        return st;
+    if (images == nullptr)
+        return fail(DPPIX_EINVAL, "images is NULL");
+    if ((st = check_store(store, true)) != DPPIX_OK)
+        return st;
+    if ((clip_bg == nullptr) != (clip_fg == nullptr))
+        return fail(DPPIX_EINVAL, "clip_bg and clip_fg must both be given or both be NULL");
+    TileArgs a = base_args(p);
+    a.images = images;
+    a.outs = fused_out;
+    a.bg = store->bg;
+    a.fg = store->fg;
+    a.store_flags = store->flags;
+    a.clip_bg = clip_bg;
+    a.clip_fg = clip_fg;
+    const size_t lds = std::max(p->lds[kFwdU8], p->lds[kFwdF32]);
+    hipError_t e = launch_forward(a, p->threads, lds, grid_for(p, lds), reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return dev_fail(e, "forward launch");
+    return DPPIX_OK;
+}
+
+dppix_status_t dp_pix_reconstruct(dppix_plan_t p, const dppix_store_t* store, void* const* out, dppix_stream_t stream)
+{
+    dppix_status_t st = need_bound(p);
+    if (st != DPPIX_OK)
+        return st;
+    if (out == nullptr)
+        return fail(DPPIX_EINVAL, "out is NULL");
+    if ((st = check_store(store, true)) != DPPIX_OK)
+        return st;
+    TileArgs a = base_args(p);
+    a.outs = out;
+    a.bg = store->bg;
+    a.fg = store->fg;
+    const size_t lds = std::max(p->lds[kRecU8], p->lds[kRecF32]);
+    hipError_t e = launch_reconstruct(a, p->threads, lds, grid_for(p, lds), reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return dev_fail(e, "reconstruct launch");
+    return DPPIX_OK;
+}
+
+dppix_status_t dp_pix_backward(dppix_plan_t p, const dppix_store_t* store, const float* const* grad_out,
+                               const uint8_t* clip_bg, const uint8_t* clip_fg, float* const* grad_in, void* scratch,
+                               size_t scratch_bytes, dppix_stream_t stream)
+{
+    dppix_status_t st = need_bound(p);
+    if (st != DPPIX_OK)
+        return st;
+    if (p->any_u8)
+        return fail(DPPIX_EINVAL, "backward needs every frame in F32_CHW layout");
+    if (grad_out == nullptr || grad_in == nullptr || clip_bg == nullptr || clip_fg == nullptr)
+        return fail(DPPIX_EINVAL, "grad_out, grad_in and clip bits are required");
+    if ((st = check_store(store, false)) != DPPIX_OK)
+        return st;
+    const size_t need = align256(4 * p->bg_cap) + align256(4 * p->fg_cap) + align256(4 * (size_t)p->total_cells);
+    if (scratch == nullptr || scratch_bytes < need)
+        return fail(DPPIX_ENOMEM, "scratch smaller than grad_scratch_bytes");
+    uint8_t* sc = static_cast<uint8_t*>(scratch);
+    TileArgs a = base_args(p);
+    a.grad_out = grad_out;
+    a.grad_in = grad_in;
+    a.clip_bg = const_cast<uint8_t*>(clip_bg);
+    a.clip_fg = const_cast<uint8_t*>(clip_fg);
+    a.g_bg = reinterpret_cast<float*>(sc);
+    a.g_fg = reinterpret_cast<float*>(sc + align256(4 * p->bg_cap));
+    a.cell_index = reinterpret_cast<uint32_t*>(sc + align256(4 * p->bg_cap) + align256(4 * p->fg_cap));
+    hipError_t e = launch_backward(a, p->threads, p->lds[kBwd], grid_for(p, p->lds[kBwd]), p->total_pixels,
+                                   reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return dev_fail(e, "backward launch");
+    return DPPIX_OK;
+}
+
+dppix_status_t dp_pix_debug_sums(dppix_plan_t p, const void* const* images, const dppix_store_t* store,
+                                 uint32_t* coarse, uint32_t* fine, dppix_stream_t stream)
+{
+    dppix_status_t st = need_bound(p);
+    if (st != DPPIX_OK)
+        return st;
+    if (p->any_f32)
+        return fail(DPPIX_EINVAL, "debug sums are for U8_HWC frames");
+    if (images == nullptr || coarse == nullptr || fine == nullptr)
+        return fail(DPPIX_EINVAL, "images, coarse and fine are required");
+    if ((st = check_store(store, true)) != DPPIX_OK)
+        return st;
+    TileArgs a = base_args(p);
+    a.images = images;
+    a.bg = store->bg;
+    a.fg = store->fg;
+    a.store_flags = store->flags;
+    a.dbg_coarse = coarse;
+    a.dbg_fine = fine;
+    const size_t lds = p->lds[kFwdU8];
+    hipError_t e = launch_forward(a, p->threads, lds, grid_for(p, lds), reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return dev_fail(e, "forward launch");
+    return DPPIX_OK;
+}
+
+dppix_status_t dp_pix_debug_philox(const uint32_t* in, uint32_t* words, int64_t n, dppix_stream_t stream)
+{
+    if (n < 0 || (n > 0 && (in == nullptr || words == nullptr)))
+        return fail(DPPIX_EINVAL, "bad philox arguments");
+    hipError_t e = launch_philox(in, words, n, reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return dev_fail(e, "philox launch");
+    return DPPIX_OK;
+}
+
+dppix_status_t dp_pix_graph_create(dppix_plan_t p, const uint8_t* const* masks, const void* const* images,
+                                   const dppix_store_t* store, void* const* fused_out, dppix_stream_t stream,
+                                   dppix_graph_t* out)
+{
+    if (out == nullptr)
+        return fail(DPPIX_EINVAL, "out is NULL");
+    *out = nullptr;
+    dppix_status_t st = need_bound(p);
+    if (st != DPPIX_OK)
+        return st;
+    if (images == nullptr || (st = check_store(store, true)) != DPPIX_OK)
+        return st == DPPIX_OK ? fail(DPPIX_EINVAL, "images is NULL") : st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess)
+        return dev_fail(e, "begin capture");
+    dppix_status_t s1 = dp_pix_plan(p, masks, store, stream);
+    dppix_status_t s2 = s1 == DPPIX_OK ? dp_pix_forward(p, images, store, nullptr, nullptr, fused_out, stream) : s1;
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(s, &g);
+    if (s2 != DPPIX_OK) {
+        if (g)
+            (void)hipGraphDestroy(g);
+        return s2;
+    }
+    if (e != hipSuccess)
+        return dev_fail(e, "end capture");
+    dppix_graph* G = new (std::nothrow) dppix_graph;
+    if (G == nullptr) {
+        (void)hipGraphDestroy(g);
+        return fail(DPPIX_ENOMEM, "host allocation failed");
+    }
+    G->graph = g;
+    e = hipGraphInstantiate(&G->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        delete G;
+        return dev_fail(e, "graph instantiate");
+    }
+    *out = G;
+    return DPPIX_OK;
+}
+
+dppix_status_t dp_pix_graph_launch(dppix_graph_t g, dppix_stream_t stream)
+{
+    if (g == nullptr)
+        return fail(DPPIX_EINVAL, "NULL graph");
+    hipError_t e = hipGraphLaunch(g->exec, reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return dev_fail(e, "graph launch");
+    return DPPIX_OK;
+}
+
+void dp_pix_graph_destroy(dppix_graph_t g)
+{
+    if (g == nullptr)
+        return;
+    if (g->exec)
+        (void)hipGraphExecDestroy(g->exec);
+    if (g->graph)
+        (void)hipGraphDestroy(g->graph);
+    delete g;
+}
+
+}  // extern "C"

@@ -1,0 +1,94 @@
+// dppix_internal.h — device-side records and launch interfaces of libdppix.
+//
+// Layout of the work: every frame is cut into bands of b_bg padded rows (one
+// row of grid cells) and each band into tiles of K grid cells.  A tile is the
+// unit a workgroup processes (Thm. 3 of the paper: cells are independent, so
+// any distribution of cells over processing units is valid).  Tiles are
+// numbered frame-major, band-major, left to right — which is also row-major
+// cell order, the order of the compact store (Table IV).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dppix {
+
+constexpr int kStrip = 16;             // bytes one lane moves per row (dwordx4)
+constexpr int kMaxThreads = 512;
+constexpr int kMaxB = 256;             // 255 * 256 rows fits a 16-bit lane sum
+constexpr int64_t kVgcBudget = 65536;  // LDS bytes for rounded subcell values
+
+// One frame as the kernels see it (host computes everything derivable).
+struct FrameRec {
+    int32_t H, W, C, layout;
+    int64_t pitch;            // U8: bytes per row; F32: floats per row
+    int32_t b, s, n, pad;     // b_bg, b_fg, n = b/s, pad mode
+    int32_t GR, GC, K, TX;    // grid rows/cols, cells per tile, tiles per band
+    int32_t tau, noise_bg, noise_fg, aligned;  // aligned: image rows 16-B aligned
+    int64_t cell_base;        // first cell of the frame in batch-wide cell arrays
+    int64_t fine_base;        // first subcell in dense fine arrays
+    int64_t tile_base;        // first tile
+    double sigma_bg, sigma_fg;
+    uint32_t key0, key1, fi0, fi1;
+};
+
+// Workspace layout (byte offsets from the bound workspace base).
+struct WsLayout {
+    size_t frames;        // FrameRec[n_frames]
+    size_t sched_frame;   // int32[n_frames]: frames in scheduling order
+    size_t sched_base;    // int64[n_frames+1]: first tile index in scheduling order
+    size_t flags;         // uint8[total_cells] (classification)
+    size_t tile_cnt;      // uint32[n_tiles]: complex cells per tile
+    size_t tile_fg;       // uint32[n_tiles]: complex cells of the frame before the tile
+    size_t frame_tot;     // uint64[n_frames][2]: n_bg, n_fg cells
+    size_t frame_base;    // uint64[n_frames][2]: float offsets of the frame in bg, fg
+    size_t counters;      // uint32[8]: tickets of persistent launches
+    size_t total;
+};
+
+struct TileArgs {
+    const FrameRec* frames;
+    const int32_t* sched_frame;
+    const int64_t* sched_base;
+    int32_t n_frames;
+    int64_t n_tiles;
+    uint32_t* ticket;         // [0]: next tile, [1]: finished workgroups
+    int32_t persistent;
+    // per-frame pointer tables (device arrays of device pointers)
+    const uint8_t* const* masks;
+    const void* const* images;
+    void* const* outs;
+    // plan products
+    uint8_t* flags;
+    uint32_t* tile_cnt;
+    uint32_t* tile_fg;
+    const uint64_t* frame_base;
+    uint64_t* frame_tot;
+    // store
+    float* bg;
+    float* fg;
+    uint8_t* store_flags;
+    uint8_t* clip_bg;
+    uint8_t* clip_fg;
+    // diagnostics
+    uint32_t* dbg_coarse;
+    uint32_t* dbg_fine;
+    // backward
+    const float* const* grad_out;
+    float* const* grad_in;
+    float* g_bg;              // per-statistic gradient, store layout
+    float* g_fg;
+    uint32_t* cell_index;     // frame-local store index of every cell
+};
+
+// Host-side launchers (defined in dppix_kernels.hip).
+hipError_t launch_classify(const TileArgs& a, int threads, size_t lds, hipStream_t s);
+hipError_t launch_scan(const TileArgs& a, uint64_t* counts_out, hipStream_t s);
+hipError_t launch_forward(const TileArgs& a, int threads, size_t lds, int grid, hipStream_t s);
+hipError_t launch_reconstruct(const TileArgs& a, int threads, size_t lds, int grid, hipStream_t s);
+hipError_t launch_backward(const TileArgs& a, int threads, size_t lds, int grid, int64_t total_pixels,
+                           hipStream_t s);
+hipError_t launch_philox(const uint32_t* in, uint32_t* out, int64_t n, hipStream_t s);
+hipError_t occupancy_forward(int threads, size_t lds, int* blocks_per_cu);
+
+}  // namespace dppix

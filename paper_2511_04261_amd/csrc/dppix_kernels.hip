@@ -1,0 +1,1142 @@
+// dppix_kernels.hip — gfx950 kernels of libdppix.
+//
+// The path is bandwidth-bound: per pixel it reads the image (and, in the plan,
+// the mask) once and writes the reconstruction once; the statistics are a few
+// percent of that.  Nothing is a dense contraction, so there is no MFMA work.
+// Every tile kernel follows one pattern:
+//   1. each lane owns a 16-byte strip of the tile's padded rows and sums it
+//      down the rows of one subgrid row in registers (two 16-bit lanes per
+//      32-bit register for bytes: 255 * 256 rows still fits);
+//   2. the column sums go to LDS, where one lane per (subcell, channel) adds
+//      its s_b columns — exact integer sums of every s_b x s_b subcell;
+//   3. a coarse cell's sum is the exact total of its n x n subcell sums
+//      (Eq. 16-17: b = n * s_b), so simple and complex cells cost the same;
+//   4. one lane per released statistic draws Philox4x32-10 words, turns them
+//      into Laplace noise in fp64, clips and rounds once to fp32;
+//   5. with a fused output, the rounded values are expanded into one padded
+//      row in LDS and each lane stores its strip on the s_b output rows.
+// Mirror padding (Algorithm 2 step 4, Algorithm 3 step 3) is never
+// materialised: padded rows fold to a source row per row, and padded columns
+// fold per byte in the few strips that cross the right edge.
+#include "dppix_internal.h"
+#include "dppix_tiles.h"
+
+#include <math.h>
+
+namespace dppix {
+namespace {
+
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// --------------------------------------------------------------------------
+// Counter-based noise.  Philox4x32 with ten rounds (Salmon et al., SC'11):
+// per round the first and third words are multiplied by two fixed odd
+// constants, the high halves of the products are xored with the other two
+// words and the round key, and the key advances by two Weyl increments.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint32_t ma = 0xD2511F53u, mb = 0xCD9E8D57u;
+        const uint32_t a_lo = ma * c.x, a_hi = __umulhi(ma, c.x);
+        const uint32_t b_lo = mb * c.z, b_hi = __umulhi(mb, c.z);
+        c = make_uint4(b_hi ^ c.y ^ k0, b_lo, a_hi ^ c.w ^ k1, a_lo);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// Laplace(0, sigma) sample of one statistic: words 0,1 of the block give a
+// uniform u = (2k+1) 2^-53 with k the top 52 bits, inverted through the
+// Laplace CDF (Eq. 9) in fp64.
+__device__ __forceinline__ double laplace_sample(const FrameRec& F, uint32_t id, int ch, int level, double sigma)
+{
+    const uint4 w = philox10(make_uint4(id, (uint32_t)ch | ((uint32_t)level << 8), F.fi0, F.fi1), F.key0, F.key1);
+    const uint64_t bits = ((uint64_t)w.y << 32) | (uint64_t)w.x;
+    const double u = (double)(((bits >> 12) << 1) | 1ull) * 0x1p-53;
+    if (u < 0.5)
+        return sigma * log(2.0 * u);
+    return -sigma * log(2.0 * (1.0 - u));
+}
+
+// Release one statistic: mean = sum / area, plus noise (Eq. 11 scale given by
+// the host), clipped to [0, 255] (Algorithm 3 steps 10, 17), one rounding to
+// fp32.  pass = the clip did not bind (gradient flows).
+__device__ __forceinline__ float release(double sum, double area, int noisy, double sigma, const FrameRec& F,
+                                         uint32_t id, int ch, int level, uint8_t& pass)
+{
+    const double mu = sum / area;
+    const double z = noisy ? mu + laplace_sample(F, id, ch, level, sigma) : mu;
+    pass = (uint8_t)(z >= 0.0 && z <= 255.0);
+    const double v = z < 0.0 ? 0.0 : (z > 255.0 ? 255.0 : z);
+    return (float)v;
+}
+
+__device__ __forceinline__ uint8_t to_u8(float v) { return (uint8_t)rintf(v); }
+
+// Mirror index of padded coordinate x >= 0 into [0, L).
+__device__ __forceinline__ int fold(int x, int L, int mode)
+{
+    if (x < L)
+        return x;
+    if (mode == 0) {
+        const int p = 2 * L;
+        const int y = x % p;
+        return y < L ? y : p - 1 - y;
+    }
+    if (L == 1)
+        return 0;
+    const int p = 2 * L - 2;
+    const int y = x % p;
+    return y < L ? y : p - y;
+}
+
+__device__ __forceinline__ uint32_t uniform_u32(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Scheduling index -> (frame, tile within frame).  sched_base holds the first
+// scheduling index of each frame in scheduling order.
+__device__ __forceinline__ void locate(const TileArgs& a, int64_t idx, int& f, int64_t& local)
+{
+    int lo = 0, hi = a.n_frames - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.sched_base[mid] <= idx)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    f = a.sched_frame[lo];
+    local = idx - a.sched_base[lo];
+}
+
+// Add the bytes of one 16-byte strip into 16-bit lane pairs: e[d] holds bytes
+// 4d and 4d+2, o[d] bytes 4d+1 and 4d+3.
+__device__ __forceinline__ void acc_bytes(const v4u& w, uint32_t (&e)[4], uint32_t (&o)[4])
+{
+    e[0] += w.x & 0x00FF00FFu; o[0] += (w.x >> 8) & 0x00FF00FFu;
+    e[1] += w.y & 0x00FF00FFu; o[1] += (w.y >> 8) & 0x00FF00FFu;
+    e[2] += w.z & 0x00FF00FFu; o[2] += (w.z >> 8) & 0x00FF00FFu;
+    e[3] += w.w & 0x00FF00FFu; o[3] += (w.w >> 8) & 0x00FF00FFu;
+}
+
+// Nonzero bytes of a dword as 0/1 bytes.
+__device__ __forceinline__ uint32_t nz_bytes(uint32_t w)
+{
+    return ((((w & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | w) >> 7) & 0x01010101u;
+}
+
+__device__ __forceinline__ void store_colsums(uint32_t* dst, const uint32_t (&e)[4], const uint32_t (&o)[4])
+{
+    v4u* d4 = reinterpret_cast<v4u*>(dst);
+#pragma unroll
+    for (int d = 0; d < 4; ++d)
+        d4[d] = v4u{e[d] & 0xFFFFu, o[d] & 0xFFFFu, e[d] >> 16, o[d] >> 16};
+}
+
+// Gather one 16-byte strip of a padded row byte by byte: columns past the
+// image fold back (mirror), bytes past the tile end read as zero.
+template <int C>
+__device__ __forceinline__ v4u gather_strip_u8(const uint8_t* row, int64_t p0, int64_t tile_end, int W, int pad)
+{
+    uint32_t w[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        uint32_t v = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t p = p0 + 4 * d + e;
+            uint32_t byte = 0;
+            if (p < tile_end) {
+                const int x = (int)(p / C);
+                const int ch = (int)(p - (int64_t)x * C);
+                byte = row[(int64_t)fold(x, W, pad) * C + ch];
+            }
+            v |= byte << (8 * e);
+        }
+        w[d] = v;
+    }
+    return v4u{w[0], w[1], w[2], w[3]};
+}
+
+// Cell classes and class-local indices of the tile's cells (wave 0):
+// complex cells count from the number of complex cells of the frame before
+// the tile, simple cells from the simple ones — row-major order, which is the
+// order of the compact store.
+__device__ __forceinline__ void tile_cells(const TileArgs& a, const FrameRec& F, int64_t t, int r, int x0c, int Kt,
+                                           uint32_t* cidx, uint8_t* cflag, bool write_store_flags)
+{
+    if (threadIdx.x >= 64)
+        return;
+    const int lane = threadIdx.x;
+    uint32_t run_fg = a.tile_fg[t];
+    const uint32_t before = (uint32_t)(r * F.GC + x0c);
+    uint32_t run_bg = before - run_fg;
+    for (int base = 0; base < Kt; base += 64) {
+        const int kc = base + lane;
+        const bool in = kc < Kt;
+        const uint8_t fl = in ? a.flags[F.cell_base + before + kc] : (uint8_t)0;
+        const uint64_t m = __ballot(fl != 0);
+        const uint64_t below = lane ? (m & (~0ull >> (64 - lane))) : 0ull;
+        const uint32_t pc = (uint32_t)__popcll(below);
+        if (in) {
+            cflag[kc] = fl;
+            cidx[kc] = fl ? run_fg + pc : run_bg + (uint32_t)lane - pc;
+            if (write_store_flags && a.store_flags)
+                a.store_flags[F.cell_base + before + kc] = fl;
+            if (a.cell_index)
+                a.cell_index[F.cell_base + before + kc] = cidx[kc];
+        }
+        const uint32_t nf = (uint32_t)__popcll(m);
+        const uint32_t nv = (uint32_t)min(64, Kt - base);
+        run_fg += nf;
+        run_bg += nv - nf;
+    }
+}
+
+struct TileCoord {
+    int f;
+    int64_t t;
+    int r, ct;
+};
+
+__device__ __forceinline__ TileCoord tile_of(const TileArgs& a, int64_t sched_idx, FrameRec& F)
+{
+    TileCoord tc;
+    int64_t local;
+    locate(a, sched_idx, tc.f, local);
+    tc.f = (int)uniform_u32((uint32_t)tc.f);
+    F = a.frames[tc.f];
+    tc.t = F.tile_base + local;
+    tc.r = (int)(local / F.TX);
+    tc.ct = (int)(local - (int64_t)tc.r * F.TX);
+    return tc;
+}
+
+// ==========================================================================
+// Plan: classify cells from the mirror-padded mask (Algorithm 3 steps 3-6).
+// ==========================================================================
+__device__ void classify_tile(const TileArgs& a, const FrameRec& F, const TileCoord& tc, uint8_t* lds)
+{
+    const int tid = threadIdx.x, NT = blockDim.x;
+    const int b = F.b, H = F.H, W = F.W;
+    const int x0c = tc.ct * F.K;
+    const int Kt = min(F.K, F.GC - x0c);
+    const int64_t X0 = (int64_t)x0c * b;
+    const int WB = Kt * b;
+    const int nstr = (WB + 15) >> 4;
+    const int64_t tile_end = X0 + WB;
+    const uint8_t* mask = a.masks ? a.masks[tc.f] : nullptr;
+    __shared__ uint32_t s_count;
+    if (mask == nullptr) {
+        for (int kc = tid; kc < Kt; kc += NT)
+            a.flags[F.cell_base + (int64_t)tc.r * F.GC + x0c + kc] = 0;
+        if (tid == 0)
+            a.tile_cnt[tc.t] = 0;
+        return;
+    }
+    const LdsPlan L = lds_plan(kClassify, F.K, b, F.n, 1);
+    uint32_t* colcnt = reinterpret_cast<uint32_t*>(lds + L.colsum);
+    if (tid == 0)
+        s_count = 0;
+    const bool aligned = ((reinterpret_cast<uintptr_t>(mask) | (uintptr_t)W | (uintptr_t)X0) & 15) == 0;
+    for (int st = tid; st < nstr; st += NT) {
+        const int64_t p0 = X0 + 16 * st;
+        uint32_t e[4] = {0, 0, 0, 0}, o[4] = {0, 0, 0, 0};
+        const bool fast = aligned && p0 + 16 <= min(tile_end, (int64_t)W);
+        for (int k = 0; k < b; ++k) {
+            const int src = fold(tc.r * b + k, H, F.pad);
+            const uint8_t* row = mask + (int64_t)src * W;
+            v4u w;
+            if (fast)
+                w = __builtin_nontemporal_load(reinterpret_cast<const v4u*>(row + p0));
+            else
+                w = gather_strip_u8<1>(row, p0, tile_end, W, F.pad);
+            w.x = nz_bytes(w.x); w.y = nz_bytes(w.y); w.z = nz_bytes(w.z); w.w = nz_bytes(w.w);
+            acc_bytes(w, e, o);
+        }
+        store_colsums(colcnt + 16 * st, e, o);
+    }
+    __syncthreads();
+    for (int kc = tid; kc < Kt; kc += NT) {
+        uint32_t cnt = 0;
+        for (int x = 0; x < b; ++x)
+            cnt += colcnt[kc * b + x];
+        const uint8_t fl = (uint8_t)(cnt >= (uint32_t)F.tau);
+        a.flags[F.cell_base + (int64_t)tc.r * F.GC + x0c + kc] = fl;
+        if (fl)
+            atomicAdd(&s_count, 1u);
+    }
+    __syncthreads();
+    if (tid == 0)
+        a.tile_cnt[tc.t] = s_count;
+}
+
+__global__ __launch_bounds__(kMaxThreads) void k_classify(TileArgs a)
+{
+    extern __shared__ __align__(16) uint8_t lds[];
+    FrameRec F;
+    const TileCoord tc = tile_of(a, blockIdx.x, F);
+    classify_tile(a, F, tc, lds);
+}
+
+// ==========================================================================
+// Plan: scan complex-cell counts into store offsets.
+// ==========================================================================
+template <typename T>
+__device__ __forceinline__ T block_exclusive_scan(T v, T* wave_tot, T& total)
+{
+    // inclusive scan inside the wavefront
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    T x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const T y = __shfl_up(x, d, 64);
+        if (lane >= d)
+            x += y;
+    }
+    if (lane == 63)
+        wave_tot[wid] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T run = 0;
+        for (int i = 0; i < nw; ++i) {
+            const T w = wave_tot[i];
+            wave_tot[i] = run;
+            run += w;
+        }
+        wave_tot[nw] = run;
+    }
+    __syncthreads();
+    const T excl = x - v + wave_tot[wid];
+    total = wave_tot[nw];
+    __syncthreads();
+    return excl;
+}
+
+// One workgroup per frame: exclusive scan of per-tile complex counts.
+__global__ __launch_bounds__(256) void k_scan_tiles(TileArgs a, uint64_t* frame_tot)
+{
+    __shared__ uint32_t wave_tot[9];
+    const int f = blockIdx.x;
+    const FrameRec F = a.frames[f];
+    const int64_t nt = (int64_t)F.GR * F.TX;
+    uint32_t carry = 0;
+    for (int64_t base = 0; base < nt; base += blockDim.x) {
+        const int64_t i = base + threadIdx.x;
+        const uint32_t v = i < nt ? a.tile_cnt[F.tile_base + i] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_exclusive_scan<uint32_t>(v, wave_tot, tot);
+        if (i < nt)
+            a.tile_fg[F.tile_base + i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) {
+        const uint64_t cells = (uint64_t)F.GR * F.GC;
+        frame_tot[2 * f + 0] = cells - carry;
+        frame_tot[2 * f + 1] = carry;
+    }
+}
+
+// One workgroup: frame offsets in the store, per-frame counts, ticket reset.
+__global__ __launch_bounds__(256) void k_scan_frames(TileArgs a, const uint64_t* frame_tot, uint64_t* frame_base,
+                                                     uint64_t* counts)
+{
+    __shared__ uint64_t wave_tot[9];
+    uint64_t carry_bg = 0, carry_fg = 0;
+    for (int base = 0; base < a.n_frames; base += blockDim.x) {
+        const int f = base + threadIdx.x;
+        uint64_t vb = 0, vf = 0, nb = 0, nf = 0;
+        if (f < a.n_frames) {
+            const FrameRec F = a.frames[f];
+            nb = frame_tot[2 * f];
+            nf = frame_tot[2 * f + 1];
+            vb = nb * (uint64_t)F.C;
+            vf = nf * (uint64_t)F.n * (uint64_t)F.n * (uint64_t)F.C;
+        }
+        uint64_t tb, tf;
+        const uint64_t eb = block_exclusive_scan<uint64_t>(vb, wave_tot, tb);
+        const uint64_t ef = block_exclusive_scan<uint64_t>(vf, wave_tot, tf);
+        if (f < a.n_frames) {
+            frame_base[2 * f + 0] = carry_bg + eb;
+            frame_base[2 * f + 1] = carry_fg + ef;
+            if (counts) {
+                counts[4 * f + 0] = nb;
+                counts[4 * f + 1] = nf;
+                counts[4 * f + 2] = carry_bg + eb;
+                counts[4 * f + 3] = carry_fg + ef;
+            }
+        }
+        carry_bg += tb;
+        carry_fg += tf;
+    }
+    if (threadIdx.x < 8)
+        a.ticket[threadIdx.x] = 0;
+}
+
+// ==========================================================================
+// Forward, uint8 HWC (Algorithm 3 steps 7-19, fused steps 11, 18-21).
+// ==========================================================================
+template <int C>
+__device__ void forward_tile_u8(const TileArgs& a, const FrameRec& F, const TileCoord& tc, uint8_t* lds)
+{
+    const int tid = threadIdx.x, NT = blockDim.x;
+    const int b = F.b, s = F.s, n = F.n, H = F.H, W = F.W, pad = F.pad;
+    const int r = tc.r;
+    const int x0c = tc.ct * F.K;
+    const int Kt = min(F.K, F.GC - x0c);
+    const int WB = Kt * b * C;
+    const int nstr = (WB + 15) >> 4;
+    const int64_t X0 = (int64_t)x0c * b * C;
+    const int64_t tile_end = X0 + WB;
+    const int64_t real_end = (int64_t)W * C;
+    const int64_t lim = min(tile_end, real_end);
+    const int64_t pitch = F.pitch;
+    const uint8_t* img = static_cast<const uint8_t*>(a.images[tc.f]);
+    uint8_t* out = a.outs ? static_cast<uint8_t*>(a.outs[tc.f]) : nullptr;
+    const bool in_aligned = ((reinterpret_cast<uintptr_t>(img) | (uintptr_t)pitch | (uintptr_t)X0) & 15) == 0;
+
+    const LdsPlan L = lds_plan(kFwdU8, F.K, b, n, C);
+    uint32_t* colsum = reinterpret_cast<uint32_t*>(lds + L.colsum);
+    uint8_t* ex = lds + L.colsum;
+    uint32_t* cspart = reinterpret_cast<uint32_t*>(lds + L.cspart);
+    uint32_t* cidx = reinterpret_cast<uint32_t*>(lds + L.cidx);
+    uint8_t* cflag = lds + L.cflag;
+    uint8_t* vgs = lds + L.vgs;
+    uint8_t* vgc = lds + L.vgc;
+
+    tile_cells(a, F, tc.t, r, x0c, Kt, cidx, cflag, true);
+    const uint64_t bg_base = a.frame_base[2 * tc.f + 0];
+    const uint64_t fg_base = a.frame_base[2 * tc.f + 1];
+    const int items = Kt * n * C;
+    const int nn = n * n;
+    __syncthreads();
+
+    // ---- subgrid rows: exact column sums, then subcell sums ----
+    for (int fr = 0; fr < n; ++fr) {
+        const int row0 = r * b + fr * s;
+        for (int st = tid; st < nstr; st += NT) {
+            const int64_t p0 = X0 + 16 * st;
+            uint32_t e[4] = {0, 0, 0, 0}, o[4] = {0, 0, 0, 0};
+            if (in_aligned && p0 + 16 <= lim) {
+                int k = 0;
+                for (; k + 4 <= s; k += 4) {
+                    const uint8_t* r0 = img + (int64_t)fold(row0 + k + 0, H, pad) * pitch + p0;
+                    const uint8_t* r1 = img + (int64_t)fold(row0 + k + 1, H, pad) * pitch + p0;
+                    const uint8_t* r2 = img + (int64_t)fold(row0 + k + 2, H, pad) * pitch + p0;
+                    const uint8_t* r3 = img + (int64_t)fold(row0 + k + 3, H, pad) * pitch + p0;
+                    const v4u w0 = __builtin_nontemporal_load(reinterpret_cast<const v4u*>(r0));
+                    const v4u w1 = __builtin_nontemporal_load(reinterpret_cast<const v4u*>(r1));
+                    const v4u w2 = __builtin_nontemporal_load(reinterpret_cast<const v4u*>(r2));
+                    const v4u w3 = __builtin_nontemporal_load(reinterpret_cast<const v4u*>(r3));
+                    acc_bytes(w0, e, o);
+                    acc_bytes(w1, e, o);
+                    acc_bytes(w2, e, o);
+                    acc_bytes(w3, e, o);
+                }
+                for (; k < s; ++k) {
+                    const uint8_t* rk = img + (int64_t)fold(row0 + k, H, pad) * pitch + p0;
+                    acc_bytes(__builtin_nontemporal_load(reinterpret_cast<const v4u*>(rk)), e, o);
+                }
+            } else {
+                for (int k = 0; k < s; ++k) {
+                    const uint8_t* rk = img + (int64_t)fold(row0 + k, H, pad) * pitch;
+                    acc_bytes(gather_strip_u8<C>(rk, p0, tile_end, W, pad), e, o);
+                }
+            }
+            store_colsums(colsum + 16 * st, e, o);
+        }
+        __syncthreads();
+        for (int j = tid; j < items; j += NT) {
+            const int fc = j / C, ch = j - fc * C;
+            const uint32_t* cp = colsum + fc * s * C + ch;
+            uint32_t S = 0;
+            for (int x = 0; x < s; ++x)
+                S += cp[x * C];
+            const int kc = fc / n, jj = fc - kc * n;
+            if (a.dbg_fine)
+                a.dbg_fine[(F.fine_base + (int64_t)(r * n + fr) * ((int64_t)F.GC * n) + (int64_t)x0c * n + fc) * C + ch] = S;
+            cspart[j] = (fr == 0 ? 0u : cspart[j]) + S;
+            if (cflag[kc]) {
+                const uint32_t id = (uint32_t)(r * n + fr) * (uint32_t)(F.GC * n) + (uint32_t)(x0c * n + fc);
+                uint8_t pass;
+                const float v = release((double)S, (double)(s * s), F.noise_fg, F.sigma_fg, F, id, ch, 1, pass);
+                const uint64_t at = fg_base + ((uint64_t)cidx[kc] * nn + fr * n + jj) * C + ch;
+                a.fg[at] = v;
+                if (a.clip_fg)
+                    a.clip_fg[at] = pass;
+                vgc[(fr * Kt * n + fc) * C + ch] = to_u8(v);
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- simple cells: coarse sum = total of the n*n subcell sums ----
+    for (int j = tid; j < Kt * C; j += NT) {
+        const int kc = j / C, ch = j - kc * C;
+        uint32_t S = 0;
+        for (int jj = 0; jj < n; ++jj)
+            S += cspart[(kc * n + jj) * C + ch];
+        if (a.dbg_coarse)
+            a.dbg_coarse[(F.cell_base + (int64_t)r * F.GC + x0c + kc) * C + ch] = S;
+        if (!cflag[kc]) {
+            const uint32_t id = (uint32_t)(r * F.GC + x0c + kc);
+            uint8_t pass;
+            const float v = release((double)S, (double)(b * b), F.noise_bg, F.sigma_bg, F, id, ch, 0, pass);
+            const uint64_t at = bg_base + (uint64_t)cidx[kc] * C + ch;
+            a.bg[at] = v;
+            if (a.clip_bg)
+                a.clip_bg[at] = pass;
+            vgs[kc * C + ch] = to_u8(v);
+        }
+    }
+    if (out == nullptr)
+        return;
+    __syncthreads();
+
+    // ---- fused reconstruction of the band's real pixels ----
+    const bool out_aligned = ((reinterpret_cast<uintptr_t>(out) | (uintptr_t)pitch | (uintptr_t)X0) & 15) == 0;
+    for (int fr = 0; fr < n; ++fr) {
+        for (int j = tid; j < items; j += NT) {
+            const int fc = j / C, ch = j - fc * C;
+            const int kc = fc / n;
+            const uint8_t v = cflag[kc] ? vgc[(fr * Kt * n + fc) * C + ch] : vgs[kc * C + ch];
+            uint8_t* e = ex + fc * s * C + ch;
+            for (int x = 0; x < s; ++x)
+                e[x * C] = v;
+        }
+        __syncthreads();
+        const int row0 = r * b + fr * s;
+        const int rows = min(s, H - row0);
+        for (int st = tid; st < nstr; st += NT) {
+            const int64_t p0 = X0 + 16 * st;
+            if (p0 >= lim)
+                continue;
+            const v4u v = *reinterpret_cast<const v4u*>(ex + 16 * st);
+            if (out_aligned && p0 + 16 <= lim) {
+                for (int k = 0; k < rows; ++k)
+                    __builtin_nontemporal_store(v, reinterpret_cast<v4u*>(out + (int64_t)(row0 + k) * pitch + p0));
+            } else {
+                const uint8_t* vb = ex + 16 * st;
+                for (int k = 0; k < rows; ++k) {
+                    uint8_t* op = out + (int64_t)(row0 + k) * pitch;
+                    for (int q = 0; q < 16 && p0 + q < lim; ++q)
+                        op[p0 + q] = vb[q];
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ==========================================================================
+// Forward, fp32 CHW.  Column sums in fp32 over at most s_b rows, subcell and
+// cell sums in fp64.
+// ==========================================================================
+__device__ void forward_tile_f32(const TileArgs& a, const FrameRec& F, const TileCoord& tc, uint8_t* lds)
+{
+    const int tid = threadIdx.x, NT = blockDim.x;
+    const int b = F.b, s = F.s, n = F.n, H = F.H, W = F.W, C = F.C, pad = F.pad;
+    const int r = tc.r;
+    const int x0c = tc.ct * F.K;
+    const int Kt = min(F.K, F.GC - x0c);
+    const int WB = Kt * b;                 // floats
+    const int nstr = (WB + 3) >> 2;
+    const int64_t X0 = (int64_t)x0c * b;
+    const int64_t tile_end = X0 + WB;
+    const int64_t lim = min(tile_end, (int64_t)W);
+    const int64_t pitch = F.pitch;
+    const int64_t plane = pitch * H;
+    const float* img = static_cast<const float*>(a.images[tc.f]);
+    float* out = a.outs ? static_cast<float*>(a.outs[tc.f]) : nullptr;
+    const bool in_aligned = ((reinterpret_cast<uintptr_t>(img) | (uintptr_t)(pitch * 4) | (uintptr_t)(X0 * 4)) & 15) == 0;
+
+    const LdsPlan L = lds_plan(kFwdF32, F.K, b, n, C);
+    float* colsum = reinterpret_cast<float*>(lds + L.colsum);
+    double* cspart = reinterpret_cast<double*>(lds + L.cspart);
+    uint32_t* cidx = reinterpret_cast<uint32_t*>(lds + L.cidx);
+    uint8_t* cflag = lds + L.cflag;
+    float* vgs = reinterpret_cast<float*>(lds + L.vgs);
+    float* vgc = reinterpret_cast<float*>(lds + L.vgc);
+
+    tile_cells(a, F, tc.t, r, x0c, Kt, cidx, cflag, true);
+    const uint64_t bg_base = a.frame_base[2 * tc.f + 0];
+    const uint64_t fg_base = a.frame_base[2 * tc.f + 1];
+    const int nn = n * n;
+    const int kn = Kt * n;
+    __syncthreads();
+
+    for (int ch = 0; ch < C; ++ch) {
+        const float* pl = img + plane * ch;
+        for (int fr = 0; fr < n; ++fr) {
+            const int row0 = r * b + fr * s;
+            for (int st = tid; st < nstr; st += NT) {
+                const int64_t p0 = X0 + 4 * st;
+                v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
+                if (in_aligned && p0 + 4 <= lim) {
+                    for (int k = 0; k < s; ++k) {
+                        acc += __builtin_nontemporal_load(
+                            reinterpret_cast<const v4f*>(pl + (int64_t)fold(row0 + k, H, pad) * pitch + p0));
+                    }
+                } else {
+                    for (int k = 0; k < s; ++k) {
+                        const float* rk = pl + (int64_t)fold(row0 + k, H, pad) * pitch;
+                        float v[4];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            v[q] = (p0 + q < tile_end) ? rk[fold((int)(p0 + q), W, pad)] : 0.f;
+                        acc.x += v[0]; acc.y += v[1]; acc.z += v[2]; acc.w += v[3];
+                    }
+                }
+                reinterpret_cast<v4f*>(colsum)[st] = acc;
+            }
+            __syncthreads();
+            for (int fc = tid; fc < kn; fc += NT) {
+                double S = 0.0;
+                for (int x = 0; x < s; ++x)
+                    S += (double)colsum[fc * s + x];
+                const int kc = fc / n, jj = fc - kc * n;
+                const int ci = fc * C + ch;
+                cspart[ci] = (fr == 0 ? 0.0 : cspart[ci]) + S;
+                if (cflag[kc]) {
+                    const uint32_t id = (uint32_t)(r * n + fr) * (uint32_t)(F.GC * n) + (uint32_t)(x0c * n + fc);
+                    uint8_t pass;
+                    const float v = release(S, (double)(s * s), F.noise_fg, F.sigma_fg, F, id, ch, 1, pass);
+                    const uint64_t at = fg_base + ((uint64_t)cidx[kc] * nn + fr * n + jj) * C + ch;
+                    a.fg[at] = v;
+                    if (a.clip_fg)
+                        a.clip_fg[at] = pass;
+                    vgc[(fr * kn + fc) * C + ch] = v;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int j = tid; j < Kt * C; j += NT) {
+        const int kc = j / C, ch = j - kc * C;
+        if (cflag[kc])
+            continue;
+        double S = 0.0;
+        for (int jj = 0; jj < n; ++jj)
+            S += cspart[(kc * n + jj) * C + ch];
+        const uint32_t id = (uint32_t)(r * F.GC + x0c + kc);
+        uint8_t pass;
+        const float v = release(S, (double)(b * b), F.noise_bg, F.sigma_bg, F, id, ch, 0, pass);
+        const uint64_t at = bg_base + (uint64_t)cidx[kc] * C + ch;
+        a.bg[at] = v;
+        if (a.clip_bg)
+            a.clip_bg[at] = pass;
+        vgs[kc * C + ch] = v;
+    }
+    if (out == nullptr)
+        return;
+    __syncthreads();
+    const bool out_aligned = ((reinterpret_cast<uintptr_t>(out) | (uintptr_t)(pitch * 4) | (uintptr_t)(X0 * 4)) & 15) == 0;
+    float* exf = colsum;
+    for (int ch = 0; ch < C; ++ch) {
+        float* pl = out + plane * ch;
+        for (int fr = 0; fr < n; ++fr) {
+            for (int fc = tid; fc < kn; fc += NT) {
+                const int kc = fc / n;
+                const float v = cflag[kc] ? vgc[(fr * kn + fc) * C + ch] : vgs[kc * C + ch];
+                for (int x = 0; x < s; ++x)
+                    exf[fc * s + x] = v;
+            }
+            __syncthreads();
+            const int row0 = r * b + fr * s;
+            const int rows = min(s, H - row0);
+            for (int st = tid; st < nstr; st += NT) {
+                const int64_t p0 = X0 + 4 * st;
+                if (p0 >= lim)
+                    continue;
+                const v4f v = reinterpret_cast<const v4f*>(exf)[st];
+                if (out_aligned && p0 + 4 <= lim) {
+                    for (int k = 0; k < rows; ++k)
+                        __builtin_nontemporal_store(v, reinterpret_cast<v4f*>(pl + (int64_t)(row0 + k) * pitch + p0));
+                } else {
+                    const float vv[4] = {v.x, v.y, v.z, v.w};
+                    for (int k = 0; k < rows; ++k)
+                        for (int q = 0; q < 4 && p0 + q < lim; ++q)
+                            pl[(int64_t)(row0 + k) * pitch + p0 + q] = vv[q];
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+__device__ __forceinline__ void forward_tile(const TileArgs& a, const FrameRec& F, const TileCoord& tc, uint8_t* lds)
+{
+    if (F.layout == 1) {
+        forward_tile_f32(a, F, tc, lds);
+        return;
+    }
+    switch (F.C) {
+    case 1: forward_tile_u8<1>(a, F, tc, lds); break;
+    case 2: forward_tile_u8<2>(a, F, tc, lds); break;
+    case 3: forward_tile_u8<3>(a, F, tc, lds); break;
+    default: forward_tile_u8<4>(a, F, tc, lds); break;
+    }
+}
+
+// Persistent workgroups take tiles from an atomic ticket; the last one out
+// resets the ticket for the next launch (no memset, so graphs can replay).
+template <typename Body>
+__device__ __forceinline__ void run_tiles(const TileArgs& a, uint8_t* lds, Body body)
+{
+    if (!a.persistent) {
+        FrameRec F;
+        const TileCoord tc = tile_of(a, blockIdx.x, F);
+        body(F, tc);
+        return;
+    }
+    __shared__ int64_t s_next;
+    for (;;) {
+        if (threadIdx.x == 0)
+            s_next = (int64_t)atomicAdd(&a.ticket[0], 1u);
+        __syncthreads();
+        const int64_t idx = s_next;
+        if (idx >= a.n_tiles)
+            break;
+        FrameRec F;
+        const TileCoord tc = tile_of(a, idx, F);
+        body(F, tc);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const uint32_t done = atomicAdd(&a.ticket[1], 1u);
+        if (done == gridDim.x - 1) {
+            atomicExch(&a.ticket[0], 0u);
+            atomicExch(&a.ticket[1], 0u);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kMaxThreads) void k_forward(TileArgs a)
+{
+    extern __shared__ __align__(16) uint8_t lds[];
+    run_tiles(a, lds, [&](const FrameRec& F, const TileCoord& tc) { forward_tile(a, F, tc, lds); });
+}
+
+// ==========================================================================
+// Reconstruction from the compact store (Sec. VI-F).
+// ==========================================================================
+template <int C>
+__device__ void reconstruct_tile_u8(const TileArgs& a, const FrameRec& F, const TileCoord& tc, uint8_t* lds)
+{
+    const int tid = threadIdx.x, NT = blockDim.x;
+    const int b = F.b, s = F.s, n = F.n, H = F.H, W = F.W;
+    const int r = tc.r;
+    const int x0c = tc.ct * F.K;
+    const int Kt = min(F.K, F.GC - x0c);
+    const int WB = Kt * b * C;
+    const int nstr = (WB + 15) >> 4;
+    const int64_t X0 = (int64_t)x0c * b * C;
+    const int64_t lim = min(X0 + WB, (int64_t)W * C);
+    const int64_t pitch = F.pitch;
+    uint8_t* out = static_cast<uint8_t*>(a.outs[tc.f]);
+    const LdsPlan L = lds_plan(kRecU8, F.K, b, n, C);
+    uint8_t* ex = lds + L.colsum;
+    uint32_t* cidx = reinterpret_cast<uint32_t*>(lds + L.cidx);
+    uint8_t* cflag = lds + L.cflag;
+    uint8_t* vgs = lds + L.vgs;
+    uint8_t* vgc = lds + L.vgc;
+    tile_cells(a, F, tc.t, r, x0c, Kt, cidx, cflag, false);
+    const uint64_t bg_base = a.frame_base[2 * tc.f + 0];
+    const uint64_t fg_base = a.frame_base[2 * tc.f + 1];
+    const int nn = n * n, kn = Kt * n, items = Kt * n * C;
+    __syncthreads();
+    for (int j = tid; j < Kt * C; j += NT) {
+        const int kc = j / C, ch = j - kc * C;
+        if (!cflag[kc])
+            vgs[j] = to_u8(a.bg[bg_base + (uint64_t)cidx[kc] * C + ch]);
+    }
+    for (int j = tid; j < Kt * nn * C; j += NT) {
+        // j = ((fr * kn) + fc) * C + ch
+        const int ch = j % C;
+        const int q = j / C;
+        const int fr = q / kn, fc = q - fr * kn;
+        const int kc = fc / n, jj = fc - kc * n;
+        if (cflag[kc])
+            vgc[j] = to_u8(a.fg[fg_base + ((uint64_t)cidx[kc] * nn + fr * n + jj) * C + ch]);
+    }
+    __syncthreads();
+    const bool out_aligned = ((reinterpret_cast<uintptr_t>(out) | (uintptr_t)pitch | (uintptr_t)X0) & 15) == 0;
+    for (int fr = 0; fr < n; ++fr) {
+        for (int j = tid; j < items; j += NT) {
+            const int fc = j / C, ch = j - fc * C;
+            const int kc = fc / n;
+            const uint8_t v = cflag[kc] ? vgc[(fr * kn + fc) * C + ch] : vgs[kc * C + ch];
+            uint8_t* e = ex + fc * s * C + ch;
+            for (int x = 0; x < s; ++x)
+                e[x * C] = v;
+        }
+        __syncthreads();
+        const int row0 = r * b + fr * s;
+        const int rows = min(s, H - row0);
+        for (int st = tid; st < nstr; st += NT) {
+            const int64_t p0 = X0 + 16 * st;
+            if (p0 >= lim)
+                continue;
+            const v4u v = *reinterpret_cast<const v4u*>(ex + 16 * st);
+            if (out_aligned && p0 + 16 <= lim) {
+                for (int k = 0; k < rows; ++k)
+                    __builtin_nontemporal_store(v, reinterpret_cast<v4u*>(out + (int64_t)(row0 + k) * pitch + p0));
+            } else {
+                const uint8_t* vb = ex + 16 * st;
+                for (int k = 0; k < rows; ++k) {
+                    uint8_t* op = out + (int64_t)(row0 + k) * pitch;
+                    for (int q = 0; q < 16 && p0 + q < lim; ++q)
+                        op[p0 + q] = vb[q];
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__device__ void reconstruct_tile_f32(const TileArgs& a, const FrameRec& F, const TileCoord& tc, uint8_t* lds)
+{
+    const int tid = threadIdx.x, NT = blockDim.x;
+    const int b = F.b, s = F.s, n = F.n, H = F.H, W = F.W, C = F.C;
+    const int r = tc.r;
+    const int x0c = tc.ct * F.K;
+    const int Kt = min(F.K, F.GC - x0c);
+    const int WB = Kt * b;
+    const int nstr = (WB + 3) >> 2;
+    const int64_t X0 = (int64_t)x0c * b;
+    const int64_t lim = min(X0 + WB, (int64_t)W);
+    const int64_t pitch = F.pitch, plane = pitch * H;
+    float* out = static_cast<float*>(a.outs[tc.f]);
+    const LdsPlan L = lds_plan(kRecF32, F.K, b, n, C);
+    float* exf = reinterpret_cast<float*>(lds + L.colsum);
+    uint32_t* cidx = reinterpret_cast<uint32_t*>(lds + L.cidx);
+    uint8_t* cflag = lds + L.cflag;
+    float* vgs = reinterpret_cast<float*>(lds + L.vgs);
+    float* vgc = reinterpret_cast<float*>(lds + L.vgc);
+    tile_cells(a, F, tc.t, r, x0c, Kt, cidx, cflag, false);
+    const uint64_t bg_base = a.frame_base[2 * tc.f + 0];
+    const uint64_t fg_base = a.frame_base[2 * tc.f + 1];
+    const int nn = n * n, kn = Kt * n;
+    __syncthreads();
+    for (int j = tid; j < Kt * C; j += NT) {
+        const int kc = j / C, ch = j - kc * C;
+        if (!cflag[kc])
+            vgs[j] = a.bg[bg_base + (uint64_t)cidx[kc] * C + ch];
+    }
+    for (int j = tid; j < Kt * nn * C; j += NT) {
+        const int ch = j % C;
+        const int q = j / C;
+        const int fr = q / kn, fc = q - fr * kn;
+        const int kc = fc / n, jj = fc - kc * n;
+        if (cflag[kc])
+            vgc[j] = a.fg[fg_base + ((uint64_t)cidx[kc] * nn + fr * n + jj) * C + ch];
+    }
+    __syncthreads();
+    const bool out_aligned = ((reinterpret_cast<uintptr_t>(out) | (uintptr_t)(pitch * 4) | (uintptr_t)(X0 * 4)) & 15) == 0;
+    for (int ch = 0; ch < C; ++ch) {
+        float* pl = out + plane * ch;
+        for (int fr = 0; fr < n; ++fr) {
+            for (int fc = tid; fc < kn; fc += NT) {
+                const int kc = fc / n;
+                const float v = cflag[kc] ? vgc[(fr * kn + fc) * C + ch] : vgs[kc * C + ch];
+                for (int x = 0; x < s; ++x)
+                    exf[fc * s + x] = v;
+            }
+            __syncthreads();
+            const int row0 = r * b + fr * s;
+            const int rows = min(s, H - row0);
+            for (int st = tid; st < nstr; st += NT) {
+                const int64_t p0 = X0 + 4 * st;
+                if (p0 >= lim)
+                    continue;
+                const v4f v = reinterpret_cast<const v4f*>(exf)[st];
+                if (out_aligned && p0 + 4 <= lim) {
+                    for (int k = 0; k < rows; ++k)
+                        __builtin_nontemporal_store(v, reinterpret_cast<v4f*>(pl + (int64_t)(row0 + k) * pitch + p0));
+                } else {
+                    const float vv[4] = {v.x, v.y, v.z, v.w};
+                    for (int k = 0; k < rows; ++k)
+                        for (int q = 0; q < 4 && p0 + q < lim; ++q)
+                            pl[(int64_t)(row0 + k) * pitch + p0 + q] = vv[q];
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+__global__ __launch_bounds__(kMaxThreads) void k_reconstruct(TileArgs a)
+{
+    extern __shared__ __align__(16) uint8_t lds[];
+    run_tiles(a, lds, [&](const FrameRec& F, const TileCoord& tc) {
+        if (F.layout == 1) {
+            reconstruct_tile_f32(a, F, tc, lds);
+            return;
+        }
+        switch (F.C) {
+        case 1: reconstruct_tile_u8<1>(a, F, tc, lds); break;
+        case 2: reconstruct_tile_u8<2>(a, F, tc, lds); break;
+        case 3: reconstruct_tile_u8<3>(a, F, tc, lds); break;
+        default: reconstruct_tile_u8<4>(a, F, tc, lds); break;
+        }
+    });
+}
+
+// ==========================================================================
+// Adjoint (fp32 CHW).  Pass 1 per tile: G_k = sum of grad_out over the real
+// pixels of statistic k, g_k = pass_k * G_k / area_k.  Pass 2 per pixel: sum
+// g over every padded position that folds onto the pixel.
+// ==========================================================================
+__device__ void backward_reduce_tile(const TileArgs& a, const FrameRec& F, const TileCoord& tc, uint8_t* lds)
+{
+    const int tid = threadIdx.x, NT = blockDim.x;
+    const int b = F.b, s = F.s, n = F.n, H = F.H, W = F.W, C = F.C;
+    const int r = tc.r;
+    const int x0c = tc.ct * F.K;
+    const int Kt = min(F.K, F.GC - x0c);
+    const int WB = Kt * b;
+    const int nstr = (WB + 3) >> 2;
+    const int64_t X0 = (int64_t)x0c * b;
+    const int64_t lim = min(X0 + WB, (int64_t)W);
+    const int64_t pitch = F.pitch, plane = pitch * H;
+    const float* go = a.grad_out[tc.f];
+    const bool aligned = ((reinterpret_cast<uintptr_t>(go) | (uintptr_t)(pitch * 4) | (uintptr_t)(X0 * 4)) & 15) == 0;
+    const LdsPlan L = lds_plan(kBwd, F.K, b, n, C);
+    float* colsum = reinterpret_cast<float*>(lds + L.colsum);
+    double* cspart = reinterpret_cast<double*>(lds + L.cspart);
+    uint32_t* cidx = reinterpret_cast<uint32_t*>(lds + L.cidx);
+    uint8_t* cflag = lds + L.cflag;
+    tile_cells(a, F, tc.t, r, x0c, Kt, cidx, cflag, false);
+    const uint64_t bg_base = a.frame_base[2 * tc.f + 0];
+    const uint64_t fg_base = a.frame_base[2 * tc.f + 1];
+    const int nn = n * n, kn = Kt * n;
+    __syncthreads();
+    for (int ch = 0; ch < C; ++ch) {
+        const float* pl = go + plane * ch;
+        for (int fr = 0; fr < n; ++fr) {
+            const int row0 = r * b + fr * s;
+            const int rows = max(0, min(s, H - row0));   // real rows only
+            for (int st = tid; st < nstr; st += NT) {
+                const int64_t p0 = X0 + 4 * st;
+                v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
+                if (aligned && p0 + 4 <= lim) {
+                    for (int k = 0; k < rows; ++k) {
+                        acc += *reinterpret_cast<const v4f*>(pl + (int64_t)(row0 + k) * pitch + p0);
+                    }
+                } else {
+                    for (int k = 0; k < rows; ++k) {
+                        const float* rk = pl + (int64_t)(row0 + k) * pitch;
+                        acc.x += (p0 + 0 < lim) ? rk[p0 + 0] : 0.f;
+                        acc.y += (p0 + 1 < lim) ? rk[p0 + 1] : 0.f;
+                        acc.z += (p0 + 2 < lim) ? rk[p0 + 2] : 0.f;
+                        acc.w += (p0 + 3 < lim) ? rk[p0 + 3] : 0.f;
+                    }
+                }
+                reinterpret_cast<v4f*>(colsum)[st] = acc;
+            }
+            __syncthreads();
+            for (int fc = tid; fc < kn; fc += NT) {
+                double G = 0.0;
+                for (int x = 0; x < s; ++x)
+                    G += (double)colsum[fc * s + x];
+                const int kc = fc / n, jj = fc - kc * n;
+                const int ci = fc * C + ch;
+                cspart[ci] = (fr == 0 ? 0.0 : cspart[ci]) + G;
+                if (cflag[kc]) {
+                    const uint64_t at = fg_base + ((uint64_t)cidx[kc] * nn + fr * n + jj) * C + ch;
+                    a.g_fg[at] = a.clip_fg[at] ? (float)(G / (double)(s * s)) : 0.f;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int j = tid; j < Kt * C; j += NT) {
+        const int kc = j / C, ch = j - kc * C;
+        if (cflag[kc])
+            continue;
+        double G = 0.0;
+        for (int jj = 0; jj < n; ++jj)
+            G += cspart[(kc * n + jj) * C + ch];
+        const uint64_t at = bg_base + (uint64_t)cidx[kc] * C + ch;
+        a.g_bg[at] = a.clip_bg[at] ? (float)(G / (double)(b * b)) : 0.f;
+    }
+}
+
+__global__ __launch_bounds__(kMaxThreads) void k_backward_reduce(TileArgs a)
+{
+    extern __shared__ __align__(16) uint8_t lds[];
+    run_tiles(a, lds, [&](const FrameRec& F, const TileCoord& tc) { backward_reduce_tile(a, F, tc, lds); });
+}
+
+__device__ __forceinline__ float g_at(const TileArgs& a, const FrameRec& F, int f, int y, int x, int ch)
+{
+    const int b = F.b, s = F.s, n = F.n;
+    const int64_t cell = F.cell_base + (int64_t)(y / b) * F.GC + x / b;
+    const uint32_t idx = a.cell_index[cell];
+    if (!a.flags[cell])
+        return a.g_bg[a.frame_base[2 * f] + (uint64_t)idx * F.C + ch];
+    const int i = (y % b) / s, j = (x % b) / s;
+    return a.g_fg[a.frame_base[2 * f + 1] + ((uint64_t)idx * n * n + i * n + j) * F.C + ch];
+}
+
+// One workgroup per (tile): every real pixel of the tile's cells collects its
+// own statistic's gradient plus those of the padded positions mirroring onto it.
+__device__ void backward_spread_tile(const TileArgs& a, const FrameRec& F, const TileCoord& tc)
+{
+    const int tid = threadIdx.x, NT = blockDim.x;
+    const int b = F.b, H = F.H, W = F.W, C = F.C, pad = F.pad;
+    const int x0c = tc.ct * F.K;
+    const int Kt = min(F.K, F.GC - x0c);
+    const int y0 = tc.r * b, y1 = min(y0 + b, H);
+    const int xa = x0c * b, xb = min((x0c + Kt) * b, W);
+    if (y0 >= H || xa >= W)
+        return;
+    const int PR = F.GR * b - H, PC = F.GC * b - W;
+    // rows at or above lo_r (columns at or above lo_c) may have mirror preimages
+    const int lo_r = (PR > 0) ? ((PR <= H - 1) ? H - 1 - PR : 0) : H;
+    const int lo_c = (PC > 0) ? ((PC <= W - 1) ? W - 1 - PC : 0) : W;
+    const int64_t pitch = F.pitch, plane = pitch * H;
+    float* gi = a.grad_in[tc.f];
+    const int wcols = xb - xa;
+    const int64_t npx = (int64_t)(y1 - y0) * wcols;
+    for (int ch = 0; ch < C; ++ch) {
+        for (int64_t q = tid; q < npx; q += NT) {
+            const int y = y0 + (int)(q / wcols), x = xa + (int)(q % wcols);
+            float acc = g_at(a, F, tc.f, y, x, ch);
+            if (y >= lo_r || x >= lo_c) {
+                // mirror rows / columns (padded coordinates >= H, >= W) folding onto y / x
+                for (int yy = (y >= lo_r ? H : F.GR * b); yy < F.GR * b; ++yy)
+                    if (fold(yy, H, pad) == y) {
+                        acc += g_at(a, F, tc.f, yy, x, ch);
+                        for (int xx = (x >= lo_c ? W : F.GC * b); xx < F.GC * b; ++xx)
+                            if (fold(xx, W, pad) == x)
+                                acc += g_at(a, F, tc.f, yy, xx, ch);
+                    }
+                for (int xx = (x >= lo_c ? W : F.GC * b); xx < F.GC * b; ++xx)
+                    if (fold(xx, W, pad) == x)
+                        acc += g_at(a, F, tc.f, y, xx, ch);
+            }
+            gi[plane * ch + (int64_t)y * pitch + x] = acc;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kMaxThreads) void k_backward_spread(TileArgs a)
+{
+    extern __shared__ __align__(16) uint8_t lds[];
+    run_tiles(a, lds, [&](const FrameRec& F, const TileCoord& tc) { backward_spread_tile(a, F, tc); });
+}
+
+// ==========================================================================
+// Diagnostics.
+// ==========================================================================
+__global__ void k_philox(const uint32_t* in, uint32_t* out, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const uint32_t* p = in + 6 * i;
+    const uint4 w = philox10(make_uint4(p[0], p[1], p[2], p[3]), p[4], p[5]);
+    out[4 * i + 0] = w.x;
+    out[4 * i + 1] = w.y;
+    out[4 * i + 2] = w.z;
+    out[4 * i + 3] = w.w;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+// Workgroups asking for more than 64 KiB of LDS must opt in per kernel.
+template <typename K>
+hipError_t allow_lds(K kernel, size_t lds)
+{
+    if (lds <= 65536)
+        return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds);
+}
+
+hipError_t launch_classify(const TileArgs& a, int threads, size_t lds, hipStream_t s)
+{
+    if (a.n_tiles == 0)
+        return hipSuccess;
+    TileArgs b = a;
+    b.persistent = 0;
+    hipError_t e = allow_lds(k_classify, lds);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_classify, dim3((unsigned)a.n_tiles), dim3(threads), lds, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan(const TileArgs& a, uint64_t* counts_out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)a.n_frames), dim3(256), 0, s, a, a.frame_tot);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_scan_frames, dim3(1), dim3(256), 0, s, a, a.frame_tot,
+                       const_cast<uint64_t*>(a.frame_base), counts_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_forward(const TileArgs& a, int threads, size_t lds, int grid, hipStream_t s)
+{
+    if (a.n_tiles == 0)
+        return hipSuccess;
+    hipError_t e = allow_lds(k_forward, lds);
+    if (e != hipSuccess)
+        return e;
+    const unsigned g = a.persistent ? (unsigned)grid : (unsigned)a.n_tiles;
+    hipLaunchKernelGGL(k_forward, dim3(g), dim3(threads), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_reconstruct(const TileArgs& a, int threads, size_t lds, int grid, hipStream_t s)
+{
+    if (a.n_tiles == 0)
+        return hipSuccess;
+    hipError_t e = allow_lds(k_reconstruct, lds);
+    if (e != hipSuccess)
+        return e;
+    const unsigned g = a.persistent ? (unsigned)grid : (unsigned)a.n_tiles;
+    hipLaunchKernelGGL(k_reconstruct, dim3(g), dim3(threads), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_backward(const TileArgs& a, int threads, size_t lds, int grid, int64_t, hipStream_t s)
+{
+    if (a.n_tiles == 0)
+        return hipSuccess;
+    const unsigned g = a.persistent ? (unsigned)grid : (unsigned)a.n_tiles;
+    hipError_t e = allow_lds(k_backward_reduce, lds);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_backward_reduce, dim3(g), dim3(threads), lds, s, a);
+    e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_backward_spread, dim3(g), dim3(threads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_philox(const uint32_t* in, uint32_t* out, int64_t n, hipStream_t s)
+{
+    if (n == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_philox, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, out, n);
+    return hipGetLastError();
+}
+
+hipError_t occupancy_forward(int threads, size_t lds, int* blocks_per_cu)
+{
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_forward, threads, lds);
+}
+
+}  // namespace dppix

@@ -1,0 +1,75 @@
+// dppix_tiles.h — LDS carving of one work tile, shared by the host (to size
+// dynamic LDS) and the kernels (to place their buffers).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dppix {
+
+enum TileKind : int {
+    kClassify = 0,   // mask counts per cell
+    kFwdU8 = 1,      // forward, uint8 HWC
+    kFwdF32 = 2,     // forward, fp32 CHW
+    kRecU8 = 3,      // reconstruction, uint8 HWC
+    kRecF32 = 4,     // reconstruction, fp32 CHW
+    kBwd = 5         // adjoint reduction, fp32 CHW
+};
+
+struct LdsPlan {
+    uint32_t colsum;  // per padded column (byte or float) of the tile; reused as the expanded output row
+    uint32_t cspart;  // per (subcell column, channel) running sum over subcell rows
+    uint32_t cidx;    // per cell: index within its class (frame-local)
+    uint32_t cflag;   // per cell: 1 = complex
+    uint32_t vgs;     // per (cell, channel): value of a simple cell
+    uint32_t vgc;     // per (subcell row, subcell column, channel): value of a complex subcell
+    uint32_t bytes;
+};
+
+__host__ __device__ inline uint32_t al16(uint32_t x) { return (x + 15u) & ~15u; }
+
+// Number of 16-byte strips covering K cells of one padded row of the tile.
+__host__ __device__ inline uint32_t tile_strips(int kind, int K, int b, int C)
+{
+    if (kind == kClassify)
+        return (uint32_t)((K * b + 15) / 16);
+    if (kind == kFwdF32 || kind == kRecF32 || kind == kBwd)
+        return (uint32_t)((K * b + 3) / 4);
+    return (uint32_t)((K * b * C + 15) / 16);
+}
+
+__host__ __device__ inline LdsPlan lds_plan(int kind, int K, int b, int n, int C)
+{
+    LdsPlan p{};
+    const uint32_t nstr = tile_strips(kind, K, b, C);
+    uint32_t o = 0;
+    p.colsum = o;
+    // u8 column sums are 32-bit per byte column; f32 sums are one float per column
+    if (kind == kClassify || kind == kFwdU8)
+        o += al16(64u * nstr);
+    else
+        o += al16(16u * nstr);
+    p.cspart = o;
+    if (kind == kFwdU8)
+        o += al16(4u * (uint32_t)(K * n * C));
+    else if (kind == kFwdF32 || kind == kBwd)
+        o += al16(8u * (uint32_t)(K * n * C));
+    p.cidx = o;
+    o += al16(4u * (uint32_t)K);
+    p.cflag = o;
+    o += al16((uint32_t)K);
+    p.vgs = o;
+    if (kind == kFwdU8 || kind == kRecU8)
+        o += al16((uint32_t)(K * C));
+    else if (kind == kFwdF32 || kind == kRecF32)
+        o += al16(4u * (uint32_t)(K * C));
+    p.vgc = o;
+    if (kind == kFwdU8 || kind == kRecU8)
+        o += al16((uint32_t)(K * n * n * C));
+    else if (kind == kFwdF32 || kind == kRecF32)
+        o += al16(4u * (uint32_t)(K * n * n * C));
+    p.bytes = o;
+    return p;
+}
+
+}  // namespace dppix
