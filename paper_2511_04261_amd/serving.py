@@ -1,0 +1,386 @@
+"""Continuous-batching server for many camera streams (not in the paper; the
+paper motivates real-time use but times one frame at a time).
+
+Requests (one frame of one stream) arrive at any time.  The scheduler admits
+them while the device-memory ledger has room, starts each admitted frame's
+host-to-device copy at once on a copy stream, and launches every admitted,
+copied frame as one batch (one plan, one persistent forward) as soon as fewer
+than ``max_inflight`` batches are on the GPU — so frames that arrive while a
+batch runs are copied during it and join the next one.  Each frame keeps its
+own Philox counter (its stream's sequence number), so its result is the same
+alone or in any mix.
+
+The scheduler is host logic over a small backend interface; ``GpuBackend``
+drives libdppix, and the tests drive the same scheduler with a CPU backend.
+"""
+from __future__ import annotations
+
+import collections
+import ctypes
+import math
+import time
+from dataclasses import dataclass, field
+from typing import Any, Deque, Dict, List, Optional
+
+import numpy as np
+
+
+@dataclass
+class Request:
+    rid: int
+    stream: int
+    frame_index: int
+    height: int
+    width: int
+    channels: int
+    b: int
+    sb: int
+    m: int
+    eps_bg: float
+    eps_fg: float
+    tau: int
+    seed: int
+    image: Any = None            # host uint8 (H, W, C) (numpy or pinned torch)
+    mask: Any = None             # host uint8 (H, W) or None
+    arrival: float = 0.0
+    admitted: Optional[float] = None
+    launched: Optional[float] = None
+    done: Optional[float] = None
+    result: Optional[dict] = None
+    error: Optional[str] = None
+    nbytes: int = 0
+    state: Any = None            # backend bookkeeping
+
+    @property
+    def latency(self) -> Optional[float]:
+        return None if self.done is None else self.done - self.arrival
+
+
+class MemoryLedger:
+    """Device bytes held by admitted, unfinished requests."""
+
+    def __init__(self, cap_bytes: int):
+        self.cap = int(cap_bytes)
+        self.used = 0
+        self.peak = 0
+
+    def try_reserve(self, n: int) -> bool:
+        if self.used + n > self.cap:
+            return False
+        self.used += n
+        self.peak = max(self.peak, self.used)
+        return True
+
+    def release(self, n: int):
+        self.used -= n
+        assert self.used >= 0
+
+
+class Scheduler:
+    """Admission by memory, continuous batching, completion polling."""
+
+    def __init__(self, backend, ledger: MemoryLedger, max_batch: int = 64, max_inflight: int = 2,
+                 max_queue: int = 4096, clock=time.perf_counter):
+        self.backend = backend
+        self.ledger = ledger
+        self.max_batch = max_batch
+        self.max_inflight = max_inflight
+        self.max_queue = max_queue
+        self.clock = clock
+        self.queue: Deque[Request] = collections.deque()     # waiting for memory
+        self.admitted: List[Request] = []                     # copying / ready, not launched
+        self.inflight: Deque[Any] = collections.deque()       # (handle, [requests])
+        self.finished: List[Request] = []
+        self.rejected: List[Request] = []
+        self.batches = 0
+        self.batch_sizes: List[int] = []
+
+    # -- intake ------------------------------------------------------------
+    def offer(self, req: Request):
+        err = self.backend.validate(req)
+        if err is not None:
+            req.error = err
+            req.done = self.clock()
+            self.rejected.append(req)
+            return
+        req.nbytes = self.backend.request_bytes(req)
+        if req.nbytes > self.ledger.cap:
+            req.error = "request needs %d bytes, above the memory cap %d" % (req.nbytes, self.ledger.cap)
+            req.done = self.clock()
+            self.rejected.append(req)
+            return
+        if len(self.queue) >= self.max_queue:
+            req.error = "queue full"
+            req.done = self.clock()
+            self.rejected.append(req)
+            return
+        self.queue.append(req)
+
+    # -- one turn of the loop ----------------------------------------------
+    def pump(self) -> int:
+        """Admit, launch, complete; returns how many requests changed state."""
+        moved = 0
+        # completions first: they free memory for admissions
+        while self.inflight and self.backend.poll(self.inflight[0][0]):
+            handle, reqs = self.inflight.popleft()
+            now = self.clock()
+            results = self.backend.collect(handle)
+            for r, res in zip(reqs, results):
+                r.result = res
+                r.done = now
+                self.ledger.release(r.nbytes)
+                self.backend.release(r)
+                self.finished.append(r)
+                moved += 1
+        # admissions in arrival order; a request that does not fit blocks the
+        # ones behind it (no overtaking, so per-stream order holds)
+        while self.queue and self.ledger.try_reserve(self.queue[0].nbytes):
+            r = self.queue.popleft()
+            r.admitted = self.clock()
+            self.backend.admit(r)
+            self.admitted.append(r)
+            moved += 1
+        # launch everything admitted (up to max_batch) when a batch slot is free
+        if self.admitted and len(self.inflight) < self.max_inflight:
+            batch = self.admitted[: self.max_batch]
+            self.admitted = self.admitted[self.max_batch:]
+            now = self.clock()
+            for r in batch:
+                r.launched = now
+            try:
+                self.inflight.append((self.backend.launch(batch), batch))
+                self.batches += 1
+                self.batch_sizes.append(len(batch))
+            except Exception:
+                # isolate the request that fails: relaunch each one alone
+                for r in batch:
+                    try:
+                        self.inflight.append((self.backend.launch([r]), [r]))
+                        self.batches += 1
+                        self.batch_sizes.append(1)
+                    except Exception as e:  # this request alone is bad
+                        r.error = "%s: %s" % (type(e).__name__, e)
+                        r.done = self.clock()
+                        self.ledger.release(r.nbytes)
+                        self.backend.release(r)
+                        self.rejected.append(r)
+            moved += len(batch)
+        return moved
+
+    def idle(self) -> bool:
+        return not self.queue and not self.admitted and not self.inflight
+
+    def drain(self, timeout_s: float = 60.0):
+        t0 = self.clock()
+        while not self.idle():
+            if self.pump() == 0:
+                time.sleep(1e-4)
+            if self.clock() - t0 > timeout_s:
+                raise TimeoutError("scheduler did not drain")
+
+
+def latency_stats(reqs: List[Request]) -> Dict[str, float]:
+    lat = np.array([r.latency for r in reqs if r.latency is not None and r.error is None])
+    if lat.size == 0:
+        return dict(n=0)
+    return dict(n=int(lat.size), p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3),
+                max_ms=float(lat.max() * 1e3), mean_ms=float(lat.mean() * 1e3))
+
+
+# ---------------------------------------------------------------------------
+# GPU backend over libdppix
+# ---------------------------------------------------------------------------
+class GpuBackend:
+    """Frames are copied host->device on a copy stream at admission; a batch
+    waits for its copies on the compute stream, runs plan + forward (optionally
+    with the fused reconstruction), and its store is copied back on the copy
+    stream into pinned host memory."""
+
+    def __init__(self, device=None, reconstruct: bool = False, persistent: bool = True):
+        import torch
+        import paper_2511_04261_amd as dp
+        self.torch = torch
+        self.dp = dp
+        self.device = torch.device(device if device is not None else "cuda:0")
+        self.reconstruct = reconstruct
+        self.persistent = persistent
+        self.copy_stream = torch.cuda.Stream(self.device)
+        self.compute_stream = torch.cuda.Stream(self.device)
+        self._pool: Dict[tuple, List[Any]] = collections.defaultdict(list)
+
+    def frame_params(self, r: Request):
+        return self.dp.FrameParams(r.height, r.width, r.channels, self.dp.U8_HWC, r.b, r.sb, r.m, r.eps_bg,
+                                   r.eps_fg, r.tau, self.dp.PAD_SYMMETRIC, r.seed, r.frame_index)
+
+    def validate(self, r: Request) -> Optional[str]:
+        lib = self.dp._lib.load()
+        d = (self.dp._lib.FrameDesc * 1)(self.frame_params(r).desc())
+        h = ctypes.c_void_p()
+        st = lib.dp_pix_plan_create(d, 1, ctypes.byref(h))
+        if st != 0:
+            return lib.dp_pix_last_error().decode(errors="replace")
+        lib.dp_pix_plan_destroy(h)
+        if r.image is None or tuple(r.image.shape[:2]) != (r.height, r.width):
+            return "image does not match the request geometry"
+        return None
+
+    def request_bytes(self, r: Request) -> int:
+        n = r.b // r.sb
+        cells = -(-r.height // r.b) * -(-r.width // r.b)
+        img = r.height * r.width * r.channels
+        store = 4 * cells * r.channels * (1 + n * n) + cells
+        return img + r.height * r.width + store + (img if self.reconstruct else 0)
+
+    def _buf(self, shape, dtype):
+        lst = self._pool[(shape, dtype)]
+        if lst:
+            return lst.pop()
+        return self.torch.empty(shape, dtype=dtype, device=self.device)
+
+    def admit(self, r: Request):
+        torch = self.torch
+        img = self._buf(tuple(r.image.shape), torch.uint8)
+        mk = None if r.mask is None else self._buf(tuple(r.mask.shape), torch.uint8)
+        with torch.cuda.stream(self.copy_stream):
+            src = r.image if isinstance(r.image, torch.Tensor) else torch.from_numpy(r.image)
+            img.copy_(src, non_blocking=True)
+            if mk is not None:
+                msrc = r.mask if isinstance(r.mask, torch.Tensor) else torch.from_numpy(r.mask)
+                mk.copy_(msrc, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(self.copy_stream)
+        r.state = dict(img=img, mask=mk, ev=ev)
+
+    def launch(self, batch: List[Request]):
+        torch = self.torch
+        frames = [self.frame_params(r) for r in batch]
+        with torch.cuda.stream(self.compute_stream):
+            for r in batch:
+                self.compute_stream.wait_event(r.state["ev"])
+            plan = self.dp.Plan(frames, device=self.device, persistent=self.persistent)
+            imgs = [r.state["img"] for r in batch]
+            masks = [r.state["mask"] for r in batch]
+            outs = [self._buf(tuple(t.shape), torch.uint8) for t in imgs] if self.reconstruct else None
+            plan.plan(masks if any(m is not None for m in masks) else None)
+            plan.forward(imgs, out=outs)
+            done = torch.cuda.Event()
+            done.record(self.compute_stream)
+        # store back to pinned host memory on the copy stream
+        with torch.cuda.stream(self.copy_stream):
+            self.copy_stream.wait_event(done)
+            host = dict(counts=plan.counts.to("cpu", non_blocking=True), bg=plan.bg.to("cpu", non_blocking=True),
+                        fg=plan.fg.to("cpu", non_blocking=True), flags=plan.flags.to("cpu", non_blocking=True))
+            if outs is not None:
+                host["recon"] = [o.to("cpu", non_blocking=True) for o in outs]
+            fin = torch.cuda.Event()
+            fin.record(self.copy_stream)
+        return dict(plan=plan, host=host, fin=fin, outs=outs, batch=batch)
+
+    def poll(self, handle) -> bool:
+        return handle["fin"].query()
+
+    def collect(self, handle) -> List[dict]:
+        plan, host = handle["plan"], handle["host"]
+        counts = host["counts"].numpy()
+        bg, fg, flags = host["bg"].numpy(), host["fg"].numpy(), host["flags"].numpy()
+        res = []
+        for f, (fp, fi) in enumerate(zip(plan.frames, plan.info)):
+            nb, nf, ob, of = (int(x) for x in counts[f])
+            C, nn = fp.channels, fi.n * fi.n
+            d = dict(flags=flags[fi.cell_offset: fi.cell_offset + fi.grid_rows * fi.grid_cols].reshape(
+                fi.grid_rows, fi.grid_cols).copy(), bg=bg[ob: ob + nb * C].reshape(nb, C).copy(),
+                fg=fg[of: of + nf * nn * C].reshape(nf, nn, C).copy(), counts=(nb, nf))
+            if "recon" in host:
+                d["recon"] = host["recon"][f].numpy()
+            res.append(d)
+        if handle["outs"] is not None:
+            for o in handle["outs"]:
+                self._pool[(tuple(o.shape), self.torch.uint8)].append(o)
+        plan.close()
+        return res
+
+    def release(self, r: Request):
+        st = r.state or {}
+        if st.get("img") is not None:
+            self._pool[(tuple(st["img"].shape), self.torch.uint8)].append(st["img"])
+        if st.get("mask") is not None:
+            self._pool[(tuple(st["mask"].shape), self.torch.uint8)].append(st["mask"])
+        r.state = None
+
+
+# ---------------------------------------------------------------------------
+# Camera-stream workload
+# ---------------------------------------------------------------------------
+@dataclass
+class StreamSpec:
+    stream: int
+    height: int
+    width: int
+    arrivals: np.ndarray
+    pool_images: list = field(default_factory=list)   # pinned host frames, cycled
+    pool_masks: list = field(default_factory=list)
+
+
+def camera_streams(duration_s: float = 60.0, rate_hz: float = 30.0, seed: int = 1004, pool: int = 8,
+                   mix=None, device=None, pinned: bool = True):
+    """16 streams (8 x 1080p, 6 x 768x576, 2 x 2160p) with Poisson arrivals;
+    each stream cycles a pool of rendered frames with moving-rectangle masks."""
+    import torch
+    from . import synth
+    mix = mix if mix is not None else synth.STREAM_MIX
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    sid = 0
+    dev = device if device is not None else ("cuda:0" if torch.cuda.is_available() else "cpu")
+    for (h, w, count) in mix:
+        for _ in range(count):
+            arr = synth.poisson_arrivals(rng, rate_hz, duration_s)
+            ramps = [synth.draw_ramp(rng) for _ in range(3)]
+            mover = synth.MovingRects(rng, h, w)
+            imgs, masks = [], []
+            base = synth.render_image_torch(ramps, h, w, dev)
+            for k in range(pool):
+                img = torch.roll(base, shifts=3 * k, dims=1).cpu()
+                mk = synth.paint_mask_torch(mover.step(), h, w, dev).cpu()
+                if pinned and torch.cuda.is_available():
+                    img, mk = img.pin_memory(), mk.pin_memory()
+                imgs.append(img)
+                masks.append(mk)
+            out.append(StreamSpec(sid, h, w, arr, imgs, masks))
+            sid += 1
+    return out
+
+
+def serve_streams(streams, scheduler: Scheduler, params: dict, duration_s: Optional[float] = None,
+                  seed: int = 4, keep_results: bool = False, clock=time.perf_counter):
+    """Replay the streams' arrivals in real time through the scheduler.
+    params: b, sb, m, eps_bg, eps_fg, tau.  Returns the finished requests."""
+    events = []
+    for s in streams:
+        for k, t in enumerate(s.arrivals):
+            if duration_s is None or t < duration_s:
+                events.append((float(t), s.stream, k))
+    events.sort()
+    by_id = {s.stream: s for s in streams}
+    t0 = clock()
+    i = rid = 0
+    while i < len(events) or not scheduler.idle():
+        now = clock() - t0
+        while i < len(events) and events[i][0] <= now:
+            t, sid, k = events[i]
+            s = by_id[sid]
+            r = Request(rid, sid, k, s.height, s.width, 3, params["b"], params["sb"], params["m"],
+                        params["eps_bg"], params["eps_fg"], params["tau"], seed,
+                        image=s.pool_images[k % len(s.pool_images)], mask=s.pool_masks[k % len(s.pool_masks)],
+                        arrival=t0 + t)
+            scheduler.offer(r)
+            rid += 1
+            i += 1
+        if scheduler.pump() == 0:
+            nxt = events[i][0] - (clock() - t0) if i < len(events) else 0.0
+            time.sleep(min(max(nxt, 0.0), 2e-4))
+    done = scheduler.finished
+    if not keep_results:
+        for r in done:
+            r.result = None
+    return done

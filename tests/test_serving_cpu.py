@@ -1,0 +1,171 @@
+"""Serving scheduler on the CPU: admission by memory, continuous batching,
+failure isolation and ordering, with the oracle as a fake backend."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2511_04261_amd import synth
+from paper_2511_04261_amd.serving import MemoryLedger, Request, Scheduler, latency_stats
+
+
+class FakeClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        self.t += 1e-3
+        return self.t
+
+
+class CpuBackend:
+    """Runs the oracle per request; a batch completes after `polls` polls."""
+
+    def __init__(self, polls=2, explode_on=None):
+        self.polls = polls
+        self.explode_on = explode_on or set()
+        self.launches = []
+
+    @staticmethod
+    def params(r):
+        return oracle.Params(r.height, r.width, r.channels, b=r.b, sb=r.sb, m=r.m, eps_simple=r.eps_bg,
+                             eps_complex=r.eps_fg, tau=r.tau, seed=r.seed, frame_index=r.frame_index)
+
+    def validate(self, r):
+        try:
+            self.params(r).geometry()
+        except ValueError as e:
+            return str(e)
+        if r.image is None or r.image.shape[:2] != (r.height, r.width):
+            return "image does not match the request geometry"
+        return None
+
+    def request_bytes(self, r):
+        return r.height * r.width * (r.channels + 1)
+
+    def admit(self, r):
+        r.state = "admitted"
+
+    def launch(self, batch):
+        if any(r.rid in self.explode_on for r in batch):
+            raise RuntimeError("backend failure on request %s" % [r.rid for r in batch if r.rid in self.explode_on])
+        self.launches.append([r.rid for r in batch])
+        res = [oracle.forward(r.image, r.mask, self.params(r)) for r in batch]
+        return {"left": self.polls, "res": res}
+
+    def poll(self, h):
+        h["left"] -= 1
+        return h["left"] <= 0
+
+    def collect(self, h):
+        return h["res"]
+
+    def release(self, r):
+        r.state = None
+
+
+def make_requests(n, streams=3, H=24, W=40, seed=0):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    reqs = []
+    per = [0] * streams
+    for i in range(n):
+        s = i % streams
+        img = synth.gradient_image(rng, H, W, 3)
+        mk = synth.rect_mask(rng, H, W, n_rects=2, rect_frac=0.05, cover=(0.05, 0.3))
+        reqs.append(Request(i, s, per[s], H, W, 3, 8, 4, 4, 1.0, 0.5, 1, 9, image=img, mask=mk, arrival=0.0))
+        per[s] += 1
+    return reqs
+
+
+def run(sched, reqs, per_pump=1):
+    i = 0
+    while i < len(reqs) or not sched.idle():
+        for _ in range(per_pump):
+            if i < len(reqs):
+                sched.offer(reqs[i])
+                i += 1
+        sched.pump()
+
+
+def test_every_request_gets_its_own_result_in_stream_order():
+    be = CpuBackend()
+    sch = Scheduler(be, MemoryLedger(10**9), max_batch=8, max_inflight=2, clock=FakeClock())
+    reqs = make_requests(30)
+    run(sch, reqs, per_pump=3)
+    assert len(sch.finished) == 30 and not sch.rejected
+    for r in reqs:
+        alone = oracle.forward(r.image, r.mask, CpuBackend.params(r))
+        assert np.array_equal(r.result["bg"], alone["bg"]) and np.array_equal(r.result["fg"], alone["fg"])
+    for s in range(3):
+        order = [r.frame_index for r in sch.finished if r.stream == s]
+        assert order == sorted(order)
+
+
+def test_continuous_batching_joins_arrivals_during_flight():
+    be = CpuBackend(polls=4)
+    sch = Scheduler(be, MemoryLedger(10**9), max_batch=64, max_inflight=1, clock=FakeClock())
+    reqs = make_requests(24)
+    run(sch, reqs, per_pump=1)
+    # first batch launches at once with one request; later ones collect what
+    # arrived while the previous batch was in flight
+    assert sch.batch_sizes[0] == 1
+    assert max(sch.batch_sizes) >= 3
+    assert sum(sch.batch_sizes) == 24
+
+
+def test_memory_cap_queues_and_bounds_peak():
+    be = CpuBackend(polls=3)
+    need = 24 * 40 * 4
+    led = MemoryLedger(3 * need)
+    sch = Scheduler(be, led, max_batch=64, max_inflight=4, clock=FakeClock())
+    reqs = make_requests(20)
+    run(sch, reqs, per_pump=5)
+    assert len(sch.finished) == 20
+    assert led.peak <= 3 * need and led.used == 0
+    assert max(sch.batch_sizes) <= 3
+
+
+def test_request_above_cap_and_malformed_fail_alone():
+    be = CpuBackend()
+    sch = Scheduler(be, MemoryLedger(24 * 40 * 4 * 4), clock=FakeClock())
+    reqs = make_requests(6)
+    big = Request(100, 0, 99, 400, 400, 3, 8, 4, 4, 1.0, 0.5, 1, 9, image=np.zeros((400, 400, 3), np.uint8))
+    bad = Request(101, 1, 98, 24, 40, 3, 8, 3, 4, 1.0, 0.5, 1, 9, image=np.zeros((24, 40, 3), np.uint8))
+    mism = Request(102, 2, 97, 24, 40, 3, 8, 4, 4, 1.0, 0.5, 1, 9, image=np.zeros((10, 10, 3), np.uint8))
+    run(sch, reqs[:3] + [big, bad, mism] + reqs[3:], per_pump=2)
+    assert {r.rid for r in sch.rejected} == {100, 101, 102}
+    assert "cap" in big.error and mism.error
+    assert len(sch.finished) == 6 and all(r.error is None for r in sch.finished)
+
+
+def test_backend_failure_in_a_batch_is_isolated():
+    be = CpuBackend(explode_on={4})
+    sch = Scheduler(be, MemoryLedger(10**9), max_batch=8, max_inflight=1, clock=FakeClock())
+    reqs = make_requests(10)
+    for r in reqs:
+        sch.offer(r)
+    sch.drain()
+    assert [r.rid for r in sch.rejected] == [4]
+    assert "backend failure" in reqs[4].error
+    assert len(sch.finished) == 9
+    assert sch.ledger.used == 0
+
+
+def test_queue_limit_rejects():
+    be = CpuBackend()
+    sch = Scheduler(be, MemoryLedger(1), max_queue=2, clock=FakeClock())  # nothing fits... except rejection
+    reqs = make_requests(3)
+    for r in reqs:
+        sch.offer(r)
+    assert all("cap" in r.error for r in sch.rejected)
+
+
+def test_latency_stats():
+    rs = []
+    for i, lat in enumerate([0.001 * k for k in range(1, 101)]):
+        r = Request(i, 0, i, 1, 1, 1, 1, 1, 1, 1.0, 1.0, 1, 0, arrival=0.0)
+        r.done = lat
+        rs.append(r)
+    st = latency_stats(rs)
+    assert st["n"] == 100 and abs(st["p50_ms"] - 50.5) < 1e-9 and abs(st["p99_ms"] - 99.01) < 1e-9
