@@ -1,0 +1,142 @@
+"""Tile-shape autotuner.
+
+Results never depend on the tile shape or the launch mode (exact integer sums,
+an index-ordered scan, geometry-keyed noise), so the tuner is free to pick the
+fastest.  For each geometry class (layout, H, W, C, b, s_b) it times
+plan + forward on a synthetic batch of that class large enough to fill the GPU,
+for a few tile widths and workgroup sizes and both launch modes, with HIP
+events, and keeps the median-fastest.  Winners are cached in a JSON file keyed
+by the device name and the class.
+"""
+from __future__ import annotations
+
+import json
+import os
+import statistics
+from dataclasses import replace
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import F32_CHW, U8_HWC, FrameParams, Plan
+
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "dppix", "autotune.json")
+TILE_BYTES = (1024, 2048, 4096, 8192)
+THREADS = (128, 256, 512)
+
+
+def class_key(fp: FrameParams) -> str:
+    sb = fp.b if fp.sb is None else fp.sb
+    return "%s:%dx%dx%d:b%d:s%d" % ("u8" if fp.layout == U8_HWC else "f32", fp.height, fp.width, fp.channels,
+                                    fp.b, sb)
+
+
+def tile_candidates(fp: FrameParams) -> List[int]:
+    unit = fp.b * fp.channels if fp.layout == U8_HWC else 4 * fp.b
+    gc = -(-fp.width // fp.b)
+    out = {0}
+    for tb in TILE_BYTES:
+        out.add(int(min(gc, max(1, tb // unit))))
+    return sorted(out)
+
+
+def _device_name(device) -> str:
+    import torch
+    return torch.cuda.get_device_name(device).replace(" ", "_")
+
+
+def _class_batch(fp: FrameParams, device, min_pixels: float):
+    """Synthetic frames of one class: random bytes, ~15% rectangle masks."""
+    import torch
+    from . import synth
+    n = max(1, int(np.ceil(min_pixels / (fp.height * fp.width))))
+    g = torch.Generator(device=device)
+    g.manual_seed(1234)
+    rng = np.random.Generator(np.random.PCG64(4321))
+    imgs, masks = [], []
+    for _ in range(n):
+        if fp.layout == U8_HWC:
+            imgs.append(torch.randint(0, 256, (fp.height, fp.width, fp.channels), dtype=torch.uint8, device=device,
+                                      generator=g))
+        else:
+            imgs.append(torch.rand((fp.channels, fp.height, fp.width), device=device, generator=g) * 255)
+        masks.append(synth.paint_mask_torch(synth.draw_rects(rng, fp.height, fp.width), fp.height, fp.width, device))
+    return n, imgs, masks
+
+
+def time_config(frames: Sequence[FrameParams], imgs, masks, device, threads: int, persistent: bool,
+                reps: int = 5, fused: bool = True) -> float:
+    """Median ms of plan + forward for one launch configuration."""
+    import torch
+    plan = Plan(frames, device=device, threads=threads, persistent=persistent)
+    outs = [torch.empty_like(t) for t in imgs] if fused else None
+    stream = torch.cuda.current_stream()
+    times = []
+    for i in range(reps + 1):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        plan.plan(masks)
+        plan.forward(imgs, out=outs)
+        b.record(stream)
+        b.synchronize()
+        if i:
+            times.append(a.elapsed_time(b))
+    plan.close()
+    return statistics.median(times)
+
+
+class Autotuner:
+    def __init__(self, device=None, cache_path: Optional[str] = DEFAULT_CACHE, min_pixels: float = 64e6,
+                 reps: int = 5):
+        import torch
+        self.device = torch.device(device if device is not None else "cuda:0")
+        self.cache_path = cache_path
+        self.min_pixels = min_pixels
+        self.reps = reps
+        self.cache: Dict[str, dict] = {}
+        if cache_path and os.path.exists(cache_path):
+            with open(cache_path) as f:
+                self.cache = json.load(f)
+
+    def _save(self):
+        if not self.cache_path:
+            return
+        os.makedirs(os.path.dirname(self.cache_path), exist_ok=True)
+        tmp = self.cache_path + ".tmp%d" % os.getpid()
+        with open(tmp, "w") as f:
+            json.dump(self.cache, f, indent=1, sort_keys=True)
+        os.replace(tmp, self.cache_path)
+
+    def tune_class(self, fp: FrameParams) -> dict:
+        key = _device_name(self.device) + "|" + class_key(fp)
+        if key in self.cache:
+            return self.cache[key]
+        n, imgs, masks = _class_batch(fp, self.device, self.min_pixels)
+        results: List[Tuple[float, int, int, bool]] = []
+        for tc in tile_candidates(fp):
+            frames = [replace(fp, tile_cells=tc, frame_index=i) for i in range(n)]
+            for th in THREADS:
+                for pers in (False, True):
+                    ms = time_config(frames, imgs, masks, self.device, th, pers, self.reps)
+                    results.append((ms, tc, th, pers))
+        results.sort()
+        ms, tc, th, pers = results[0]
+        best = dict(tile_cells=tc, threads=th, persistent=pers, ms=ms, frames=n,
+                    mpix_per_s=n * fp.height * fp.width / (ms * 1e-3) / 1e6,
+                    tried=[dict(ms=r[0], tile_cells=r[1], threads=r[2], persistent=r[3]) for r in results[:8]])
+        self.cache[key] = best
+        self._save()
+        return best
+
+    def tune_batch(self, frames: Sequence[FrameParams]) -> Tuple[List[FrameParams], dict]:
+        """Per-class tile widths for every frame, and one launch shape for the
+        batch: the workgroup size voted by pixel count, persistent mode."""
+        votes: Dict[int, float] = {}
+        out = []
+        for fp in frames:
+            best = self.tune_class(fp)
+            out.append(replace(fp, tile_cells=best["tile_cells"]))
+            votes[best["threads"]] = votes.get(best["threads"], 0.0) + fp.height * fp.width
+        threads = max(votes, key=votes.get)
+        return out, dict(threads=threads, persistent=True)

@@ -41,6 +41,13 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 }  // namespace
 
+// Frames sharing layout and channel count, launched together.
+struct LaunchGroup {
+    int layout, C;
+    int64_t lo, hi;       // scheduling-index range
+    size_t lds_fwd, lds_rec;
+};
+
 struct dppix_plan {
     std::vector<dppix_frame_desc_t> desc;
     std::vector<FrameRec> frames;
@@ -53,6 +60,7 @@ struct dppix_plan {
     size_t bg_cap = 0, fg_cap = 0;
     WsLayout ws{};
     size_t lds[6] = {0, 0, 0, 0, 0, 0};
+    std::vector<LaunchGroup> groups;
     bool any_f32 = false, any_u8 = false;
     int threads = kDefaultThreads;
     int persistent = 0;
@@ -268,7 +276,13 @@ dppix_status_t dp_pix_plan_create(const dppix_frame_desc_t* descs, int32_t n_fra
         const int64_t bpp = F.layout == DPPIX_F32_CHW ? 4 : 1;
         return (int64_t)F.b * F.K * F.b * F.C * bpp;
     };
-    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return tile_cost(x) > tile_cost(y); });
+    // group-major (one kernel instantiation per layout and channel count)
+    auto group_key = [&](int32_t f) { return p->frames[f].layout * 8 + p->frames[f].C; };
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+        if (group_key(x) != group_key(y))
+            return group_key(x) < group_key(y);
+        return tile_cost(x) > tile_cost(y);
+    });
     p->sched_frame = order;
     p->sched_base.resize(n_frames + 1);
     int64_t acc = 0;
@@ -278,6 +292,15 @@ dppix_status_t dp_pix_plan_create(const dppix_frame_desc_t* descs, int32_t n_fra
         acc += (int64_t)F.GR * F.TX;
     }
     p->sched_base[n_frames] = acc;
+    for (int32_t k = 0; k < n_frames; ++k) {
+        const FrameRec& F = p->frames[order[k]];
+        if (p->groups.empty() || p->groups.back().layout != F.layout || p->groups.back().C != F.C)
+            p->groups.push_back(LaunchGroup{F.layout, F.C, p->sched_base[k], p->sched_base[k], 0, 0});
+        LaunchGroup& g = p->groups.back();
+        g.hi = p->sched_base[k + 1];
+        g.lds_fwd = std::max(g.lds_fwd, frame_lds(kind_fwd(F), F));
+        g.lds_rec = std::max(g.lds_rec, frame_lds(kind_rec(F), F));
+    }
 
     // Workspace layout.
     WsLayout& w = p->ws;
@@ -290,7 +313,7 @@ dppix_status_t dp_pix_plan_create(const dppix_frame_desc_t* descs, int32_t n_fra
     w.tile_fg = o;     o = align256(o + sizeof(uint32_t) * (size_t)p->n_tiles);
     w.frame_tot = o;   o = align256(o + sizeof(uint64_t) * 2 * n_frames);
     w.frame_base = o;  o = align256(o + sizeof(uint64_t) * 2 * n_frames);
-    w.counters = o;    o = align256(o + sizeof(uint32_t) * 8);
+    w.counters = o;    o = align256(o + sizeof(uint32_t) * kTicketWords);
     w.total = o;
 
     // Host image of the static tables (frames, sched_frame, sched_base).
@@ -370,7 +393,7 @@ dppix_status_t dp_pix_plan_bind(dppix_plan_t p, void* ws, size_t bytes, dppix_st
     if (e != hipSuccess)
         return dev_fail(e, "uploading plan tables");
     // tickets start at zero; the scan kernel clears them again on every plan
-    e = hipMemsetAsync(static_cast<uint8_t*>(ws) + p->ws.counters, 0, sizeof(uint32_t) * 8,
+    e = hipMemsetAsync(static_cast<uint8_t*>(ws) + p->ws.counters, 0, sizeof(uint32_t) * kTicketWords,
                        reinterpret_cast<hipStream_t>(stream));
     if (e != hipSuccess)
         return dev_fail(e, "clearing tickets");
@@ -421,20 +444,38 @@ dppix_status_t check_store(const dppix_store_t* s, bool need_stats)
     return DPPIX_OK;
 }
 
-int grid_for(dppix_plan_t p, size_t lds)
+int grid_for(dppix_plan_t p, int layout, int C, int64_t tiles, size_t lds)
 {
     if (!p->persistent)
-        return (int)p->n_tiles;
+        return (int)tiles;
     int dev = 0, cus = 256, per_cu = 1;
     if (hipGetDevice(&dev) == hipSuccess) {
         hipDeviceProp_t prop;
         if (hipGetDeviceProperties(&prop, dev) == hipSuccess)
             cus = prop.multiProcessorCount;
     }
-    if (occupancy_forward(p->threads, lds, &per_cu) != hipSuccess || per_cu < 1)
+    if (occupancy_forward(layout, C, p->threads, lds, &per_cu) != hipSuccess || per_cu < 1)
         per_cu = 1;
-    const int64_t g = std::min<int64_t>((int64_t)cus * per_cu, p->n_tiles);
+    const int64_t g = std::min<int64_t>((int64_t)cus * per_cu, tiles);
     return (int)std::max<int64_t>(1, g);
+}
+
+// One launch per group: its scheduling range and its own ticket pair.
+template <typename Launch>
+hipError_t for_groups(dppix_plan_t p, const TileArgs& base, bool rec, Launch launch)
+{
+    for (size_t gi = 0; gi < p->groups.size(); ++gi) {
+        const LaunchGroup& g = p->groups[gi];
+        TileArgs a = base;
+        a.sched_offset = g.lo;
+        a.n_tiles = g.hi - g.lo;
+        a.ticket = base.ticket + 2 * gi;
+        const size_t lds = rec ? g.lds_rec : g.lds_fwd;
+        hipError_t e = launch(a, g, lds, grid_for(p, g.layout, g.C, a.n_tiles, lds));
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace
@@ -479,8 +520,10 @@ dppix_status_t dp_pix_forward(dppix_plan_t p, const void* const* images, const d
     a.store_flags = store->flags;
     a.clip_bg = clip_bg;
     a.clip_fg = clip_fg;
-    const size_t lds = std::max(p->lds[kFwdU8], p->lds[kFwdF32]);
-    hipError_t e = launch_forward(a, p->threads, lds, grid_for(p, lds), reinterpret_cast<hipStream_t>(stream));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = for_groups(p, a, false, [&](const TileArgs& ga, const LaunchGroup& g, size_t lds, int grid) {
+        return launch_forward(ga, g.layout, g.C, p->threads, lds, grid, s);
+    });
     if (e != hipSuccess)
         return dev_fail(e, "forward launch");
     return DPPIX_OK;
@@ -499,8 +542,10 @@ dppix_status_t dp_pix_reconstruct(dppix_plan_t p, const dppix_store_t* store, vo
     a.outs = out;
     a.bg = store->bg;
     a.fg = store->fg;
-    const size_t lds = std::max(p->lds[kRecU8], p->lds[kRecF32]);
-    hipError_t e = launch_reconstruct(a, p->threads, lds, grid_for(p, lds), reinterpret_cast<hipStream_t>(stream));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = for_groups(p, a, true, [&](const TileArgs& ga, const LaunchGroup& g, size_t lds, int grid) {
+        return launch_reconstruct(ga, g.layout, g.C, p->threads, lds, grid, s);
+    });
     if (e != hipSuccess)
         return dev_fail(e, "reconstruct launch");
     return DPPIX_OK;
@@ -531,7 +576,8 @@ dppix_status_t dp_pix_backward(dppix_plan_t p, const dppix_store_t* store, const
     a.g_bg = reinterpret_cast<float*>(sc);
     a.g_fg = reinterpret_cast<float*>(sc + align256(4 * p->bg_cap));
     a.cell_index = reinterpret_cast<uint32_t*>(sc + align256(4 * p->bg_cap) + align256(4 * p->fg_cap));
-    hipError_t e = launch_backward(a, p->threads, p->lds[kBwd], grid_for(p, p->lds[kBwd]), p->total_pixels,
+    hipError_t e = launch_backward(a, p->threads, p->lds[kBwd], grid_for(p, 1, 1, p->n_tiles, p->lds[kBwd]),
+                                   p->total_pixels,
                                    reinterpret_cast<hipStream_t>(stream));
     if (e != hipSuccess)
         return dev_fail(e, "backward launch");
@@ -557,8 +603,10 @@ dppix_status_t dp_pix_debug_sums(dppix_plan_t p, const void* const* images, cons
     a.store_flags = store->flags;
     a.dbg_coarse = coarse;
     a.dbg_fine = fine;
-    const size_t lds = p->lds[kFwdU8];
-    hipError_t e = launch_forward(a, p->threads, lds, grid_for(p, lds), reinterpret_cast<hipStream_t>(stream));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = for_groups(p, a, false, [&](const TileArgs& ga, const LaunchGroup& g, size_t lds, int grid) {
+        return launch_forward(ga, g.layout, g.C, p->threads, lds, grid, s);
+    });
     if (e != hipSuccess)
         return dev_fail(e, "forward launch");
     return DPPIX_OK;

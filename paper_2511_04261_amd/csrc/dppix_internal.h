@@ -16,7 +16,7 @@ namespace dppix {
 constexpr int kStrip = 16;             // bytes one lane moves per row (dwordx4)
 constexpr int kMaxThreads = 512;
 constexpr int kMaxB = 256;             // 255 * 256 rows fits a 16-bit lane sum
-constexpr int64_t kVgcBudget = 65536;  // LDS bytes for rounded subcell values
+constexpr int kTicketWords = 16;       // two per launch group (at most 5 groups)
 
 // One frame as the kernels see it (host computes everything derivable).
 struct FrameRec {
@@ -42,7 +42,7 @@ struct WsLayout {
     size_t tile_fg;       // uint32[n_tiles]: complex cells of the frame before the tile
     size_t frame_tot;     // uint64[n_frames][2]: n_bg, n_fg cells
     size_t frame_base;    // uint64[n_frames][2]: float offsets of the frame in bg, fg
-    size_t counters;      // uint32[8]: tickets of persistent launches
+    size_t counters;      // uint32[kTicketWords]: tickets of persistent launches, two per group
     size_t total;
 };
 
@@ -51,7 +51,8 @@ struct TileArgs {
     const int32_t* sched_frame;
     const int64_t* sched_base;
     int32_t n_frames;
-    int64_t n_tiles;
+    int64_t sched_offset;     // first scheduling index of this launch
+    int64_t n_tiles;          // tiles of this launch
     uint32_t* ticket;         // [0]: next tile, [1]: finished workgroups
     int32_t persistent;
     // per-frame pointer tables (device arrays of device pointers)
@@ -84,11 +85,12 @@ struct TileArgs {
 // Host-side launchers (defined in dppix_kernels.hip).
 hipError_t launch_classify(const TileArgs& a, int threads, size_t lds, hipStream_t s);
 hipError_t launch_scan(const TileArgs& a, uint64_t* counts_out, hipStream_t s);
-hipError_t launch_forward(const TileArgs& a, int threads, size_t lds, int grid, hipStream_t s);
-hipError_t launch_reconstruct(const TileArgs& a, int threads, size_t lds, int grid, hipStream_t s);
+hipError_t launch_forward(const TileArgs& a, int layout, int C, int threads, size_t lds, int grid, hipStream_t s);
+hipError_t launch_reconstruct(const TileArgs& a, int layout, int C, int threads, size_t lds, int grid,
+                              hipStream_t s);
 hipError_t launch_backward(const TileArgs& a, int threads, size_t lds, int grid, int64_t total_pixels,
                            hipStream_t s);
 hipError_t launch_philox(const uint32_t* in, uint32_t* out, int64_t n, hipStream_t s);
-hipError_t occupancy_forward(int threads, size_t lds, int* blocks_per_cu);
+hipError_t occupancy_forward(int layout, int C, int threads, size_t lds, int* blocks_per_cu);
 
 }  // namespace dppix

@@ -137,28 +137,31 @@ __device__ __forceinline__ void store_colsums(uint32_t* dst, const uint32_t (&e)
 }
 
 // Gather one 16-byte strip of a padded row byte by byte: columns past the
-// image fold back (mirror), bytes past the tile end read as zero.
+// image fold back (mirror), bytes past the tile end read as zero.  Only the
+// strips that cross the right edge or a misaligned row take this path.
 template <int C>
-__device__ __forceinline__ v4u gather_strip_u8(const uint8_t* row, int64_t p0, int64_t tile_end, int W, int pad)
+__device__ __noinline__ v4u gather_strip_u8(const uint8_t* row, int p0, int tile_end, int W, int pad)
 {
-    uint32_t w[4];
-#pragma unroll
-    for (int d = 0; d < 4; ++d) {
-        uint32_t v = 0;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int64_t p = p0 + 4 * d + e;
-            uint32_t byte = 0;
-            if (p < tile_end) {
-                const int x = (int)(p / C);
-                const int ch = (int)(p - (int64_t)x * C);
-                byte = row[(int64_t)fold(x, W, pad) * C + ch];
-            }
-            v |= byte << (8 * e);
+    uint64_t lo = 0, hi = 0;
+    int x = p0 / C;
+    int ch = p0 - x * C;
+    int sx = fold(x, W, pad);
+#pragma unroll 1
+    for (int q = 0; q < 16; ++q) {
+        if (p0 + q < tile_end) {
+            const uint64_t byte = row[sx * C + ch];
+            if (q < 8)
+                lo |= byte << (8 * q);
+            else
+                hi |= byte << (8 * (q - 8));
         }
-        w[d] = v;
+        if (++ch == C) {
+            ch = 0;
+            ++x;
+            sx = fold(x, W, pad);
+        }
     }
-    return v4u{w[0], w[1], w[2], w[3]};
+    return v4u{(uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32)};
 }
 
 // Cell classes and class-local indices of the tile's cells (wave 0):
@@ -206,7 +209,7 @@ __device__ __forceinline__ TileCoord tile_of(const TileArgs& a, int64_t sched_id
 {
     TileCoord tc;
     int64_t local;
-    locate(a, sched_idx, tc.f, local);
+    locate(a, a.sched_offset + sched_idx, tc.f, local);
     tc.f = (int)uniform_u32((uint32_t)tc.f);
     F = a.frames[tc.f];
     tc.t = F.tile_base + local;
@@ -253,7 +256,7 @@ __device__ void classify_tile(const TileArgs& a, const FrameRec& F, const TileCo
             if (fast)
                 w = __builtin_nontemporal_load(reinterpret_cast<const v4u*>(row + p0));
             else
-                w = gather_strip_u8<1>(row, p0, tile_end, W, F.pad);
+                w = gather_strip_u8<1>(row, (int)p0, (int)tile_end, W, F.pad);
             w.x = nz_bytes(w.x); w.y = nz_bytes(w.y); w.z = nz_bytes(w.z); w.w = nz_bytes(w.w);
             acc_bytes(w, e, o);
         }
@@ -372,7 +375,7 @@ __global__ __launch_bounds__(256) void k_scan_frames(TileArgs a, const uint64_t*
         carry_bg += tb;
         carry_fg += tf;
     }
-    if (threadIdx.x < 8)
+    if (threadIdx.x < kTicketWords)
         a.ticket[threadIdx.x] = 0;
 }
 
@@ -443,7 +446,7 @@ __device__ void forward_tile_u8(const TileArgs& a, const FrameRec& F, const Tile
             } else {
                 for (int k = 0; k < s; ++k) {
                     const uint8_t* rk = img + (int64_t)fold(row0 + k, H, pad) * pitch;
-                    acc_bytes(gather_strip_u8<C>(rk, p0, tile_end, W, pad), e, o);
+                    acc_bytes(gather_strip_u8<C>(rk, (int)p0, (int)tile_end, W, pad), e, o);
                 }
             }
             store_colsums(colsum + 16 * st, e, o);
@@ -667,22 +670,11 @@ __device__ void forward_tile_f32(const TileArgs& a, const FrameRec& F, const Til
     }
 }
 
-__device__ __forceinline__ void forward_tile(const TileArgs& a, const FrameRec& F, const TileCoord& tc, uint8_t* lds)
-{
-    if (F.layout == 1) {
-        forward_tile_f32(a, F, tc, lds);
-        return;
-    }
-    switch (F.C) {
-    case 1: forward_tile_u8<1>(a, F, tc, lds); break;
-    case 2: forward_tile_u8<2>(a, F, tc, lds); break;
-    case 3: forward_tile_u8<3>(a, F, tc, lds); break;
-    default: forward_tile_u8<4>(a, F, tc, lds); break;
-    }
-}
-
 // Persistent workgroups take tiles from an atomic ticket; the last one out
 // resets the ticket for the next launch (no memset, so graphs can replay).
+// Each launch covers one group of frames sharing layout and channel count
+// (scheduling indices [sched_offset, sched_offset + n_tiles)), so every kernel
+// instantiation carries only its own path.
 template <typename Body>
 __device__ __forceinline__ void run_tiles(const TileArgs& a, uint8_t* lds, Body body)
 {
@@ -715,10 +707,17 @@ __device__ __forceinline__ void run_tiles(const TileArgs& a, uint8_t* lds, Body 
     }
 }
 
-__global__ __launch_bounds__(kMaxThreads) void k_forward(TileArgs a)
+template <int C>
+__global__ __launch_bounds__(kMaxThreads) void k_forward_u8(TileArgs a)
 {
     extern __shared__ __align__(16) uint8_t lds[];
-    run_tiles(a, lds, [&](const FrameRec& F, const TileCoord& tc) { forward_tile(a, F, tc, lds); });
+    run_tiles(a, lds, [&](const FrameRec& F, const TileCoord& tc) { forward_tile_u8<C>(a, F, tc, lds); });
+}
+
+__global__ __launch_bounds__(kMaxThreads) void k_forward_f32(TileArgs a)
+{
+    extern __shared__ __align__(16) uint8_t lds[];
+    run_tiles(a, lds, [&](const FrameRec& F, const TileCoord& tc) { forward_tile_f32(a, F, tc, lds); });
 }
 
 // ==========================================================================
@@ -869,21 +868,17 @@ __device__ void reconstruct_tile_f32(const TileArgs& a, const FrameRec& F, const
     }
 }
 
-__global__ __launch_bounds__(kMaxThreads) void k_reconstruct(TileArgs a)
+template <int C>
+__global__ __launch_bounds__(kMaxThreads) void k_reconstruct_u8(TileArgs a)
 {
     extern __shared__ __align__(16) uint8_t lds[];
-    run_tiles(a, lds, [&](const FrameRec& F, const TileCoord& tc) {
-        if (F.layout == 1) {
-            reconstruct_tile_f32(a, F, tc, lds);
-            return;
-        }
-        switch (F.C) {
-        case 1: reconstruct_tile_u8<1>(a, F, tc, lds); break;
-        case 2: reconstruct_tile_u8<2>(a, F, tc, lds); break;
-        case 3: reconstruct_tile_u8<3>(a, F, tc, lds); break;
-        default: reconstruct_tile_u8<4>(a, F, tc, lds); break;
-        }
-    });
+    run_tiles(a, lds, [&](const FrameRec& F, const TileCoord& tc) { reconstruct_tile_u8<C>(a, F, tc, lds); });
+}
+
+__global__ __launch_bounds__(kMaxThreads) void k_reconstruct_f32(TileArgs a)
+{
+    extern __shared__ __align__(16) uint8_t lds[];
+    run_tiles(a, lds, [&](const FrameRec& F, const TileCoord& tc) { reconstruct_tile_f32(a, F, tc, lds); });
 }
 
 // ==========================================================================
@@ -1086,28 +1081,41 @@ hipError_t launch_scan(const TileArgs& a, uint64_t* counts_out, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_forward(const TileArgs& a, int threads, size_t lds, int grid, hipStream_t s)
+template <typename K>
+hipError_t launch_tiles(K kernel, const TileArgs& a, int threads, size_t lds, int grid, hipStream_t s)
 {
     if (a.n_tiles == 0)
         return hipSuccess;
-    hipError_t e = allow_lds(k_forward, lds);
+    hipError_t e = allow_lds(kernel, lds);
     if (e != hipSuccess)
         return e;
     const unsigned g = a.persistent ? (unsigned)grid : (unsigned)a.n_tiles;
-    hipLaunchKernelGGL(k_forward, dim3(g), dim3(threads), lds, s, a);
+    hipLaunchKernelGGL(kernel, dim3(g), dim3(threads), lds, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_reconstruct(const TileArgs& a, int threads, size_t lds, int grid, hipStream_t s)
+hipError_t launch_forward(const TileArgs& a, int layout, int C, int threads, size_t lds, int grid, hipStream_t s)
 {
-    if (a.n_tiles == 0)
-        return hipSuccess;
-    hipError_t e = allow_lds(k_reconstruct, lds);
-    if (e != hipSuccess)
-        return e;
-    const unsigned g = a.persistent ? (unsigned)grid : (unsigned)a.n_tiles;
-    hipLaunchKernelGGL(k_reconstruct, dim3(g), dim3(threads), lds, s, a);
-    return hipGetLastError();
+    if (layout == 1)
+        return launch_tiles(k_forward_f32, a, threads, lds, grid, s);
+    switch (C) {
+    case 1: return launch_tiles(k_forward_u8<1>, a, threads, lds, grid, s);
+    case 2: return launch_tiles(k_forward_u8<2>, a, threads, lds, grid, s);
+    case 3: return launch_tiles(k_forward_u8<3>, a, threads, lds, grid, s);
+    default: return launch_tiles(k_forward_u8<4>, a, threads, lds, grid, s);
+    }
+}
+
+hipError_t launch_reconstruct(const TileArgs& a, int layout, int C, int threads, size_t lds, int grid, hipStream_t s)
+{
+    if (layout == 1)
+        return launch_tiles(k_reconstruct_f32, a, threads, lds, grid, s);
+    switch (C) {
+    case 1: return launch_tiles(k_reconstruct_u8<1>, a, threads, lds, grid, s);
+    case 2: return launch_tiles(k_reconstruct_u8<2>, a, threads, lds, grid, s);
+    case 3: return launch_tiles(k_reconstruct_u8<3>, a, threads, lds, grid, s);
+    default: return launch_tiles(k_reconstruct_u8<4>, a, threads, lds, grid, s);
+    }
 }
 
 hipError_t launch_backward(const TileArgs& a, int threads, size_t lds, int grid, int64_t, hipStream_t s)
@@ -1134,9 +1142,20 @@ hipError_t launch_philox(const uint32_t* in, uint32_t* out, int64_t n, hipStream
     return hipGetLastError();
 }
 
-hipError_t occupancy_forward(int threads, size_t lds, int* blocks_per_cu)
+hipError_t occupancy_forward(int layout, int C, int threads, size_t lds, int* blocks_per_cu)
 {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_forward, threads, lds);
+    const void* k;
+    if (layout == 1)
+        k = reinterpret_cast<const void*>(k_forward_f32);
+    else if (C == 1)
+        k = reinterpret_cast<const void*>(k_forward_u8<1>);
+    else if (C == 2)
+        k = reinterpret_cast<const void*>(k_forward_u8<2>);
+    else if (C == 3)
+        k = reinterpret_cast<const void*>(k_forward_u8<3>);
+    else
+        k = reinterpret_cast<const void*>(k_forward_u8<4>);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, threads, lds);
 }
 
 }  // namespace dppix

@@ -1,0 +1,205 @@
+"""GPU tests of batching, graphs, tuning, the autograd layer and serving,
+each against the oracle or against the plain eager path (bitwise)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from tests.helpers import compare_frame, oracle_params, chw_to_hwc
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+dp = pytest.importorskip("paper_2511_04261_amd")
+from paper_2511_04261_amd import synth  # noqa: E402
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _store_equal(a, b):
+    return all(np.array_equal(a[k], b[k]) for k in ("flags", "bg", "fg")) and tuple(a["counts"]) == tuple(b["counts"])
+
+
+def test_graph_replays_match_eager(dev):
+    """Replay several times with eager work and new frame contents between
+    replays; every replay equals the eager plan + forward on the same data."""
+    say("case: graph replay")
+    specs = synth.region_batch(6, height=270, width=480)
+    frames = [dp.FrameParams.from_spec(s) for s in specs]
+    plan = dp.Plan(frames, device=dev, persistent=True)
+    imgs = [s.image_torch(dev) for s in specs]
+    masks = [s.mask_torch(dev) for s in specs]
+    outs = [torch.empty_like(t) for t in imgs]
+    g = plan.graph(masks, imgs, outs)
+    ref = dp.Plan(frames, device=dev, persistent=False)
+    rng = np.random.Generator(np.random.PCG64(77))
+    for rep in range(4):
+        if rep:
+            for t, m in zip(imgs, masks):     # new contents, same buffers (eager torch work in between)
+                t.copy_(torch.randint(0, 256, t.shape, dtype=torch.uint8, device=dev))
+                m.copy_(synth.paint_mask_torch(synth.draw_rects(rng, 270, 480), 270, 480, dev))
+        g.launch()
+        torch.cuda.synchronize()
+        got = plan.store_host()
+        got_out = [o.cpu().numpy() for o in outs]
+        ro = [torch.empty_like(t) for t in imgs]
+        ref.plan(masks)
+        ref.forward(imgs, out=ro)
+        torch.cuda.synchronize()
+        want = ref.store_host()
+        for i in range(len(frames)):
+            assert _store_equal(got[i], want[i]), (rep, i)
+            assert np.array_equal(got_out[i], ro[i].cpu().numpy()), (rep, i)
+    g.close()
+
+
+def test_autotuned_shapes_are_bitwise_identical(dev, tmp_path):
+    say("case: autotune")
+    from paper_2511_04261_amd.autotune import Autotuner
+    specs = synth.region_batch(3, height=300, width=500)
+    frames = [dp.FrameParams.from_spec(s) for s in specs]
+    tuner = Autotuner(dev, cache_path=str(tmp_path / "cache.json"), min_pixels=2e6, reps=2)
+    tuned, launch = tuner.tune_batch(frames)
+    assert (tmp_path / "cache.json").exists()
+    imgs = [s.image_torch(dev) for s in specs]
+    masks = [s.mask_torch(dev) for s in specs]
+    a = dp.Plan(frames, device=dev)
+    b = dp.Plan(tuned, device=dev, **launch)
+    oa = [torch.empty_like(t) for t in imgs]
+    ob = [torch.empty_like(t) for t in imgs]
+    for p, o in ((a, oa), (b, ob)):
+        p.plan(masks)
+        p.forward(imgs, out=o)
+    torch.cuda.synchronize()
+    for x, y in zip(a.store_host(), b.store_host()):
+        assert _store_equal(x, y)
+    for x, y in zip(oa, ob):
+        assert torch.equal(x, y)
+
+
+def test_uneven_batch_full_size_sampled(dev):
+    """256 frames of 768x576 .. 6000x4000, per-frame grids and budgets, one
+    persistent graph-replayed launch; one frame of each resolution checked
+    in full against the oracle, all frames for store invariants."""
+    say("case: uneven 256-frame batch")
+    specs = synth.uneven_batch(256)
+    frames = [dp.FrameParams.from_spec(s) for s in specs]
+    plan = dp.Plan(frames, device=dev, persistent=True)
+    imgs = [s.image_torch(dev) for s in specs]
+    masks = [s.mask_torch(dev) for s in specs]
+    outs = [torch.empty_like(t) for t in imgs]
+    g = plan.graph(masks, imgs, outs)
+    g.launch()
+    g.launch()
+    torch.cuda.synchronize()
+    store = plan.store_host()
+    ob = of = 0
+    for i, (fp, fi, st) in enumerate(zip(frames, plan.info, store)):
+        nb, nf = st["counts"]
+        assert nb + nf == fi.grid_rows * fi.grid_cols and nf == int(st["flags"].sum())
+        assert st["offsets"] == (ob, of)
+        ob += nb * 3
+        of += nf * fi.n * fi.n * 3
+    seen = set()
+    for i, s in enumerate(specs):
+        if (s.height, s.width) in seen:
+            continue
+        seen.add((s.height, s.width))
+        say("  oracle on frame", i, s.height, s.width, s.b, s.sb)
+        img = imgs[i].cpu().numpy()
+        want = oracle.forward(img, s.mask, oracle_params(frames[i]))
+        compare_frame(store[i], want, outs[i].cpu().numpy(), "frame %d" % i)
+        s.drop_host()
+    g.close()
+
+
+def test_autograd_layer_matches_oracle(dev):
+    """DPPixFn through the autograd engine: y and dL/dx against the oracle for
+    3x64x64 crops (no padding) and 3x61x57 (mirror multiplicity)."""
+    for (H, W) in [(64, 64), (61, 57)]:
+        say("case: autograd", H, W)
+        r = np.random.Generator(np.random.PCG64(H))
+        x = synth.uniform_f32(r, (2, 3, H, W))
+        masks = [synth.rect_mask(r, H, W, n_rects=2, rect_frac=0.1, cover=(0.05, 0.5)) for _ in range(2)]
+        w = r.standard_normal((2, 3, H, W)).astype(np.float32)
+        layer = dp.DPPixLayer(b=16, sb=8, m=8, eps_bg=1.0, eps_fg=0.5, tau=1, seed=3)
+        tx = torch.from_numpy(x).to(dev).requires_grad_(True)
+        tm = [torch.from_numpy(m).to(dev) for m in masks]
+        y = layer(tx, tm)
+        (y * torch.from_numpy(w).to(dev)).sum().backward()
+        for i in range(2):
+            fp = dp.FrameParams(H, W, 3, dp.F32_CHW, b=16, sb=8, m=8, eps_bg=1.0, eps_fg=0.5, tau=1, seed=3,
+                                frame_index=i)
+            p = oracle_params(fp)
+            want = oracle.forward(chw_to_hwc(x[i]), masks[i], p)
+            assert np.abs(chw_to_hwc(y[i].detach().cpu().numpy()) - want["recon_f32"]).max() <= 1e-3
+            gw = oracle.backward(chw_to_hwc(x[i]).astype(np.float64), masks[i], chw_to_hwc(w[i]).astype(np.float64), p)
+            got = chw_to_hwc(tx.grad[i].cpu().numpy())
+            assert np.abs(got - gw).max() <= 1e-5
+
+
+def test_autograd_full_batch_and_fd(dev):
+    """32x3x512x512 fp32, b_fg=8 / b_bg=16, m=8, eps 0.5 / 1.0: forward and
+    backward on the GPU; two images against the oracle gradient; central
+    differences of the GPU forward (piecewise linear, h=0.5) at sampled pixels."""
+    say("case: autograd 32x3x512x512")
+    x, masks, w = synth.autograd_batch()
+    layer = dp.DPPixLayer(b=16, sb=8, m=8, eps_bg=1.0, eps_fg=0.5, tau=1, seed=5)
+    tx = torch.from_numpy(x).to(dev).requires_grad_(True)
+    tm = [torch.from_numpy(m).to(dev) for m in masks]
+    tw = torch.from_numpy(w).to(dev)
+    y = layer(tx, tm)
+    (y * tw).sum().backward()
+    torch.cuda.synchronize()
+    for i in (0, 31):
+        fp = dp.FrameParams(512, 512, 3, dp.F32_CHW, b=16, sb=8, m=8, eps_bg=1.0, eps_fg=0.5, tau=1, seed=5,
+                            frame_index=i)
+        gw = oracle.backward(chw_to_hwc(x[i]).astype(np.float64), masks[i], chw_to_hwc(w[i]).astype(np.float64),
+                             oracle_params(fp))
+        assert np.abs(chw_to_hwc(tx.grad[i].cpu().numpy()) - gw).max() <= 1e-5
+    r = np.random.Generator(np.random.PCG64(8))
+    h = 0.5
+    with torch.no_grad():
+        for _ in range(6):
+            i, c, yy, xx = int(r.integers(0, 32)), int(r.integers(0, 3)), int(r.integers(0, 512)), int(r.integers(0, 512))
+            xp = tx.detach().clone()
+            xp[i, c, yy, xx] += h
+            xm = tx.detach().clone()
+            xm[i, c, yy, xx] -= h
+            fd = ((layer(xp, tm) * tw).sum(dtype=torch.float64) - (layer(xm, tm) * tw).sum(dtype=torch.float64)) / (2 * h)
+            assert abs(fd.item() - tx.grad[i, c, yy, xx].item()) <= 2e-3 + 1e-3 * abs(tx.grad[i, c, yy, xx].item())
+
+
+def test_serving_alone_equals_mix(dev):
+    """Frames served from 16 mixed-resolution streams (continuous batching,
+    memory admission) give the same store bit for bit as each frame alone."""
+    say("case: serving alone vs mix")
+    from paper_2511_04261_amd.serving import GpuBackend, MemoryLedger, Scheduler, camera_streams, serve_streams
+    streams = camera_streams(duration_s=1.5, pool=3, device=dev)
+    params = dict(b=32, sb=8, m=16, eps_bg=1.0, eps_fg=0.3, tau=1)
+    be = GpuBackend(dev)
+    sch = Scheduler(be, MemoryLedger(4 << 30), max_batch=64, max_inflight=2)
+    done = serve_streams(streams, sch, params, keep_results=True)
+    assert not sch.rejected and len(done) > 100
+    assert max(sch.batch_sizes) > 1
+    r = np.random.Generator(np.random.PCG64(5))
+    for k in r.choice(len(done), size=12, replace=False):
+        q = done[int(k)]
+        fp = be.frame_params(q)
+        plan = dp.Plan([fp], device=dev)
+        plan.plan([q.mask.to(dev)])
+        plan.forward([q.image.to(dev)])
+        torch.cuda.synchronize()
+        alone = plan.store_host()[0]
+        assert _store_equal(q.result, alone), (q.rid, q.stream, q.frame_index)
