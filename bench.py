@@ -157,6 +157,54 @@ def run_per_frame(frames_s, dev, warmup, steps):
     return dict(seconds=dt, step_ms=1e3 * dt / steps, pixels=px, bytes=b)
 
 
+SERVE_PARAMS = dict(b=32, sb=8, m=16, eps_bg=1.0, eps_fg=0.3, tau=1)
+
+
+def run_serving(dev, seconds, cap_bytes=8 << 30):
+    """16 camera streams (8 x 1080p, 6 x 768x576, 2 x 2160p), Poisson 30 Hz
+    each, replayed in real time through the continuous-batching server."""
+    from paper_2511_04261_amd.serving import (GpuBackend, MemoryLedger, Scheduler, camera_streams, latency_stats,
+                                              serve_streams)
+    be = GpuBackend(dev)
+    warm = camera_streams(duration_s=1.0, pool=2, device=dev, seed=999)
+    serve_streams(warm, Scheduler(be, MemoryLedger(cap_bytes)), SERVE_PARAMS)
+    streams = camera_streams(duration_s=seconds, pool=8, device=dev)
+    sch = Scheduler(be, MemoryLedger(cap_bytes), max_batch=64, max_inflight=2)
+    t0 = time.perf_counter()
+    done = serve_streams(streams, sch, SERVE_PARAMS)
+    wall = time.perf_counter() - t0
+    st = latency_stats(done)
+    ok = [r for r in done if r.error is None]
+    px = sum(r.height * r.width for r in ok)
+    return dict(p50_ms=round(st.get("p50_ms", float("nan")), 3), p99_ms=round(st.get("p99_ms", float("nan")), 3),
+                max_ms=round(st.get("max_ms", float("nan")), 3), frames=len(ok), rejected=len(sch.rejected),
+                megapixels_per_s=round(px / wall / 1e6, 1), seconds=round(wall, 2), streams=len(streams),
+                batches=sch.batches, mean_batch=round(sum(sch.batch_sizes) / max(1, len(sch.batch_sizes)), 2),
+                peak_admitted_bytes=sch.ledger.peak)
+
+
+def counters_run(frames_s, dev, launches=3, copy_bytes=1 << 30):
+    """Short run for rocprofv3 --pmc: one plain device copy of known size
+    (the calibration of FETCH_SIZE / WRITE_SIZE), then a few plan + forward
+    launches of the headline workload."""
+    import torch
+    src = torch.empty(copy_bytes, dtype=torch.uint8, device=dev).fill_(1)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    plan, imgs, masks, outs = build_batch(frames_s, dev, persistent=True)
+    for _ in range(launches):
+        plan.plan(masks)
+        plan.forward(imgs, out=outs)
+    torch.cuda.synchronize()
+    ab = alg_bytes(plan)
+    log("counters run: copy %d bytes; forward alg bytes %d per launch" % (copy_bytes, ab["forward"]))
+    print(json.dumps({"copy_bytes": copy_bytes, "forward_alg_bytes": ab["forward"],
+                      "kernel_source_sha256_16": kernel_source_hash()}), flush=True)
+
+
 def cpu_baseline(frames_s, budget_s=15.0, dev=None):
     """The oracle as it stands, single-threaded, on a bounded sample of the
     same workload: whole frames until about budget_s of CPU work."""
@@ -192,6 +240,9 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-extra", action="store_true", help="only the headline workload")
     ap.add_argument("--threads", type=int, default=0)
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="seconds of camera-stream arrivals for the latency leg (0 skips it)")
+    ap.add_argument("--counters", action="store_true", help="short run for rocprofv3 --pmc")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the method shards by frame with no collective, "
@@ -203,6 +254,9 @@ def main():
     dev = torch.device("cuda:0")
     log("bench: generating %d RGB 1080p frames" % args.frames)
     frames_s = synth.region_batch(args.frames)
+    if args.counters:
+        counters_run(frames_s, dev)
+        return
 
     log("bench: batched region-adaptive 1080p")
     res = run_batched(frames_s, dev, args.warmup, args.steps, graph=True, threads=args.threads)
@@ -257,6 +311,12 @@ def main():
                                "step_frac_hbm": round(u_gbs / HBM_PEAK_GBS, 4),
                                "forward_frac_hbm": round(uf_gbs / HBM_PEAK_GBS, 4)}
         del ur, ub
+        torch.cuda.empty_cache()
+    if args.serve_seconds > 0 and not args.skip_extra:
+        log("bench: serving %.0f s of 16 camera streams" % args.serve_seconds)
+        out["serving"] = run_serving(dev, args.serve_seconds)
+        out["p50_ms"] = out["serving"]["p50_ms"]
+        out["p99_ms"] = out["serving"]["p99_ms"]
         torch.cuda.empty_cache()
     if not args.skip_cpu:
         log("bench: CPU oracle sample")

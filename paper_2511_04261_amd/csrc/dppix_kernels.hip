@@ -96,6 +96,15 @@ __device__ __forceinline__ int fold(int x, int L, int mode)
 
 __device__ __forceinline__ uint32_t uniform_u32(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Workgroup barrier for LDS hand-offs only.  The tile kernels never read
+// global memory written by their own workgroup, so outstanding global stores
+// (the reconstruction, the store) need not drain at every barrier, which a
+// full __syncthreads() would force.
+__device__ __forceinline__ void lds_barrier()
+{
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 // Scheduling index -> (frame, tile within frame).  sched_base holds the first
 // scheduling index of each frame in scheduling order.
 __device__ __forceinline__ void locate(const TileArgs& a, int64_t idx, int& f, int64_t& local)
@@ -262,7 +271,7 @@ __device__ void classify_tile(const TileArgs& a, const FrameRec& F, const TileCo
         }
         store_colsums(colcnt + 16 * st, e, o);
     }
-    __syncthreads();
+    lds_barrier();
     for (int kc = tid; kc < Kt; kc += NT) {
         uint32_t cnt = 0;
         for (int x = 0; x < b; ++x)
@@ -272,7 +281,7 @@ __device__ void classify_tile(const TileArgs& a, const FrameRec& F, const TileCo
         if (fl)
             atomicAdd(&s_count, 1u);
     }
-    __syncthreads();
+    lds_barrier();
     if (tid == 0)
         a.tile_cnt[tc.t] = s_count;
 }
@@ -415,7 +424,7 @@ __device__ void forward_tile_u8(const TileArgs& a, const FrameRec& F, const Tile
     const uint64_t fg_base = a.frame_base[2 * tc.f + 1];
     const int items = Kt * n * C;
     const int nn = n * n;
-    __syncthreads();
+    lds_barrier();
 
     // ---- subgrid rows: exact column sums, then subcell sums ----
     for (int fr = 0; fr < n; ++fr) {
@@ -451,7 +460,7 @@ __device__ void forward_tile_u8(const TileArgs& a, const FrameRec& F, const Tile
             }
             store_colsums(colsum + 16 * st, e, o);
         }
-        __syncthreads();
+        lds_barrier();
         for (int j = tid; j < items; j += NT) {
             const int fc = j / C, ch = j - fc * C;
             const uint32_t* cp = colsum + fc * s * C + ch;
@@ -473,7 +482,7 @@ __device__ void forward_tile_u8(const TileArgs& a, const FrameRec& F, const Tile
                 vgc[(fr * Kt * n + fc) * C + ch] = to_u8(v);
             }
         }
-        __syncthreads();
+        lds_barrier();
     }
 
     // ---- simple cells: coarse sum = total of the n*n subcell sums ----
@@ -497,32 +506,36 @@ __device__ void forward_tile_u8(const TileArgs& a, const FrameRec& F, const Tile
     }
     if (out == nullptr)
         return;
-    __syncthreads();
+    lds_barrier();
 
     // ---- fused reconstruction of the band's real pixels ----
+    // The expanded row alternates between two LDS buffers, so one barrier per
+    // subgrid row suffices: a buffer is rewritten two rows later, after every
+    // lane has passed the barrier that follows its last read.
     const bool out_aligned = ((reinterpret_cast<uintptr_t>(out) | (uintptr_t)pitch | (uintptr_t)X0) & 15) == 0;
     for (int fr = 0; fr < n; ++fr) {
+        uint8_t* exb = ex + (fr & 1) * (16 * nstr);
         for (int j = tid; j < items; j += NT) {
             const int fc = j / C, ch = j - fc * C;
             const int kc = fc / n;
             const uint8_t v = cflag[kc] ? vgc[(fr * Kt * n + fc) * C + ch] : vgs[kc * C + ch];
-            uint8_t* e = ex + fc * s * C + ch;
+            uint8_t* e = exb + fc * s * C + ch;
             for (int x = 0; x < s; ++x)
                 e[x * C] = v;
         }
-        __syncthreads();
+        lds_barrier();
         const int row0 = r * b + fr * s;
         const int rows = min(s, H - row0);
         for (int st = tid; st < nstr; st += NT) {
             const int64_t p0 = X0 + 16 * st;
             if (p0 >= lim)
                 continue;
-            const v4u v = *reinterpret_cast<const v4u*>(ex + 16 * st);
+            const v4u v = *reinterpret_cast<const v4u*>(exb + 16 * st);
             if (out_aligned && p0 + 16 <= lim) {
                 for (int k = 0; k < rows; ++k)
                     __builtin_nontemporal_store(v, reinterpret_cast<v4u*>(out + (int64_t)(row0 + k) * pitch + p0));
             } else {
-                const uint8_t* vb = ex + 16 * st;
+                const uint8_t* vb = exb + 16 * st;
                 for (int k = 0; k < rows; ++k) {
                     uint8_t* op = out + (int64_t)(row0 + k) * pitch;
                     for (int q = 0; q < 16 && p0 + q < lim; ++q)
@@ -530,7 +543,6 @@ __device__ void forward_tile_u8(const TileArgs& a, const FrameRec& F, const Tile
                 }
             }
         }
-        __syncthreads();
     }
 }
 
@@ -569,7 +581,7 @@ __device__ void forward_tile_f32(const TileArgs& a, const FrameRec& F, const Til
     const uint64_t fg_base = a.frame_base[2 * tc.f + 1];
     const int nn = n * n;
     const int kn = Kt * n;
-    __syncthreads();
+    lds_barrier();
 
     for (int ch = 0; ch < C; ++ch) {
         const float* pl = img + plane * ch;
@@ -595,7 +607,7 @@ __device__ void forward_tile_f32(const TileArgs& a, const FrameRec& F, const Til
                 }
                 reinterpret_cast<v4f*>(colsum)[st] = acc;
             }
-            __syncthreads();
+            lds_barrier();
             for (int fc = tid; fc < kn; fc += NT) {
                 double S = 0.0;
                 for (int x = 0; x < s; ++x)
@@ -614,7 +626,7 @@ __device__ void forward_tile_f32(const TileArgs& a, const FrameRec& F, const Til
                     vgc[(fr * kn + fc) * C + ch] = v;
                 }
             }
-            __syncthreads();
+            lds_barrier();
         }
     }
     for (int j = tid; j < Kt * C; j += NT) {
@@ -635,19 +647,19 @@ __device__ void forward_tile_f32(const TileArgs& a, const FrameRec& F, const Til
     }
     if (out == nullptr)
         return;
-    __syncthreads();
+    lds_barrier();
     const bool out_aligned = ((reinterpret_cast<uintptr_t>(out) | (uintptr_t)(pitch * 4) | (uintptr_t)(X0 * 4)) & 15) == 0;
-    float* exf = colsum;
     for (int ch = 0; ch < C; ++ch) {
         float* pl = out + plane * ch;
         for (int fr = 0; fr < n; ++fr) {
+            float* exf = colsum + ((ch * n + fr) & 1) * (4 * nstr);   // two alternating row buffers
             for (int fc = tid; fc < kn; fc += NT) {
                 const int kc = fc / n;
                 const float v = cflag[kc] ? vgc[(fr * kn + fc) * C + ch] : vgs[kc * C + ch];
                 for (int x = 0; x < s; ++x)
                     exf[fc * s + x] = v;
             }
-            __syncthreads();
+            lds_barrier();
             const int row0 = r * b + fr * s;
             const int rows = min(s, H - row0);
             for (int st = tid; st < nstr; st += NT) {
@@ -665,7 +677,6 @@ __device__ void forward_tile_f32(const TileArgs& a, const FrameRec& F, const Til
                             pl[(int64_t)(row0 + k) * pitch + p0 + q] = vv[q];
                 }
             }
-            __syncthreads();
         }
     }
 }
@@ -688,14 +699,14 @@ __device__ __forceinline__ void run_tiles(const TileArgs& a, uint8_t* lds, Body 
     for (;;) {
         if (threadIdx.x == 0)
             s_next = (int64_t)atomicAdd(&a.ticket[0], 1u);
-        __syncthreads();
+        lds_barrier();
         const int64_t idx = s_next;
         if (idx >= a.n_tiles)
             break;
         FrameRec F;
         const TileCoord tc = tile_of(a, idx, F);
         body(F, tc);
-        __syncthreads();
+        lds_barrier();
     }
     if (threadIdx.x == 0) {
         __threadfence();
@@ -747,7 +758,7 @@ __device__ void reconstruct_tile_u8(const TileArgs& a, const FrameRec& F, const 
     const uint64_t bg_base = a.frame_base[2 * tc.f + 0];
     const uint64_t fg_base = a.frame_base[2 * tc.f + 1];
     const int nn = n * n, kn = Kt * n, items = Kt * n * C;
-    __syncthreads();
+    lds_barrier();
     for (int j = tid; j < Kt * C; j += NT) {
         const int kc = j / C, ch = j - kc * C;
         if (!cflag[kc])
@@ -762,30 +773,31 @@ __device__ void reconstruct_tile_u8(const TileArgs& a, const FrameRec& F, const 
         if (cflag[kc])
             vgc[j] = to_u8(a.fg[fg_base + ((uint64_t)cidx[kc] * nn + fr * n + jj) * C + ch]);
     }
-    __syncthreads();
+    lds_barrier();
     const bool out_aligned = ((reinterpret_cast<uintptr_t>(out) | (uintptr_t)pitch | (uintptr_t)X0) & 15) == 0;
     for (int fr = 0; fr < n; ++fr) {
+        uint8_t* exb = ex + (fr & 1) * (16 * nstr);   // two alternating row buffers
         for (int j = tid; j < items; j += NT) {
             const int fc = j / C, ch = j - fc * C;
             const int kc = fc / n;
             const uint8_t v = cflag[kc] ? vgc[(fr * kn + fc) * C + ch] : vgs[kc * C + ch];
-            uint8_t* e = ex + fc * s * C + ch;
+            uint8_t* e = exb + fc * s * C + ch;
             for (int x = 0; x < s; ++x)
                 e[x * C] = v;
         }
-        __syncthreads();
+        lds_barrier();
         const int row0 = r * b + fr * s;
         const int rows = min(s, H - row0);
         for (int st = tid; st < nstr; st += NT) {
             const int64_t p0 = X0 + 16 * st;
             if (p0 >= lim)
                 continue;
-            const v4u v = *reinterpret_cast<const v4u*>(ex + 16 * st);
+            const v4u v = *reinterpret_cast<const v4u*>(exb + 16 * st);
             if (out_aligned && p0 + 16 <= lim) {
                 for (int k = 0; k < rows; ++k)
                     __builtin_nontemporal_store(v, reinterpret_cast<v4u*>(out + (int64_t)(row0 + k) * pitch + p0));
             } else {
-                const uint8_t* vb = ex + 16 * st;
+                const uint8_t* vb = exb + 16 * st;
                 for (int k = 0; k < rows; ++k) {
                     uint8_t* op = out + (int64_t)(row0 + k) * pitch;
                     for (int q = 0; q < 16 && p0 + q < lim; ++q)
@@ -793,7 +805,6 @@ __device__ void reconstruct_tile_u8(const TileArgs& a, const FrameRec& F, const 
                 }
             }
         }
-        __syncthreads();
     }
 }
 
@@ -811,7 +822,7 @@ __device__ void reconstruct_tile_f32(const TileArgs& a, const FrameRec& F, const
     const int64_t pitch = F.pitch, plane = pitch * H;
     float* out = static_cast<float*>(a.outs[tc.f]);
     const LdsPlan L = lds_plan(kRecF32, F.K, b, n, C);
-    float* exf = reinterpret_cast<float*>(lds + L.colsum);
+    float* exbase = reinterpret_cast<float*>(lds + L.colsum);
     uint32_t* cidx = reinterpret_cast<uint32_t*>(lds + L.cidx);
     uint8_t* cflag = lds + L.cflag;
     float* vgs = reinterpret_cast<float*>(lds + L.vgs);
@@ -820,7 +831,7 @@ __device__ void reconstruct_tile_f32(const TileArgs& a, const FrameRec& F, const
     const uint64_t bg_base = a.frame_base[2 * tc.f + 0];
     const uint64_t fg_base = a.frame_base[2 * tc.f + 1];
     const int nn = n * n, kn = Kt * n;
-    __syncthreads();
+    lds_barrier();
     for (int j = tid; j < Kt * C; j += NT) {
         const int kc = j / C, ch = j - kc * C;
         if (!cflag[kc])
@@ -834,18 +845,19 @@ __device__ void reconstruct_tile_f32(const TileArgs& a, const FrameRec& F, const
         if (cflag[kc])
             vgc[j] = a.fg[fg_base + ((uint64_t)cidx[kc] * nn + fr * n + jj) * C + ch];
     }
-    __syncthreads();
+    lds_barrier();
     const bool out_aligned = ((reinterpret_cast<uintptr_t>(out) | (uintptr_t)(pitch * 4) | (uintptr_t)(X0 * 4)) & 15) == 0;
     for (int ch = 0; ch < C; ++ch) {
         float* pl = out + plane * ch;
         for (int fr = 0; fr < n; ++fr) {
+            float* exf = exbase + ((ch * n + fr) & 1) * (4 * nstr);   // two alternating row buffers
             for (int fc = tid; fc < kn; fc += NT) {
                 const int kc = fc / n;
                 const float v = cflag[kc] ? vgc[(fr * kn + fc) * C + ch] : vgs[kc * C + ch];
                 for (int x = 0; x < s; ++x)
                     exf[fc * s + x] = v;
             }
-            __syncthreads();
+            lds_barrier();
             const int row0 = r * b + fr * s;
             const int rows = min(s, H - row0);
             for (int st = tid; st < nstr; st += NT) {
@@ -863,7 +875,6 @@ __device__ void reconstruct_tile_f32(const TileArgs& a, const FrameRec& F, const
                             pl[(int64_t)(row0 + k) * pitch + p0 + q] = vv[q];
                 }
             }
-            __syncthreads();
         }
     }
 }
@@ -909,7 +920,7 @@ __device__ void backward_reduce_tile(const TileArgs& a, const FrameRec& F, const
     const uint64_t bg_base = a.frame_base[2 * tc.f + 0];
     const uint64_t fg_base = a.frame_base[2 * tc.f + 1];
     const int nn = n * n, kn = Kt * n;
-    __syncthreads();
+    lds_barrier();
     for (int ch = 0; ch < C; ++ch) {
         const float* pl = go + plane * ch;
         for (int fr = 0; fr < n; ++fr) {
@@ -933,7 +944,7 @@ __device__ void backward_reduce_tile(const TileArgs& a, const FrameRec& F, const
                 }
                 reinterpret_cast<v4f*>(colsum)[st] = acc;
             }
-            __syncthreads();
+            lds_barrier();
             for (int fc = tid; fc < kn; fc += NT) {
                 double G = 0.0;
                 for (int x = 0; x < s; ++x)
@@ -946,7 +957,7 @@ __device__ void backward_reduce_tile(const TileArgs& a, const FrameRec& F, const
                     a.g_fg[at] = a.clip_fg[at] ? (float)(G / (double)(s * s)) : 0.f;
                 }
             }
-            __syncthreads();
+            lds_barrier();
         }
     }
     for (int j = tid; j < Kt * C; j += NT) {

@@ -44,11 +44,15 @@ __host__ __device__ inline LdsPlan lds_plan(int kind, int K, int b, int n, int C
     const uint32_t nstr = tile_strips(kind, K, b, C);
     uint32_t o = 0;
     p.colsum = o;
-    // u8 column sums are 32-bit per byte column; f32 sums are one float per column
+    // u8 column sums are 32-bit per byte column (the u8 forward reuses them as
+    // two expanded output rows); reconstruction and f32 forward keep two
+    // expanded output rows; the adjoint one row of float column sums
     if (kind == kClassify || kind == kFwdU8)
         o += al16(64u * nstr);
-    else
+    else if (kind == kBwd)
         o += al16(16u * nstr);
+    else
+        o += al16(32u * nstr);
     p.cspart = o;
     if (kind == kFwdU8)
         o += al16(4u * (uint32_t)(K * n * C));
