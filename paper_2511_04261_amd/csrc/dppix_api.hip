@@ -64,6 +64,7 @@ struct dppix_plan {
     bool any_f32 = false, any_u8 = false;
     int threads = kDefaultThreads;
     int persistent = 0;
+    int cus = 0;                        // compute units of the device (queried once)
     uint8_t* bound = nullptr;
     size_t bound_bytes = 0;
     std::vector<uint8_t> host_tables;   // frames + sched tables as uploaded
@@ -448,12 +449,16 @@ int grid_for(dppix_plan_t p, int layout, int C, int64_t tiles, size_t lds)
 {
     if (!p->persistent)
         return (int)tiles;
-    int dev = 0, cus = 256, per_cu = 1;
-    if (hipGetDevice(&dev) == hipSuccess) {
-        hipDeviceProp_t prop;
-        if (hipGetDeviceProperties(&prop, dev) == hipSuccess)
-            cus = prop.multiProcessorCount;
+    if (p->cus == 0) {
+        int dev = 0, n = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+            p->cus = n;
+        else
+            p->cus = 256;
     }
+    const int cus = p->cus;
+    int per_cu = 1;
     if (occupancy_forward(layout, C, p->threads, lds, &per_cu) != hipSuccess || per_cu < 1)
         per_cu = 1;
     const int64_t g = std::min<int64_t>((int64_t)cus * per_cu, tiles);
@@ -634,14 +639,29 @@ dppix_status_t dp_pix_graph_create(dppix_plan_t p, const uint8_t* const* masks, 
         return st;
     if (images == nullptr || (st = check_store(store, true)) != DPPIX_OK)
         return st == DPPIX_OK ? fail(DPPIX_EINVAL, "images is NULL") : st;
+    // The legacy default stream cannot be captured; capture on a private
+    // non-blocking stream instead (the graph does not depend on it).
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipStream_t own = nullptr;
+    if (s == nullptr) {
+        hipError_t ec = hipStreamCreateWithFlags(&own, hipStreamNonBlocking);
+        if (ec != hipSuccess)
+            return dev_fail(ec, "capture stream");
+        s = own;
+    }
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess)
+    if (e != hipSuccess) {
+        if (own)
+            (void)hipStreamDestroy(own);
         return dev_fail(e, "begin capture");
-    dppix_status_t s1 = dp_pix_plan(p, masks, store, stream);
-    dppix_status_t s2 = s1 == DPPIX_OK ? dp_pix_forward(p, images, store, nullptr, nullptr, fused_out, stream) : s1;
+    }
+    dppix_stream_t cs = reinterpret_cast<dppix_stream_t>(s);
+    dppix_status_t s1 = dp_pix_plan(p, masks, store, cs);
+    dppix_status_t s2 = s1 == DPPIX_OK ? dp_pix_forward(p, images, store, nullptr, nullptr, fused_out, cs) : s1;
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(s, &g);
+    if (own)
+        (void)hipStreamDestroy(own);
     if (s2 != DPPIX_OK) {
         if (g)
             (void)hipGraphDestroy(g);

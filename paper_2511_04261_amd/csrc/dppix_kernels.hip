@@ -251,25 +251,60 @@ __device__ void classify_tile(const TileArgs& a, const FrameRec& F, const TileCo
     }
     const LdsPlan L = lds_plan(kClassify, F.K, b, F.n, 1);
     uint32_t* colcnt = reinterpret_cast<uint32_t*>(lds + L.colsum);
+    for (int i = tid; i < 16 * nstr; i += NT)
+        colcnt[i] = 0;
     if (tid == 0)
         s_count = 0;
+    lds_barrier();
+    // A mask row of a tile is narrow (K*b bytes), so lanes split the band's
+    // rows into `groups` interleaved sets; partial column counts meet in LDS.
+    const int groups = max(1, min(b, NT / nstr));
     const bool aligned = ((reinterpret_cast<uintptr_t>(mask) | (uintptr_t)W | (uintptr_t)X0) & 15) == 0;
-    for (int st = tid; st < nstr; st += NT) {
+    const int row0 = tc.r * b;
+    for (int item = tid; item < nstr * groups; item += NT) {
+        const int st = item % nstr, g = item / nstr;
         const int64_t p0 = X0 + 16 * st;
         uint32_t e[4] = {0, 0, 0, 0}, o[4] = {0, 0, 0, 0};
-        const bool fast = aligned && p0 + 16 <= min(tile_end, (int64_t)W);
-        for (int k = 0; k < b; ++k) {
-            const int src = fold(tc.r * b + k, H, F.pad);
-            const uint8_t* row = mask + (int64_t)src * W;
-            v4u w;
-            if (fast)
-                w = __builtin_nontemporal_load(reinterpret_cast<const v4u*>(row + p0));
-            else
-                w = gather_strip_u8<1>(row, (int)p0, (int)tile_end, W, F.pad);
-            w.x = nz_bytes(w.x); w.y = nz_bytes(w.y); w.z = nz_bytes(w.z); w.w = nz_bytes(w.w);
-            acc_bytes(w, e, o);
+        if (aligned && p0 + 16 <= min(tile_end, (int64_t)W)) {
+            int k = g;
+            for (; k + 3 * groups < b; k += 4 * groups) {
+                v4u w0 = __builtin_nontemporal_load(
+                    reinterpret_cast<const v4u*>(mask + (int64_t)fold(row0 + k, H, F.pad) * W + p0));
+                v4u w1 = __builtin_nontemporal_load(
+                    reinterpret_cast<const v4u*>(mask + (int64_t)fold(row0 + k + groups, H, F.pad) * W + p0));
+                v4u w2 = __builtin_nontemporal_load(
+                    reinterpret_cast<const v4u*>(mask + (int64_t)fold(row0 + k + 2 * groups, H, F.pad) * W + p0));
+                v4u w3 = __builtin_nontemporal_load(
+                    reinterpret_cast<const v4u*>(mask + (int64_t)fold(row0 + k + 3 * groups, H, F.pad) * W + p0));
+                w0 = v4u{nz_bytes(w0.x), nz_bytes(w0.y), nz_bytes(w0.z), nz_bytes(w0.w)};
+                w1 = v4u{nz_bytes(w1.x), nz_bytes(w1.y), nz_bytes(w1.z), nz_bytes(w1.w)};
+                w2 = v4u{nz_bytes(w2.x), nz_bytes(w2.y), nz_bytes(w2.z), nz_bytes(w2.w)};
+                w3 = v4u{nz_bytes(w3.x), nz_bytes(w3.y), nz_bytes(w3.z), nz_bytes(w3.w)};
+                acc_bytes(w0, e, o);
+                acc_bytes(w1, e, o);
+                acc_bytes(w2, e, o);
+                acc_bytes(w3, e, o);
+            }
+            for (; k < b; k += groups) {
+                v4u w = __builtin_nontemporal_load(
+                    reinterpret_cast<const v4u*>(mask + (int64_t)fold(row0 + k, H, F.pad) * W + p0));
+                acc_bytes(v4u{nz_bytes(w.x), nz_bytes(w.y), nz_bytes(w.z), nz_bytes(w.w)}, e, o);
+            }
+        } else {
+            for (int k = g; k < b; k += groups) {
+                v4u w = gather_strip_u8<1>(mask + (int64_t)fold(row0 + k, H, F.pad) * W, (int)p0, (int)tile_end,
+                                           W, F.pad);
+                acc_bytes(v4u{nz_bytes(w.x), nz_bytes(w.y), nz_bytes(w.z), nz_bytes(w.w)}, e, o);
+            }
         }
-        store_colsums(colcnt + 16 * st, e, o);
+        uint32_t* cc = colcnt + 16 * st;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            atomicAdd(cc + 4 * d + 0, e[d] & 0xFFFFu);
+            atomicAdd(cc + 4 * d + 1, o[d] & 0xFFFFu);
+            atomicAdd(cc + 4 * d + 2, e[d] >> 16);
+            atomicAdd(cc + 4 * d + 3, o[d] >> 16);
+        }
     }
     lds_barrier();
     for (int kc = tid; kc < Kt; kc += NT) {
