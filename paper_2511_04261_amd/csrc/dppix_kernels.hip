@@ -145,6 +145,17 @@ __device__ __forceinline__ void store_colsums(uint32_t* dst, const uint32_t (&e)
         d4[d] = v4u{e[d] & 0xFFFFu, o[d] & 0xFFFFu, e[d] >> 16, o[d] >> 16};
 }
 
+// Same, as 16-bit column sums in natural byte-column order (a subgrid row
+// has at most 256 rows of bytes, so 255 * 256 fits).
+__device__ __forceinline__ void store_colsums16(uint16_t* dst, const uint32_t (&e)[4], const uint32_t (&o)[4])
+{
+    v4u* d4 = reinterpret_cast<v4u*>(dst);
+    d4[0] = v4u{(e[0] & 0xFFFFu) | (o[0] << 16), (e[0] >> 16) | (o[0] & 0xFFFF0000u),
+                (e[1] & 0xFFFFu) | (o[1] << 16), (e[1] >> 16) | (o[1] & 0xFFFF0000u)};
+    d4[1] = v4u{(e[2] & 0xFFFFu) | (o[2] << 16), (e[2] >> 16) | (o[2] & 0xFFFF0000u),
+                (e[3] & 0xFFFFu) | (o[3] << 16), (e[3] >> 16) | (o[3] & 0xFFFF0000u)};
+}
+
 // Gather one 16-byte strip of a padded row byte by byte: columns past the
 // image fold back (mirror), bytes past the tile end read as zero.  Only the
 // strips that cross the right edge or a misaligned row take this path.
@@ -446,7 +457,7 @@ __device__ void forward_tile_u8(const TileArgs& a, const FrameRec& F, const Tile
     const bool in_aligned = ((reinterpret_cast<uintptr_t>(img) | (uintptr_t)pitch | (uintptr_t)X0) & 15) == 0;
 
     const LdsPlan L = lds_plan(kFwdU8, F.K, b, n, C);
-    uint32_t* colsum = reinterpret_cast<uint32_t*>(lds + L.colsum);
+    uint16_t* col16 = reinterpret_cast<uint16_t*>(lds + L.colsum);
     uint8_t* ex = lds + L.colsum;
     uint32_t* cspart = reinterpret_cast<uint32_t*>(lds + L.cspart);
     uint32_t* cidx = reinterpret_cast<uint32_t*>(lds + L.cidx);
@@ -459,63 +470,78 @@ __device__ void forward_tile_u8(const TileArgs& a, const FrameRec& F, const Tile
     const uint64_t fg_base = a.frame_base[2 * tc.f + 1];
     const int items = Kt * n * C;
     const int nn = n * n;
+    const int rowbuf = 16 * nstr;           // 16-bit column sums of one subgrid row
     lds_barrier();
 
-    // ---- subgrid rows: exact column sums, then subcell sums ----
-    for (int fr = 0; fr < n; ++fr) {
-        const int row0 = r * b + fr * s;
+    // ---- subgrid rows, up to kRowGroup at a time: each lane streams its strip
+    // down all rows of the group (exact 16-bit column sums per subgrid row,
+    // one LDS buffer each), then one lane per (subcell column, channel) adds
+    // s_b columns per subgrid row and releases complex subcells ----
+    for (int fr0 = 0; fr0 < n; fr0 += kRowGroup) {
+        const int ng = min(kRowGroup, n - fr0);
         for (int st = tid; st < nstr; st += NT) {
             const int64_t p0 = X0 + 16 * st;
-            uint32_t e[4] = {0, 0, 0, 0}, o[4] = {0, 0, 0, 0};
-            if (in_aligned && p0 + 16 <= lim) {
-                int k = 0;
-                for (; k + 4 <= s; k += 4) {
-                    const uint8_t* r0 = img + (int64_t)fold(row0 + k + 0, H, pad) * pitch + p0;
-                    const uint8_t* r1 = img + (int64_t)fold(row0 + k + 1, H, pad) * pitch + p0;
-                    const uint8_t* r2 = img + (int64_t)fold(row0 + k + 2, H, pad) * pitch + p0;
-                    const uint8_t* r3 = img + (int64_t)fold(row0 + k + 3, H, pad) * pitch + p0;
-                    const v4u w0 = __builtin_nontemporal_load(reinterpret_cast<const v4u*>(r0));
-                    const v4u w1 = __builtin_nontemporal_load(reinterpret_cast<const v4u*>(r1));
-                    const v4u w2 = __builtin_nontemporal_load(reinterpret_cast<const v4u*>(r2));
-                    const v4u w3 = __builtin_nontemporal_load(reinterpret_cast<const v4u*>(r3));
-                    acc_bytes(w0, e, o);
-                    acc_bytes(w1, e, o);
-                    acc_bytes(w2, e, o);
-                    acc_bytes(w3, e, o);
+            const bool fast = in_aligned && p0 + 16 <= lim;
+            for (int g = 0; g < ng; ++g) {
+                const int row0 = r * b + (fr0 + g) * s;
+                uint32_t e[4] = {0, 0, 0, 0}, o[4] = {0, 0, 0, 0};
+                if (fast) {
+                    int k = 0;
+                    for (; k + 4 <= s; k += 4) {
+                        const uint8_t* r0 = img + (int64_t)fold(row0 + k + 0, H, pad) * pitch + p0;
+                        const uint8_t* r1 = img + (int64_t)fold(row0 + k + 1, H, pad) * pitch + p0;
+                        const uint8_t* r2 = img + (int64_t)fold(row0 + k + 2, H, pad) * pitch + p0;
+                        const uint8_t* r3 = img + (int64_t)fold(row0 + k + 3, H, pad) * pitch + p0;
+                        const v4u w0 = __builtin_nontemporal_load(reinterpret_cast<const v4u*>(r0));
+                        const v4u w1 = __builtin_nontemporal_load(reinterpret_cast<const v4u*>(r1));
+                        const v4u w2 = __builtin_nontemporal_load(reinterpret_cast<const v4u*>(r2));
+                        const v4u w3 = __builtin_nontemporal_load(reinterpret_cast<const v4u*>(r3));
+                        acc_bytes(w0, e, o);
+                        acc_bytes(w1, e, o);
+                        acc_bytes(w2, e, o);
+                        acc_bytes(w3, e, o);
+                    }
+                    for (; k < s; ++k) {
+                        const uint8_t* rk = img + (int64_t)fold(row0 + k, H, pad) * pitch + p0;
+                        acc_bytes(__builtin_nontemporal_load(reinterpret_cast<const v4u*>(rk)), e, o);
+                    }
+                } else {
+                    for (int k = 0; k < s; ++k) {
+                        const uint8_t* rk = img + (int64_t)fold(row0 + k, H, pad) * pitch;
+                        acc_bytes(gather_strip_u8<C>(rk, (int)p0, (int)tile_end, W, pad), e, o);
+                    }
                 }
-                for (; k < s; ++k) {
-                    const uint8_t* rk = img + (int64_t)fold(row0 + k, H, pad) * pitch + p0;
-                    acc_bytes(__builtin_nontemporal_load(reinterpret_cast<const v4u*>(rk)), e, o);
-                }
-            } else {
-                for (int k = 0; k < s; ++k) {
-                    const uint8_t* rk = img + (int64_t)fold(row0 + k, H, pad) * pitch;
-                    acc_bytes(gather_strip_u8<C>(rk, (int)p0, (int)tile_end, W, pad), e, o);
-                }
+                store_colsums16(col16 + g * rowbuf + 16 * st, e, o);
             }
-            store_colsums(colsum + 16 * st, e, o);
         }
         lds_barrier();
         for (int j = tid; j < items; j += NT) {
             const int fc = j / C, ch = j - fc * C;
-            const uint32_t* cp = colsum + fc * s * C + ch;
-            uint32_t S = 0;
-            for (int x = 0; x < s; ++x)
-                S += cp[x * C];
             const int kc = fc / n, jj = fc - kc * n;
-            if (a.dbg_fine)
-                a.dbg_fine[(F.fine_base + (int64_t)(r * n + fr) * ((int64_t)F.GC * n) + (int64_t)x0c * n + fc) * C + ch] = S;
-            cspart[j] = (fr == 0 ? 0u : cspart[j]) + S;
-            if (cflag[kc]) {
-                const uint32_t id = (uint32_t)(r * n + fr) * (uint32_t)(F.GC * n) + (uint32_t)(x0c * n + fc);
-                uint8_t pass;
-                const float v = release((double)S, (double)(s * s), F.noise_fg, F.sigma_fg, F, id, ch, 1, pass);
-                const uint64_t at = fg_base + ((uint64_t)cidx[kc] * nn + fr * n + jj) * C + ch;
-                a.fg[at] = v;
-                if (a.clip_fg)
-                    a.clip_fg[at] = pass;
-                vgc[(fr * Kt * n + fc) * C + ch] = to_u8(v);
+            const bool cx = cflag[kc] != 0;
+            uint32_t total = fr0 == 0 ? 0u : cspart[j];
+            for (int g = 0; g < ng; ++g) {
+                const int fr = fr0 + g;
+                const uint16_t* cp = col16 + g * rowbuf + fc * s * C + ch;
+                uint32_t S = 0;
+                for (int x = 0; x < s; ++x)
+                    S += cp[x * C];
+                total += S;
+                if (a.dbg_fine)
+                    a.dbg_fine[(F.fine_base + (int64_t)(r * n + fr) * ((int64_t)F.GC * n) + (int64_t)x0c * n + fc) * C +
+                               ch] = S;
+                if (cx) {
+                    const uint32_t id = (uint32_t)(r * n + fr) * (uint32_t)(F.GC * n) + (uint32_t)(x0c * n + fc);
+                    uint8_t pass;
+                    const float v = release((double)S, (double)(s * s), F.noise_fg, F.sigma_fg, F, id, ch, 1, pass);
+                    const uint64_t at = fg_base + ((uint64_t)cidx[kc] * nn + fr * n + jj) * C + ch;
+                    a.fg[at] = v;
+                    if (a.clip_fg)
+                        a.clip_fg[at] = pass;
+                    vgc[(fr * Kt * n + fc) * C + ch] = to_u8(v);
+                }
             }
+            cspart[j] = total;
         }
         lds_barrier();
     }
@@ -753,8 +779,10 @@ __device__ __forceinline__ void run_tiles(const TileArgs& a, uint8_t* lds, Body 
     }
 }
 
+// Five waves per SIMD: enough resident tiles per CU to keep HBM busy while
+// other waves are in their LDS phases (the register budget still fits).
 template <int C>
-__global__ __launch_bounds__(kMaxThreads) void k_forward_u8(TileArgs a)
+__global__ __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(5))) void k_forward_u8(TileArgs a)
 {
     extern __shared__ __align__(16) uint8_t lds[];
     run_tiles(a, lds, [&](const FrameRec& F, const TileCoord& tc) { forward_tile_u8<C>(a, F, tc, lds); });

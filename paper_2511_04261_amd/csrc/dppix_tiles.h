@@ -7,6 +7,8 @@
 
 namespace dppix {
 
+constexpr int kRowGroup = 8;   // subgrid rows summed per pass of the u8 forward
+
 enum TileKind : int {
     kClassify = 0,   // mask counts per cell
     kFwdU8 = 1,      // forward, uint8 HWC
@@ -44,11 +46,14 @@ __host__ __device__ inline LdsPlan lds_plan(int kind, int K, int b, int n, int C
     const uint32_t nstr = tile_strips(kind, K, b, C);
     uint32_t o = 0;
     p.colsum = o;
-    // u8 column sums are 32-bit per byte column (the u8 forward reuses them as
-    // two expanded output rows); reconstruction and f32 forward keep two
-    // expanded output rows; the adjoint one row of float column sums
-    if (kind == kClassify || kind == kFwdU8)
+    // classify: 32-bit column counts; u8 forward: 16-bit column sums of up to
+    // kRowGroup subgrid rows (reused as two expanded output rows); f32 forward
+    // and reconstruction: two expanded output rows; adjoint: one row of float
+    // column sums
+    if (kind == kClassify)
         o += al16(64u * nstr);
+    else if (kind == kFwdU8)
+        o += al16(32u * nstr * (uint32_t)(n < kRowGroup ? n : kRowGroup));
     else if (kind == kBwd)
         o += al16(16u * nstr);
     else
