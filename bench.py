@@ -8,7 +8,7 @@ Laplace noise, clip, compact store) with the reconstruction fused in.
 Default workload: 64 RGB 1920x1080 frames, 8-rectangle foreground masks,
 simple cells b=32 / eps=1.0, complex subcells s_b=8 / eps=0.3, m=16.
 Reported beside it: the same kernels launched once per frame, the uneven
-mixed-resolution batch (256 frames, one persistent launch, graph-replayed),
+mixed-resolution batch (256 frames, one launch per layout group, graph-replayed),
 and the CPU oracle on a bounded sample.
 
 Prints ONE JSON line.
@@ -65,7 +65,7 @@ def read_traffic(bytes_per_launch_alg: float):
     return fetch + write
 
 
-def build_batch(frames_s, dev, persistent=True, threads=0):
+def build_batch(frames_s, dev, persistent=0, threads=0):
     import torch
     import paper_2511_04261_amd as dp
     frames = [dp.FrameParams.from_spec(s) for s in frames_s]
@@ -111,9 +111,9 @@ def time_steps(step_fn, warmup, steps, stream, fwd_events=None):
     return dt, fwd_ms
 
 
-def run_batched(frames_s, dev, warmup, steps, graph=False, threads=0):
+def run_batched(frames_s, dev, warmup, steps, graph=False, threads=0, persistent=0):
     import torch
-    plan, imgs, masks, outs = build_batch(frames_s, dev, persistent=True, threads=threads)
+    plan, imgs, masks, outs = build_batch(frames_s, dev, persistent=persistent, threads=threads)
     stream = torch.cuda.current_stream()
     g = plan.graph(masks, imgs, outs) if graph else None
 
@@ -194,7 +194,7 @@ def counters_run(frames_s, dev, launches=3, copy_bytes=1 << 30):
     dst.copy_(src)
     torch.cuda.synchronize()
     del src, dst
-    plan, imgs, masks, outs = build_batch(frames_s, dev, persistent=True)
+    plan, imgs, masks, outs = build_batch(frames_s, dev)
     for _ in range(launches):
         plan.plan(masks)
         plan.forward(imgs, out=outs)
@@ -211,24 +211,27 @@ def cpu_baseline(frames_s, budget_s=15.0, dev=None):
     import oracle
     oracle.build()
     dt = 0.0
-    done = px = 0
-    for s in frames_s:
-        # inputs rendered on the device and copied back (byte-identical), not timed
-        img = s.image_torch(dev).cpu().numpy() if dev is not None else s.image
-        mask = s.mask
-        t1 = time.perf_counter()
-        oracle.forward(img, mask, oracle.Params(s.height, s.width, s.channels, b=s.b, sb=s.sb, m=s.m,
-                                                eps_simple=s.eps_simple, eps_complex=s.eps_complex, tau=s.tau,
-                                                seed=s.seed, frame_index=s.frame_index))
-        dt += time.perf_counter() - t1
-        done += 1
-        px += s.height * s.width
-        s.drop_host()
-        if dt > budget_s:
-            break
+    done = px = passes = 0
+    while dt < budget_s and passes < 8:
+        passes += 1
+        for s in frames_s:
+            # inputs rendered on the device and copied back (byte-identical), not timed
+            img = s.image_torch(dev).cpu().numpy() if dev is not None else s.image
+            mask = s.mask
+            t1 = time.perf_counter()
+            oracle.forward(img, mask, oracle.Params(s.height, s.width, s.channels, b=s.b, sb=s.sb, m=s.m,
+                                                    eps_simple=s.eps_simple, eps_complex=s.eps_complex, tau=s.tau,
+                                                    seed=s.seed, frame_index=s.frame_index))
+            dt += time.perf_counter() - t1
+            done += 1
+            px += s.height * s.width
+            s.drop_host()
+            if dt > budget_s:
+                break
     return dict(value=round(px / dt / 1e6, 3), unit="megapixels/s", cores=1, kind="oracle",
-                sample="%d of %d frames (%dx%d RGB), single thread, %.1f s" % (
-                    done, len(frames_s), frames_s[0].width, frames_s[0].height, dt))
+                sample="%d frame passes over the %d-frame batch (%dx%d RGB, masks, same parameters), "
+                       "single thread, %.1f s of oracle time" % (
+                           done, len(frames_s), frames_s[0].width, frames_s[0].height, dt))
 
 
 def main():
@@ -280,7 +283,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "region-adaptive DP pixelization, %d RGB 1920x1080 uint8 frames, 8-rectangle "
                                "masks (~15%% cover), b=32 eps=1.0 simple / s_b=8 eps=0.3 complex, m=16, "
-                               "plan+forward with fused reconstruction, one persistent launch, graph-replayed"
+                               "plan+forward with fused reconstruction, one launch for the batch, graph-replayed"
                                % args.frames,
                    "frames": args.frames, "resolution": "1920x1080x3", "b_bg": 32, "b_fg": 8, "m": 16,
                    "eps_bg": 1.0, "eps_fg": 0.3},

@@ -208,9 +208,12 @@ dppix_status_t dp_pix_backward(dppix_plan_t plan, const dppix_store_t* store, co
  * ------------------------------------------------------------------------- */
 
 /* Launch shape of the tile kernels: threads per workgroup (64..512, multiple
- * of 64; 0 = default) and persistent mode (1: a grid of resident workgroups
- * pulls tiles from an atomic ticket in the workspace; 0: one workgroup per
- * tile).  Results never depend on these. */
+ * of 64; 0 = default) and the work distribution: persistent = 0 launches one
+ * workgroup per tile (the hardware dispatcher feeds the CUs; the default);
+ * persistent = 1 launches as many workgroups as the CUs hold at once and
+ * persistent = k in 2..64 launches k per CU — those workgroups stay resident
+ * and pull tiles from an atomic ticket in the workspace.  Results never
+ * depend on these. */
 dppix_status_t dp_pix_plan_set_launch(dppix_plan_t plan, int32_t threads, int32_t persistent);
 
 /* Capture plan + forward (+ fused reconstruction) on the stream into a HIP

@@ -86,7 +86,7 @@ class Plan:
     reconstruct/backward); calls are stream-ordered and never synchronise.
     """
 
-    def __init__(self, frames: Sequence[FrameParams], device=None, threads: int = 0, persistent: bool = False):
+    def __init__(self, frames: Sequence[FrameParams], device=None, threads: int = 0, persistent: int = 0):
         torch = _torch()
         self.lib = _lib.load()
         self.frames = list(frames)
@@ -117,9 +117,11 @@ class Plan:
         self._tables = {}
 
     # -- plumbing ---------------------------------------------------------
-    def set_launch(self, threads: int = 0, persistent: bool = False):
-        _lib.check(self.lib.dp_pix_plan_set_launch(self.handle, int(threads), int(bool(persistent))))
-        self.threads, self.persistent = threads, bool(persistent)
+    def set_launch(self, threads: int = 0, persistent: int = 0):
+        """threads per workgroup (0: default); persistent: 0 one workgroup per
+        tile, 1 a resident grid pulling tiles from a ticket, k >= 2 k per CU."""
+        _lib.check(self.lib.dp_pix_plan_set_launch(self.handle, int(threads), int(persistent)))
+        self.threads, self.persistent = threads, int(persistent)
 
     def pointer_table(self, tensors: Optional[Sequence]):
         """Device array of device pointers (None entries -> NULL)."""

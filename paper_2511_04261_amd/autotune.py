@@ -5,7 +5,7 @@ an index-ordered scan, geometry-keyed noise), so the tuner is free to pick the
 fastest.  For each geometry class (layout, H, W, C, b, s_b) it times
 plan + forward on a synthetic batch of that class large enough to fill the GPU,
 for a few tile widths and workgroup sizes and both launch modes, with HIP
-events, and keeps the median-fastest.  Winners are cached in a JSON file keyed
+events around steps enqueued back to back, and keeps the fastest.  Winners are cached in a JSON file keyed
 by the device name and the class.
 """
 from __future__ import annotations
@@ -22,7 +22,9 @@ from . import F32_CHW, U8_HWC, FrameParams, Plan
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "dppix", "autotune.json")
 TILE_BYTES = (1024, 2048, 4096, 8192)
-THREADS = (128, 256, 512)
+THREADS = (128, 192, 256, 512)
+#: 0: one workgroup per tile; 1: resident grid pulling tiles from a ticket
+LAUNCH_MODES = (0, 1)
 
 
 def class_key(fp: FrameParams) -> str:
@@ -64,24 +66,36 @@ def _class_batch(fp: FrameParams, device, min_pixels: float):
     return n, imgs, masks
 
 
-def time_config(frames: Sequence[FrameParams], imgs, masks, device, threads: int, persistent: bool,
+def time_config(frames: Sequence[FrameParams], imgs, masks, device, threads: int, persistent: int,
                 reps: int = 5, fused: bool = True) -> float:
-    """Median ms of plan + forward for one launch configuration."""
+    """GPU ms of one plan + forward for one launch configuration: the median
+    of three windows of `reps` steps enqueued back to back through the C ABI
+    (no host work between steps inside a window)."""
+    import ctypes
     import torch
+    from . import _lib
     plan = Plan(frames, device=device, threads=threads, persistent=persistent)
     outs = [torch.empty_like(t) for t in imgs] if fused else None
+    plan.plan(masks)
+    plan.forward(imgs, out=outs)      # checks shapes once, builds the pointer tables
+    lib, h, st = plan.lib, plan.handle, ctypes.byref(plan.store)
+    ip = ctypes.c_void_p(plan.pointer_table(imgs).data_ptr())
+    mt = plan.pointer_table(masks)
+    mp = None if mt is None else ctypes.c_void_p(mt.data_ptr())
+    op = None if outs is None else ctypes.c_void_p(plan.pointer_table(outs).data_ptr())
     stream = torch.cuda.current_stream()
+    sh = ctypes.c_void_p(stream.cuda_stream)
     times = []
-    for i in range(reps + 1):
+    for _ in range(3):
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
         a.record(stream)
-        plan.plan(masks)
-        plan.forward(imgs, out=outs)
+        for _ in range(reps):
+            _lib.check(lib.dp_pix_plan(h, mp, st, sh))
+            _lib.check(lib.dp_pix_forward(h, ip, st, None, None, op, sh))
         b.record(stream)
         b.synchronize()
-        if i:
-            times.append(a.elapsed_time(b))
+        times.append(a.elapsed_time(b) / reps)
     plan.close()
     return statistics.median(times)
 
@@ -113,11 +127,11 @@ class Autotuner:
         if key in self.cache:
             return self.cache[key]
         n, imgs, masks = _class_batch(fp, self.device, self.min_pixels)
-        results: List[Tuple[float, int, int, bool]] = []
+        results: List[Tuple[float, int, int, int]] = []
         for tc in tile_candidates(fp):
             frames = [replace(fp, tile_cells=tc, frame_index=i) for i in range(n)]
             for th in THREADS:
-                for pers in (False, True):
+                for pers in LAUNCH_MODES:
                     ms = time_config(frames, imgs, masks, self.device, th, pers, self.reps)
                     results.append((ms, tc, th, pers))
         results.sort()
@@ -131,12 +145,13 @@ class Autotuner:
 
     def tune_batch(self, frames: Sequence[FrameParams]) -> Tuple[List[FrameParams], dict]:
         """Per-class tile widths for every frame, and one launch shape for the
-        batch: the workgroup size voted by pixel count, persistent mode."""
-        votes: Dict[int, float] = {}
+        batch: the (workgroup size, launch mode) pair voted by pixel count."""
+        votes: Dict[Tuple[int, int], float] = {}
         out = []
         for fp in frames:
             best = self.tune_class(fp)
             out.append(replace(fp, tile_cells=best["tile_cells"]))
-            votes[best["threads"]] = votes.get(best["threads"], 0.0) + fp.height * fp.width
-        threads = max(votes, key=votes.get)
-        return out, dict(threads=threads, persistent=True)
+            k = (best["threads"], best["persistent"])
+            votes[k] = votes.get(k, 0.0) + fp.height * fp.width
+        threads, persistent = max(votes, key=votes.get)
+        return out, dict(threads=threads, persistent=persistent)

@@ -307,8 +307,7 @@ dppix_status_t dp_pix_plan_create(const dppix_frame_desc_t* descs, int32_t n_fra
     WsLayout& w = p->ws;
     size_t o = 0;
     w.frames = o;      o = align256(o + sizeof(FrameRec) * n_frames);
-    w.sched_frame = o; o = align256(o + sizeof(int32_t) * n_frames);
-    w.sched_base = o;  o = align256(o + sizeof(int64_t) * (n_frames + 1));
+    w.tile_map = o;    o = align256(o + sizeof(int32_t) * 2 * (size_t)p->n_tiles);
     w.flags = o;       o = align256(o + (size_t)p->total_cells);
     w.tile_cnt = o;    o = align256(o + sizeof(uint32_t) * (size_t)p->n_tiles);
     w.tile_fg = o;     o = align256(o + sizeof(uint32_t) * (size_t)p->n_tiles);
@@ -317,11 +316,16 @@ dppix_status_t dp_pix_plan_create(const dppix_frame_desc_t* descs, int32_t n_fra
     w.counters = o;    o = align256(o + sizeof(uint32_t) * kTicketWords);
     w.total = o;
 
-    // Host image of the static tables (frames, sched_frame, sched_base).
+    // Host image of the static tables: frame records, and per scheduling index
+    // the frame and the tile within it.
     p->host_tables.assign(w.flags, 0);
     std::memcpy(p->host_tables.data() + w.frames, p->frames.data(), sizeof(FrameRec) * n_frames);
-    std::memcpy(p->host_tables.data() + w.sched_frame, p->sched_frame.data(), sizeof(int32_t) * n_frames);
-    std::memcpy(p->host_tables.data() + w.sched_base, p->sched_base.data(), sizeof(int64_t) * (n_frames + 1));
+    int32_t* map = reinterpret_cast<int32_t*>(p->host_tables.data() + w.tile_map);
+    for (int32_t k = 0; k < n_frames; ++k)
+        for (int64_t i = p->sched_base[k]; i < p->sched_base[k + 1]; ++i) {
+            map[2 * i] = order[k];
+            map[2 * i + 1] = (int32_t)(i - p->sched_base[k]);
+        }
     *out = p;
     return DPPIX_OK;
 }
@@ -374,8 +378,9 @@ dppix_status_t dp_pix_plan_set_launch(dppix_plan_t p, int32_t threads, int32_t p
         threads = kDefaultThreads;
     if (threads < 64 || threads > kMaxThreads || threads % 64 != 0)
         return fail(DPPIX_EINVAL, "threads must be a multiple of 64 in 64..512");
-    if (persistent != 0 && persistent != 1)
-        return fail(DPPIX_EINVAL, "persistent must be 0 or 1");
+    if (persistent < 0 || persistent > 64)
+        return fail(DPPIX_EINVAL, "persistent must be 0 (one workgroup per tile), 1 (resident grid) or 2..64 "
+                                  "(workgroups per CU)");
     p->threads = threads;
     p->persistent = persistent;
     return DPPIX_OK;
@@ -413,8 +418,7 @@ TileArgs base_args(dppix_plan_t p)
     std::memset(&a, 0, sizeof a);
     uint8_t* w = p->bound;
     a.frames = reinterpret_cast<const FrameRec*>(w + p->ws.frames);
-    a.sched_frame = reinterpret_cast<const int32_t*>(w + p->ws.sched_frame);
-    a.sched_base = reinterpret_cast<const int64_t*>(w + p->ws.sched_base);
+    a.tile_map = reinterpret_cast<const int32_t*>(w + p->ws.tile_map);
     a.n_frames = (int32_t)p->frames.size();
     a.n_tiles = p->n_tiles;
     a.ticket = reinterpret_cast<uint32_t*>(w + p->ws.counters);
@@ -458,8 +462,8 @@ int grid_for(dppix_plan_t p, int layout, int C, int64_t tiles, size_t lds)
             p->cus = 256;
     }
     const int cus = p->cus;
-    int per_cu = 1;
-    if (occupancy_forward(layout, C, p->threads, lds, &per_cu) != hipSuccess || per_cu < 1)
+    int per_cu = p->persistent;
+    if (per_cu == 1 && (occupancy_forward(layout, C, p->threads, lds, &per_cu) != hipSuccess || per_cu < 1))
         per_cu = 1;
     const int64_t g = std::min<int64_t>((int64_t)cus * per_cu, tiles);
     return (int)std::max<int64_t>(1, g);

@@ -16,7 +16,8 @@ namespace dppix {
 constexpr int kStrip = 16;             // bytes one lane moves per row (dwordx4)
 constexpr int kMaxThreads = 512;
 constexpr int kMaxB = 256;             // 255 * 256 rows fits a 16-bit lane sum
-constexpr int kTicketWords = 16;       // two per launch group (at most 5 groups)
+constexpr int kTicketWords = 16;       // two per launch group (at most 5 groups) ...
+constexpr int kScanWord = 15;          // ... and the finished-workgroup count of the scan
 
 // One frame as the kernels see it (host computes everything derivable).
 struct FrameRec {
@@ -35,8 +36,7 @@ struct FrameRec {
 // Workspace layout (byte offsets from the bound workspace base).
 struct WsLayout {
     size_t frames;        // FrameRec[n_frames]
-    size_t sched_frame;   // int32[n_frames]: frames in scheduling order
-    size_t sched_base;    // int64[n_frames+1]: first tile index in scheduling order
+    size_t tile_map;      // int32[n_tiles][2]: (frame, tile within frame) per scheduling index
     size_t flags;         // uint8[total_cells] (classification)
     size_t tile_cnt;      // uint32[n_tiles]: complex cells per tile
     size_t tile_fg;       // uint32[n_tiles]: complex cells of the frame before the tile
@@ -48,8 +48,7 @@ struct WsLayout {
 
 struct TileArgs {
     const FrameRec* frames;
-    const int32_t* sched_frame;
-    const int64_t* sched_base;
+    const int32_t* tile_map;
     int32_t n_frames;
     int64_t sched_offset;     // first scheduling index of this launch
     int64_t n_tiles;          // tiles of this launch

@@ -105,22 +105,6 @@ __device__ __forceinline__ void lds_barrier()
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
-// Scheduling index -> (frame, tile within frame).  sched_base holds the first
-// scheduling index of each frame in scheduling order.
-__device__ __forceinline__ void locate(const TileArgs& a, int64_t idx, int& f, int64_t& local)
-{
-    int lo = 0, hi = a.n_frames - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (a.sched_base[mid] <= idx)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    f = a.sched_frame[lo];
-    local = idx - a.sched_base[lo];
-}
-
 // Add the bytes of one 16-byte strip into 16-bit lane pairs: e[d] holds bytes
 // 4d and 4d+2, o[d] bytes 4d+1 and 4d+3.
 __device__ __forceinline__ void acc_bytes(const v4u& w, uint32_t (&e)[4], uint32_t (&o)[4])
@@ -228,9 +212,10 @@ struct TileCoord {
 __device__ __forceinline__ TileCoord tile_of(const TileArgs& a, int64_t sched_idx, FrameRec& F)
 {
     TileCoord tc;
-    int64_t local;
-    locate(a, a.sched_offset + sched_idx, tc.f, local);
-    tc.f = (int)uniform_u32((uint32_t)tc.f);
+    // one load: (frame, tile within frame) of this scheduling index
+    const int64_t idx = a.sched_offset + sched_idx;
+    tc.f = (int)uniform_u32((uint32_t)a.tile_map[2 * idx]);
+    const int64_t local = (int64_t)uniform_u32((uint32_t)a.tile_map[2 * idx + 1]);
     F = a.frames[tc.f];
     tc.t = F.tile_base + local;
     tc.r = (int)(local / F.TX);
@@ -374,43 +359,20 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T* wave_tot, T& total)
     return excl;
 }
 
-// One workgroup per frame: exclusive scan of per-tile complex counts.
-__global__ __launch_bounds__(256) void k_scan_tiles(TileArgs a, uint64_t* frame_tot)
+// Frame-level pass of the scan: store offsets of every frame (frames
+// concatenated in batch order), per-frame counts, ticket reset.  Run by the
+// last workgroup of k_scan; the per-frame totals written by the others are
+// read with agent-scope atomic loads after an acquire fence.
+__device__ void scan_frames(const TileArgs& a, uint64_t* frame_base, uint64_t* counts, uint64_t* wave_tot)
 {
-    __shared__ uint32_t wave_tot[9];
-    const int f = blockIdx.x;
-    const FrameRec F = a.frames[f];
-    const int64_t nt = (int64_t)F.GR * F.TX;
-    uint32_t carry = 0;
-    for (int64_t base = 0; base < nt; base += blockDim.x) {
-        const int64_t i = base + threadIdx.x;
-        const uint32_t v = i < nt ? a.tile_cnt[F.tile_base + i] : 0u;
-        uint32_t tot;
-        const uint32_t ex = block_exclusive_scan<uint32_t>(v, wave_tot, tot);
-        if (i < nt)
-            a.tile_fg[F.tile_base + i] = carry + ex;
-        carry += tot;
-    }
-    if (threadIdx.x == 0) {
-        const uint64_t cells = (uint64_t)F.GR * F.GC;
-        frame_tot[2 * f + 0] = cells - carry;
-        frame_tot[2 * f + 1] = carry;
-    }
-}
-
-// One workgroup: frame offsets in the store, per-frame counts, ticket reset.
-__global__ __launch_bounds__(256) void k_scan_frames(TileArgs a, const uint64_t* frame_tot, uint64_t* frame_base,
-                                                     uint64_t* counts)
-{
-    __shared__ uint64_t wave_tot[9];
     uint64_t carry_bg = 0, carry_fg = 0;
     for (int base = 0; base < a.n_frames; base += blockDim.x) {
         const int f = base + threadIdx.x;
         uint64_t vb = 0, vf = 0, nb = 0, nf = 0;
         if (f < a.n_frames) {
             const FrameRec F = a.frames[f];
-            nb = frame_tot[2 * f];
-            nf = frame_tot[2 * f + 1];
+            nb = __hip_atomic_load(&a.frame_tot[2 * f], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            nf = __hip_atomic_load(&a.frame_tot[2 * f + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             vb = nb * (uint64_t)F.C;
             vf = nf * (uint64_t)F.n * (uint64_t)F.n * (uint64_t)F.C;
         }
@@ -430,8 +392,47 @@ __global__ __launch_bounds__(256) void k_scan_frames(TileArgs a, const uint64_t*
         carry_bg += tb;
         carry_fg += tf;
     }
-    if (threadIdx.x < kTicketWords)
+    if (threadIdx.x < kScanWord)
         a.ticket[threadIdx.x] = 0;
+}
+
+// One workgroup per frame: exclusive scan of the per-tile complex counts into
+// each tile's count of complex cells before it; the last workgroup to finish
+// then runs the frame-level pass.
+__global__ __launch_bounds__(256) void k_scan(TileArgs a, uint64_t* frame_base, uint64_t* counts)
+{
+    __shared__ uint32_t wave_tot[9];
+    __shared__ uint64_t wave_tot64[9];
+    __shared__ int s_last;
+    const int f = blockIdx.x;
+    const FrameRec F = a.frames[f];
+    const int64_t nt = (int64_t)F.GR * F.TX;
+    uint32_t carry = 0;
+    for (int64_t base = 0; base < nt; base += blockDim.x) {
+        const int64_t i = base + threadIdx.x;
+        const uint32_t v = i < nt ? a.tile_cnt[F.tile_base + i] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_exclusive_scan<uint32_t>(v, wave_tot, tot);
+        if (i < nt)
+            a.tile_fg[F.tile_base + i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) {
+        const uint64_t cells = (uint64_t)F.GR * F.GC;
+        a.frame_tot[2 * f + 0] = cells - carry;
+        a.frame_tot[2 * f + 1] = carry;
+        __threadfence();                                    // release the totals
+        const uint32_t done = atomicAdd(&a.ticket[kScanWord], 1u);
+        s_last = (done == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!s_last)
+        return;
+    __threadfence();                                        // acquire the others' totals
+    scan_frames(a, frame_base, counts, wave_tot64);
+    __syncthreads();
+    if (threadIdx.x == 0)
+        atomicExch(&a.ticket[kScanWord], 0u);
 }
 
 // ==========================================================================
@@ -1146,12 +1147,8 @@ hipError_t launch_classify(const TileArgs& a, int threads, size_t lds, hipStream
 
 hipError_t launch_scan(const TileArgs& a, uint64_t* counts_out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)a.n_frames), dim3(256), 0, s, a, a.frame_tot);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess)
-        return e;
-    hipLaunchKernelGGL(k_scan_frames, dim3(1), dim3(256), 0, s, a, a.frame_tot,
-                       const_cast<uint64_t*>(a.frame_base), counts_out);
+    hipLaunchKernelGGL(k_scan, dim3((unsigned)a.n_frames), dim3(256), 0, s, a, const_cast<uint64_t*>(a.frame_base),
+                       counts_out);
     return hipGetLastError();
 }
 

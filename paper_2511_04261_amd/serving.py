@@ -4,7 +4,7 @@ paper motivates real-time use but times one frame at a time).
 Requests (one frame of one stream) arrive at any time.  The scheduler admits
 them while the device-memory ledger has room, starts each admitted frame's
 host-to-device copy at once on a copy stream, and launches every admitted,
-copied frame as one batch (one plan, one persistent forward) as soon as fewer
+copied frame as one batch (one plan, one forward launch) as soon as fewer
 than ``max_inflight`` batches are on the GPU — so frames that arrive while a
 batch runs are copied during it and join the next one.  Each frame keeps its
 own Philox counter (its stream's sequence number), so its result is the same
@@ -196,7 +196,7 @@ class GpuBackend:
     with the fused reconstruction), and its store is copied back on the copy
     stream into pinned host memory."""
 
-    def __init__(self, device=None, reconstruct: bool = False, persistent: bool = True):
+    def __init__(self, device=None, reconstruct: bool = False, persistent: int = 0):
         import torch
         import paper_2511_04261_amd as dp
         self.torch = torch

@@ -139,7 +139,8 @@ def test_uneven_batch_matches_frames_alone(dev):
         compare_frame(batch["store"][i], want, batch["fused"][i], "frame %d" % i)
 
 
-@pytest.mark.parametrize("threads,persistent,tile", [(64, 0, 1), (128, 1, 3), (256, 0, 0), (512, 1, 7), (192, 1, 0)])
+@pytest.mark.parametrize("threads,persistent,tile", [(64, 0, 1), (128, 1, 3), (256, 0, 0), (512, 1, 7), (192, 1, 0),
+                                                     (256, 3, 0), (128, 2, 5)])
 def test_launch_shapes_are_bitwise_identical(dev, threads, persistent, tile):
     """Tile shape and launch mode never change a result (integer sums, an
     index-ordered scan, geometry-keyed noise): any race shows up here."""
@@ -152,11 +153,11 @@ def test_launch_shapes_are_bitwise_identical(dev, threads, persistent, tile):
     ref = run_gpu([base], [img], [mask], dev)
     fp = dp.FrameParams(H, W, C, dp.U8_HWC, b=16, sb=4, m=16, eps_bg=1.0, eps_fg=0.3, tau=1, seed=1,
                         tile_cells=tile)
-    got = run_gpu([fp], [img], [mask], dev, threads=threads, persistent=bool(persistent))
+    got = run_gpu([fp], [img], [mask], dev, threads=threads, persistent=persistent)
     for k in ("bg", "fg", "flags"):
         assert np.array_equal(got["store"][0][k], ref["store"][0][k]), k
     assert np.array_equal(got["fused"][0], ref["fused"][0])
-    again = run_gpu([fp], [img], [mask], dev, threads=threads, persistent=bool(persistent))
+    again = run_gpu([fp], [img], [mask], dev, threads=threads, persistent=persistent)
     assert np.array_equal(again["fused"][0], got["fused"][0])
 
 
