@@ -79,6 +79,9 @@ def _load():
         lib.orc_reconstruct.restype = ctypes.c_int32
         lib.orc_backward.argtypes = [P(_Params), vp, vp, vp, vp]
         lib.orc_backward.restype = ctypes.c_int32
+        lib.orc_edge_mask.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_int32,
+                                      ctypes.c_int32, vp]
+        lib.orc_edge_mask.restype = ctypes.c_int32
         _lib = lib
     return _lib
 
@@ -219,6 +222,20 @@ def reconstruct(flags, bg, fg, p: Params):
     if _load().orc_reconstruct(ctypes.byref(p._c()), _ptr(fl), _ptr(b_), _ptr(f_), _ptr(rf), _ptr(ru)):
         raise RuntimeError("orc_reconstruct failed")
     return rf, ru
+
+
+def edge_mask(img, threshold: int, pad_mode: int = PAD_SYMMETRIC):
+    """uint8 (H, W) Sobel edge mask of an HWC (or HW) image: 1 where
+    |Gx| + |Gy| of the channel sum reaches threshold * C."""
+    a = np.asarray(img)
+    if a.ndim == 2:
+        a = a[:, :, None]
+    H, W, C = a.shape
+    x = np.ascontiguousarray(a, dtype=np.float64)
+    out = np.zeros((H, W), np.uint8)
+    if _load().orc_edge_mask(H, W, C, _ptr(x), int(threshold), pad_mode, _ptr(out)):
+        raise ValueError("bad edge-mask arguments")
+    return out
 
 
 def backward(img, mask, grad_out, p: Params):

@@ -303,6 +303,41 @@ int32_t orc_forward(const orc_params_t* p, const double* img, const uint8_t* mas
     return 0;
 }
 
+/* Mirror index of a coordinate that may be -1 (one step before the start). */
+static int64_t edge_fold(int64_t x, int64_t L, int32_t mode)
+{
+    if (x < 0) {
+        if (mode == ORC_PAD_SYMMETRIC || L == 1)
+            return 0;
+        return 1;
+    }
+    return orc_fold(x, L, mode);
+}
+
+int32_t orc_edge_mask(int32_t M, int32_t N, int32_t C, const double* img, int32_t threshold, int32_t pad_mode,
+                      uint8_t* out)
+{
+    if (M < 1 || N < 1 || C < 1 || threshold < 0)
+        return 1;
+    for (int64_t i = 0; i < M; ++i)
+        for (int64_t j = 0; j < N; ++j) {
+            double S[3][3];
+            for (int di = -1; di <= 1; ++di)
+                for (int dj = -1; dj <= 1; ++dj) {
+                    int64_t y = edge_fold(i + di, M, pad_mode), x = edge_fold(j + dj, N, pad_mode);
+                    double s = 0.0;
+                    for (int64_t ch = 0; ch < C; ++ch)
+                        s += img[(y * N + x) * C + ch];
+                    S[di + 1][dj + 1] = s;
+                }
+            /* Sobel: derivative [-1 0 1] along one axis, smoothing [1 2 1] along the other */
+            double gx = (S[0][2] + 2.0 * S[1][2] + S[2][2]) - (S[0][0] + 2.0 * S[1][0] + S[2][0]);
+            double gy = (S[2][0] + 2.0 * S[2][1] + S[2][2]) - (S[0][0] + 2.0 * S[0][1] + S[0][2]);
+            out[i * N + j] = (uint8_t)(fabs(gx) + fabs(gy) >= (double)threshold * (double)C);
+        }
+    return 0;
+}
+
 /* Restoration from the stored metadata: broadcast each stored scalar over its
  * grid or subgrid in the padded frame, then crop. */
 int32_t orc_reconstruct(const orc_params_t* p, const uint8_t* flags, const float* bg,

@@ -104,6 +104,17 @@ int32_t orc_forward(const orc_params_t* p, const double* img, const uint8_t* mas
                     double* coarse_sum, double* fine_sum,
                     uint8_t* pass_bg, uint8_t* pass_fg);
 
+/*
+ * Complexity label from the image itself (the paper's Sec. VI-A names the
+ * Sobel operator as one way to obtain the mask).  S(i,j) = sum of the C
+ * channels; Gx, Gy = 3x3 Sobel responses of S with neighbours past the border
+ * mirrored (pad_mode); a pixel is an edge pixel (mask byte 1) when
+ * |Gx| + |Gy| >= threshold * C.  img: M*N*C doubles (HWC, integer-valued);
+ * out: M*N bytes.
+ */
+int32_t orc_edge_mask(int32_t M, int32_t N, int32_t C, const double* img, int32_t threshold, int32_t pad_mode,
+                      uint8_t* out);
+
 /* Reconstruction from the compact store only (flags, bg, fg, b, s_b, M x N). */
 int32_t orc_reconstruct(const orc_params_t* p, const uint8_t* flags, const float* bg,
                         const float* fg, float* recon_f32, uint8_t* recon_u8);

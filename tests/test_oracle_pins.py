@@ -510,3 +510,38 @@ def test_clip_bounds_and_tail_mass():
         assert abs(frac - want) < 5 * math.sqrt(want * (1 - want) / v.size) + 1e-7
     # pass bits: 1 exactly where the value was not clipped
     assert np.array_equal(o["pass_bg"][:, 0] == 1, (v > 0) & (v < 255))
+
+
+# --------------------------------------------------------------------------
+# Complexity label from the image (Sobel, Sec. VI-A)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("mode,scipy_mode", [(oracle.PAD_SYMMETRIC, "reflect"), (oracle.PAD_REFLECT, "mirror")])
+@pytest.mark.parametrize("H,W,C,T", [(37, 53, 3, 40), (16, 16, 1, 100), (5, 9, 3, 10), (64, 48, 4, 60)])
+def test_edge_mask_matches_scipy_sobel(mode, scipy_mode, H, W, C, T):
+    ndi = pytest.importorskip("scipy.ndimage")
+    r = rng(H * W + C)
+    img = synth_like(r, H, W, C)
+    S = img.astype(np.float64).sum(axis=2)
+    gx = ndi.sobel(S, axis=1, mode=scipy_mode)
+    gy = ndi.sobel(S, axis=0, mode=scipy_mode)
+    want = (np.abs(gx) + np.abs(gy) >= T * C).astype(np.uint8)
+    assert np.array_equal(oracle.edge_mask(img, T, mode), want)
+
+
+def synth_like(r, H, W, C):
+    """Piecewise-smooth test image: ramps, a bright rectangle, noise."""
+    i, j = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    base = (2 * i + 3 * j) % 200
+    img = np.repeat(base[:, :, None], C, axis=2) + r.integers(0, 20, (H, W, C))
+    img[H // 4: H // 2, W // 3: 2 * W // 3] = 240
+    return np.clip(img, 0, 255).astype(np.uint8)
+
+
+def test_edge_mask_ramp_closed_form():
+    # S(i,j) = a*j: interior |Gx| = 8a, |Gy| = 0; first/last column (symmetric mirror) 4a
+    a = 3
+    img = np.tile((a * np.arange(20))[None, :, None], (6, 1, 1)).astype(np.uint8)
+    for T, want_inner, want_edge in [(24, 1, 0), (12, 1, 1), (25, 0, 0)]:
+        m = oracle.edge_mask(img, T)
+        assert (m[:, 1:-1] == want_inner).all() and (m[:, [0, -1]] == want_edge).all()
+    assert (oracle.edge_mask(np.full((7, 7, 3), 99, np.uint8), 1) == 0).all()   # flat: no edges
