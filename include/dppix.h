@@ -169,6 +169,20 @@ dppix_status_t dp_pix_plan_bind(dppix_plan_t plan, void* workspace, size_t bytes
 dppix_status_t dp_pix_plan(dppix_plan_t plan, const uint8_t* const* masks, const dppix_store_t* store,
                            dppix_stream_t stream);
 
+/* Region mask from the frames themselves (Sec. VI-A: the mask may come from an
+ * edge detector such as the Sobel operator): for every real pixel, the 3x3
+ * Sobel responses Gx, Gy of the sum of its channels, neighbours past the
+ * border mirrored as pad_mode says; the mask byte is 1 when
+ * |Gx| + |Gy| >= threshold * channels, else 0.
+ *   images     device array of n_frames device pointers (U8_HWC frames only)
+ *   threshold  0..4096, per-channel units
+ *   masks_out  device array of n_frames device pointers to height*width bytes
+ *              (rows width bytes apart), ready for dp_pix_plan.
+ * A mask computed from the frame depends on the data: the released flags then
+ * carry information the Laplace noise does not cover. */
+dppix_status_t dp_pix_edge_mask(dppix_plan_t plan, const void* const* images, int32_t threshold,
+                                uint8_t* const* masks_out, dppix_stream_t stream);
+
 /* ---------------------------------------------------------------------------
  * Forward (Algorithm 3 steps 7-19; Algorithm 2 steps 6-9).
  * Exact integer sums of every subcell over the mirror-padded frame (uint8

@@ -170,6 +170,20 @@ class Plan:
         _lib.check(self.lib.dp_pix_plan(self.handle, None if tab is None else ctypes.c_void_p(tab.data_ptr()),
                                         ctypes.byref(self.store), _stream_handle(stream)))
 
+    def edge_masks(self, images, threshold: int, out=None, stream=None):
+        """Sobel complexity labels of uint8 frames (one (H, W) uint8 mask per
+        frame, 1 where |Gx| + |Gy| of the channel sum >= threshold * C), ready
+        for ``plan``."""
+        torch = _torch()
+        self._check_images(images, "images")
+        if out is None:
+            out = [torch.empty((fp.height, fp.width), dtype=torch.uint8, device=self.device) for fp in self.frames]
+        it = self.pointer_table(images)
+        mt = self.pointer_table(out)
+        _lib.check(self.lib.dp_pix_edge_mask(self.handle, ctypes.c_void_p(it.data_ptr()), int(threshold),
+                                             ctypes.c_void_p(mt.data_ptr()), _stream_handle(stream)))
+        return out
+
     def forward(self, images, out=None, clip=None, stream=None):
         """Noisy statistics into the store; with ``out`` also the reconstruction.
         ``clip``: optional (clip_bg, clip_fg) uint8 tensors of the store's capacities."""

@@ -64,6 +64,7 @@ SYMBOLS = {
     "dp_pix_plan_frame_info": (_st, [_vp, ctypes.c_int32, _P(FrameInfo)]),
     "dp_pix_plan_bind": (_st, [_vp, _vp, ctypes.c_size_t, _vp]),
     "dp_pix_plan": (_st, [_vp, _vp, _P(Store), _vp]),
+    "dp_pix_edge_mask": (_st, [_vp, _vp, ctypes.c_int32, _vp, _vp]),
     "dp_pix_forward": (_st, [_vp, _vp, _P(Store), _vp, _vp, _vp, _vp]),
     "dp_pix_reconstruct": (_st, [_vp, _P(Store), _vp, _vp]),
     "dp_pix_backward": (_st, [_vp, _P(Store), _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),

@@ -621,6 +621,34 @@ dppix_status_t dp_pix_debug_sums(dppix_plan_t p, const void* const* images, cons
     return DPPIX_OK;
 }
 
+dppix_status_t dp_pix_edge_mask(dppix_plan_t p, const void* const* images, int32_t threshold, uint8_t* const* masks_out,
+                                dppix_stream_t stream)
+{
+    dppix_status_t st = need_bound(p);
+    if (st != DPPIX_OK)
+        return st;
+    if (p->any_f32)
+        return fail(DPPIX_EINVAL, "edge masks are computed from U8_HWC frames");
+    if (images == nullptr || masks_out == nullptr)
+        return fail(DPPIX_EINVAL, "images and masks_out are required");
+    if (threshold < 0 || threshold > 4 * 1024)
+        return fail(DPPIX_EINVAL, "threshold must be in 0..4096");
+    TileArgs a = base_args(p);
+    a.images = images;
+    a.masks_out = masks_out;
+    a.edge_threshold = threshold;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    for (const LaunchGroup& g : p->groups) {
+        TileArgs ga = a;
+        ga.sched_offset = g.lo;
+        ga.n_tiles = g.hi - g.lo;
+        hipError_t e = launch_edge_mask(ga, g.C, p->threads, s);
+        if (e != hipSuccess)
+            return dev_fail(e, "edge mask launch");
+    }
+    return DPPIX_OK;
+}
+
 dppix_status_t dp_pix_debug_philox(const uint32_t* in, uint32_t* words, int64_t n, dppix_stream_t stream)
 {
     if (n < 0 || (n > 0 && (in == nullptr || words == nullptr)))

@@ -79,6 +79,9 @@ struct TileArgs {
     float* g_bg;              // per-statistic gradient, store layout
     float* g_fg;
     uint32_t* cell_index;     // frame-local store index of every cell
+    // complexity label
+    uint8_t* const* masks_out;
+    int32_t edge_threshold;
 };
 
 // Host-side launchers (defined in dppix_kernels.hip).
@@ -90,6 +93,7 @@ hipError_t launch_reconstruct(const TileArgs& a, int layout, int C, int threads,
 hipError_t launch_backward(const TileArgs& a, int threads, size_t lds, int grid, int64_t total_pixels,
                            hipStream_t s);
 hipError_t launch_philox(const uint32_t* in, uint32_t* out, int64_t n, hipStream_t s);
+hipError_t launch_edge_mask(const TileArgs& a, int C, int threads, hipStream_t s);
 hipError_t occupancy_forward(int layout, int C, int threads, size_t lds, int* blocks_per_cu);
 
 }  // namespace dppix

@@ -1102,6 +1102,77 @@ __global__ __launch_bounds__(kMaxThreads) void k_backward_spread(TileArgs a)
 }
 
 // ==========================================================================
+// Complexity label from the image (Sec. VI-A names the Sobel operator as one
+// source of the region mask): per real pixel, the 3x3 Sobel responses of the
+// channel sum S, with neighbours past the border mirrored; the pixel is an
+// edge pixel when |Gx| + |Gy| >= threshold * C.  Each tile's real pixels are
+// processed in chunks of kEdgeRows x kEdgeCols whose sums, with a one-pixel
+// mirrored halo, are staged in LDS.
+// ==========================================================================
+constexpr int kEdgeRows = 8;
+constexpr int kEdgeCols = 512;
+
+// Mirror index of a coordinate in [-1, 2L).
+__device__ __forceinline__ int edge_fold(int x, int L, int mode)
+{
+    if (x < 0)
+        return (mode == 0 || L == 1) ? 0 : 1;
+    return fold(x, L, mode);
+}
+
+template <int C>
+__device__ void edge_tile(const TileArgs& a, const FrameRec& F, const TileCoord& tc, uint16_t* S)
+{
+    const int tid = threadIdx.x, NT = blockDim.x;
+    const int b = F.b, H = F.H, W = F.W, pad = F.pad;
+    const int x0c = tc.ct * F.K;
+    const int Kt = min(F.K, F.GC - x0c);
+    const int y0 = tc.r * b, y1 = min(y0 + b, H);
+    const int xa = x0c * b, xb = min((x0c + Kt) * b, W);
+    if (y0 >= H || xa >= W)
+        return;
+    const uint8_t* img = static_cast<const uint8_t*>(a.images[tc.f]);
+    uint8_t* out = a.masks_out[tc.f];
+    const int64_t pitch = F.pitch;
+    const int thr = a.edge_threshold * C;
+    constexpr int SW = kEdgeCols + 2;
+    for (int cy = y0; cy < y1; cy += kEdgeRows) {
+        const int rows = min(kEdgeRows, y1 - cy);
+        for (int cx = xa; cx < xb; cx += kEdgeCols) {
+            const int cols = min(kEdgeCols, xb - cx);
+            // channel sums of the chunk and its halo
+            for (int q = tid; q < (rows + 2) * (cols + 2); q += NT) {
+                const int ly = q / (cols + 2), lx = q - ly * (cols + 2);
+                const int y = edge_fold(cy + ly - 1, H, pad), x = edge_fold(cx + lx - 1, W, pad);
+                const uint8_t* p = img + (int64_t)y * pitch + (int64_t)x * C;
+                uint32_t sum = 0;
+#pragma unroll
+                for (int ch = 0; ch < C; ++ch)
+                    sum += p[ch];
+                S[ly * SW + lx] = (uint16_t)sum;
+            }
+            lds_barrier();
+            for (int q = tid; q < rows * cols; q += NT) {
+                const int ly = q / cols, lx = q - ly * cols;
+                const uint16_t* s = S + ly * SW + lx;   // top-left of the 3x3 window
+                const int gx = (s[2] + 2 * s[SW + 2] + s[2 * SW + 2]) - (s[0] + 2 * s[SW] + s[2 * SW]);
+                const int gy = (s[2 * SW] + 2 * s[2 * SW + 1] + s[2 * SW + 2]) - (s[0] + 2 * s[1] + s[2]);
+                out[(int64_t)(cy + ly) * W + cx + lx] = (uint8_t)(abs(gx) + abs(gy) >= thr);
+            }
+            lds_barrier();
+        }
+    }
+}
+
+template <int C>
+__global__ __launch_bounds__(kMaxThreads) void k_edge_mask(TileArgs a)
+{
+    __shared__ __align__(16) uint16_t S[(kEdgeRows + 2) * (kEdgeCols + 2)];
+    extern __shared__ __align__(16) uint8_t lds[];
+    run_tiles(a, lds, [&](const FrameRec& F, const TileCoord& tc) { edge_tile<C>(a, F, tc, S); });
+}
+
+// ==========================================================================
 // Diagnostics.
 // ==========================================================================
 __global__ void k_philox(const uint32_t* in, uint32_t* out, int64_t n)
@@ -1203,6 +1274,18 @@ hipError_t launch_backward(const TileArgs& a, int threads, size_t lds, int grid,
         return e;
     hipLaunchKernelGGL(k_backward_spread, dim3(g), dim3(threads), 0, s, a);
     return hipGetLastError();
+}
+
+hipError_t launch_edge_mask(const TileArgs& a, int C, int threads, hipStream_t s)
+{
+    TileArgs b = a;
+    b.persistent = 0;
+    switch (C) {
+    case 1: return launch_tiles(k_edge_mask<1>, b, threads, 0, (int)b.n_tiles, s);
+    case 2: return launch_tiles(k_edge_mask<2>, b, threads, 0, (int)b.n_tiles, s);
+    case 3: return launch_tiles(k_edge_mask<3>, b, threads, 0, (int)b.n_tiles, s);
+    default: return launch_tiles(k_edge_mask<4>, b, threads, 0, (int)b.n_tiles, s);
+    }
 }
 
 hipError_t launch_philox(const uint32_t* in, uint32_t* out, int64_t n, hipStream_t s)

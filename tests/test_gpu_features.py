@@ -203,3 +203,27 @@ def test_serving_alone_equals_mix(dev):
         torch.cuda.synchronize()
         alone = plan.store_host()[0]
         assert _store_equal(q.result, alone), (q.rid, q.stream, q.frame_index)
+
+
+@pytest.mark.parametrize("H,W,C,b,sb,T,pad", [(75, 97, 3, 16, 4, 60, 0), (270, 480, 3, 32, 8, 40, 0),
+                                              (33, 40, 1, 8, 2, 30, 1), (1080, 1920, 3, 32, 8, 48, 0),
+                                              (5, 3, 3, 8, 4, 10, 0)])
+def test_edge_mask_label_matches_oracle(dev, H, W, C, b, sb, T, pad):
+    """Sobel complexity labels bit-exact against the oracle, then the whole
+    path driven by them against the oracle driven by the oracle's labels."""
+    say("case: edge mask", H, W, C, b, sb, T, pad)
+    r = np.random.Generator(np.random.PCG64(H * W))
+    img = synth.gradient_image(r, H, W, C)
+    img[H // 4: H // 2, W // 5: W // 2] = 250          # a bright block: strong edges
+    fp = dp.FrameParams(H, W, C, dp.U8_HWC, b=b, sb=sb, m=16, eps_bg=1.0, eps_fg=0.3, tau=4, pad_mode=pad, seed=6)
+    plan = dp.Plan([fp], device=dev)
+    ti = torch.from_numpy(img).to(dev)
+    masks = plan.edge_masks([ti], T)
+    out = torch.empty_like(ti)
+    plan.plan(masks)
+    plan.forward([ti], out=[out])
+    torch.cuda.synchronize()
+    want_mask = oracle.edge_mask(img, T, pad)
+    assert np.array_equal(masks[0].cpu().numpy(), want_mask)
+    want = oracle.forward(img, want_mask, oracle_params(fp))
+    compare_frame(plan.store_host()[0], want, out.cpu().numpy(), "edge-labelled")
