@@ -82,6 +82,9 @@ def _load():
         lib.orc_edge_mask.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_int32,
                                       ctypes.c_int32, vp]
         lib.orc_edge_mask.restype = ctypes.c_int32
+        lib.orc_metrics.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp, P(ctypes.c_double),
+                                    P(ctypes.c_double)]
+        lib.orc_metrics.restype = ctypes.c_int32
         _lib = lib
     return _lib
 
@@ -236,6 +239,23 @@ def edge_mask(img, threshold: int, pad_mode: int = PAD_SYMMETRIC):
     if _load().orc_edge_mask(H, W, C, _ptr(x), int(threshold), pad_mode, _ptr(out)):
         raise ValueError("bad edge-mask arguments")
     return out
+
+
+def metrics(x, y):
+    """(MSE, SSIM) between two HWC (or HW) images of the same shape."""
+    a = np.asarray(x)
+    b = np.asarray(y)
+    if a.ndim == 2:
+        a, b = a[:, :, None], b[:, :, None]
+    if a.shape != b.shape:
+        raise ValueError("shape mismatch")
+    H, W, C = a.shape
+    xa = np.ascontiguousarray(a, dtype=np.float64)
+    ya = np.ascontiguousarray(b, dtype=np.float64)
+    mse, ssim = ctypes.c_double(), ctypes.c_double()
+    if _load().orc_metrics(H, W, C, _ptr(xa), _ptr(ya), ctypes.byref(mse), ctypes.byref(ssim)):
+        raise ValueError("metrics need frames of at least 7 x 7")
+    return mse.value, ssim.value
 
 
 def backward(img, mask, grad_out, p: Params):

@@ -338,6 +338,45 @@ int32_t orc_edge_mask(int32_t M, int32_t N, int32_t C, const double* img, int32_
     return 0;
 }
 
+int32_t orc_metrics(int32_t M, int32_t N, int32_t C, const double* x, const double* y, double* mse, double* ssim)
+{
+    if (M < 7 || N < 7 || C < 1)
+        return 1;
+    const int64_t total = (int64_t)M * N * C;
+    double se = 0.0;
+    for (int64_t q = 0; q < total; ++q)
+        se += (x[q] - y[q]) * (x[q] - y[q]);
+    *mse = se / (double)total;
+
+    const double R = 255.0, c1 = (0.01 * R) * (0.01 * R), c2 = (0.03 * R) * (0.03 * R);
+    const double np = 49.0;
+    double acc = 0.0;
+    int64_t windows = 0;
+    for (int64_t ch = 0; ch < C; ++ch)
+        for (int64_t i = 3; i < M - 3; ++i)
+            for (int64_t j = 3; j < N - 3; ++j) {
+                double sx = 0, sy = 0, sxx = 0, syy = 0, sxy = 0;
+                for (int64_t di = -3; di <= 3; ++di)
+                    for (int64_t dj = -3; dj <= 3; ++dj) {
+                        double a = x[((i + di) * N + (j + dj)) * C + ch];
+                        double b = y[((i + di) * N + (j + dj)) * C + ch];
+                        sx += a; sy += b; sxx += a * a; syy += b * b; sxy += a * b;
+                    }
+                double ux = sx / np, uy = sy / np;
+                /* sample variances: divide the centred sums by np - 1 */
+                double vx = (sxx / np - ux * ux) * np / (np - 1.0);
+                double vy = (syy / np - uy * uy) * np / (np - 1.0);
+                double vxy = (sxy / np - ux * uy) * np / (np - 1.0);
+                double s = ((2.0 * ux * uy + c1) * (2.0 * vxy + c2)) / ((ux * ux + uy * uy + c1) * (vx + vy + c2));
+                acc += s;
+                ++windows;
+            }
+    /* every channel has the same number of windows: the mean over all windows
+     * equals the mean of the per-channel means */
+    *ssim = acc / (double)windows;
+    return 0;
+}
+
 /* Restoration from the stored metadata: broadcast each stored scalar over its
  * grid or subgrid in the padded frame, then crop. */
 int32_t orc_reconstruct(const orc_params_t* p, const uint8_t* flags, const float* bg,

@@ -115,6 +115,16 @@ int32_t orc_forward(const orc_params_t* p, const double* img, const uint8_t* mas
 int32_t orc_edge_mask(int32_t M, int32_t N, int32_t C, const double* img, int32_t threshold, int32_t pad_mode,
                       uint8_t* out);
 
+/*
+ * Utility metrics of the paper's runtime/utility study (Sec. VII-A): mean
+ * squared error and SSIM (Wang, Bovik, Sheikh, Simoncelli 2004) between two
+ * M x N x C images (HWC doubles, values 0..255).  SSIM uses 7 x 7 windows
+ * with equal weights, sample (co)variances (divisor 48), K1 = 0.01,
+ * K2 = 0.03, dynamic range 255; the SSIM map is averaged over the windows
+ * that lie fully inside the frame and over channels.  Needs M, N >= 7.
+ */
+int32_t orc_metrics(int32_t M, int32_t N, int32_t C, const double* x, const double* y, double* mse, double* ssim);
+
 /* Reconstruction from the compact store only (flags, bg, fg, b, s_b, M x N). */
 int32_t orc_reconstruct(const orc_params_t* p, const uint8_t* flags, const float* bg,
                         const float* fg, float* recon_f32, uint8_t* recon_u8);
