@@ -127,6 +127,7 @@ typedef struct {
     size_t grad_scratch_bytes; /* device scratch for dp_pix_backward            */
     int64_t n_tiles;         /* work tiles of the batch                         */
     int64_t total_pixels;    /* sum of height*width                             */
+    size_t metrics_scratch_bytes; /* device scratch for dp_pix_metrics          */
 } dppix_sizes_t;
 
 typedef struct {
@@ -182,6 +183,17 @@ dppix_status_t dp_pix_plan(dppix_plan_t plan, const uint8_t* const* masks, const
  * carry information the Laplace noise does not cover. */
 dppix_status_t dp_pix_edge_mask(dppix_plan_t plan, const void* const* images, int32_t threshold,
                                 uint8_t* const* masks_out, dppix_stream_t stream);
+
+/* Utility of a release, as the paper measures it (Sec. VII-A): per frame the
+ * mean squared error and SSIM (Wang et al. 2004) between images[f] and
+ * recons[f] (U8_HWC frames of the plan's geometry, e.g. a frame and its
+ * reconstruction).  SSIM: 7 x 7 equal-weight windows lying inside the frame,
+ * sample covariances, K1 = 0.01, K2 = 0.03, range 255, averaged over windows
+ * and channels (0 for frames under 7 x 7).  out: device array of n_frames
+ * (MSE, SSIM) double pairs; scratch: metrics_scratch_bytes of device memory.
+ * Window sums are exact integers; the result does not depend on scheduling. */
+dppix_status_t dp_pix_metrics(dppix_plan_t plan, const void* const* images, const void* const* recons, void* scratch,
+                              size_t scratch_bytes, double* out, dppix_stream_t stream);
 
 /* ---------------------------------------------------------------------------
  * Forward (Algorithm 3 steps 7-19; Algorithm 2 steps 6-9).

@@ -184,6 +184,21 @@ class Plan:
                                              ctypes.c_void_p(mt.data_ptr()), _stream_handle(stream)))
         return out
 
+    def metrics(self, images, recons, stream=None):
+        """Per-frame (MSE, SSIM) between uint8 frames and their reconstructions,
+        computed on the GPU; returns a (n_frames, 2) float64 tensor on the device."""
+        torch = _torch()
+        self._check_images(images, "images")
+        self._check_images(recons, "recons")
+        scratch = torch.empty(max(self.sizes.metrics_scratch_bytes, 256), dtype=torch.uint8, device=self.device)
+        out = torch.empty((len(self.frames), 2), dtype=torch.float64, device=self.device)
+        it = self.pointer_table(images)
+        rt = self.pointer_table(recons)
+        _lib.check(self.lib.dp_pix_metrics(self.handle, ctypes.c_void_p(it.data_ptr()), ctypes.c_void_p(rt.data_ptr()),
+                                           ctypes.c_void_p(scratch.data_ptr()), scratch.numel(),
+                                           ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
+        return out
+
     def forward(self, images, out=None, clip=None, stream=None):
         """Noisy statistics into the store; with ``out`` also the reconstruction.
         ``clip``: optional (clip_bg, clip_fg) uint8 tensors of the store's capacities."""

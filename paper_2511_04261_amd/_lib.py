@@ -42,7 +42,7 @@ class Sizes(ctypes.Structure):
                 ("fg_capacity", ctypes.c_size_t), ("flag_bytes", ctypes.c_size_t),
                 ("clip_bytes_bg", ctypes.c_size_t), ("clip_bytes_fg", ctypes.c_size_t),
                 ("grad_scratch_bytes", ctypes.c_size_t), ("n_tiles", ctypes.c_int64),
-                ("total_pixels", ctypes.c_int64)]
+                ("total_pixels", ctypes.c_int64), ("metrics_scratch_bytes", ctypes.c_size_t)]
 
 
 class FrameInfo(ctypes.Structure):
@@ -74,6 +74,7 @@ SYMBOLS = {
     "dp_pix_graph_destroy": (None, [_vp]),
     "dp_pix_debug_sums": (_st, [_vp, _vp, _P(Store), _vp, _vp, _vp]),
     "dp_pix_debug_philox": (_st, [_vp, _vp, ctypes.c_int64, _vp]),
+    "dp_pix_metrics": (_st, [_vp, _vp, _vp, _vp, ctypes.c_size_t, _vp, _vp]),
     "dp_pix_status_string": (ctypes.c_char_p, [_st]),
     "dp_pix_last_error": (ctypes.c_char_p, []),
     "dp_pix_version": (ctypes.c_char_p, []),

@@ -343,6 +343,7 @@ dppix_status_t dp_pix_plan_sizes(dppix_plan_t p, dppix_sizes_t* out)
     out->clip_bytes_bg = p->bg_cap;
     out->clip_bytes_fg = p->fg_cap;
     out->grad_scratch_bytes = align256(4 * p->bg_cap) + align256(4 * p->fg_cap) + align256(4 * (size_t)p->total_cells);
+    out->metrics_scratch_bytes = align256(16 * (size_t)p->n_tiles);
     out->n_tiles = p->n_tiles;
     out->total_pixels = p->total_pixels;
     return DPPIX_OK;
@@ -646,6 +647,37 @@ dppix_status_t dp_pix_edge_mask(dppix_plan_t p, const void* const* images, int32
         if (e != hipSuccess)
             return dev_fail(e, "edge mask launch");
     }
+    return DPPIX_OK;
+}
+
+dppix_status_t dp_pix_metrics(dppix_plan_t p, const void* const* images, const void* const* recons, void* scratch,
+                              size_t scratch_bytes, double* out, dppix_stream_t stream)
+{
+    dppix_status_t st = need_bound(p);
+    if (st != DPPIX_OK)
+        return st;
+    if (p->any_f32)
+        return fail(DPPIX_EINVAL, "metrics are computed on U8_HWC frames");
+    if (images == nullptr || recons == nullptr || out == nullptr)
+        return fail(DPPIX_EINVAL, "images, recons and out are required");
+    if (scratch == nullptr || scratch_bytes < (size_t)(16 * p->n_tiles))
+        return fail(DPPIX_ENOMEM, "scratch smaller than metrics_scratch_bytes");
+    TileArgs a = base_args(p);
+    a.images = images;
+    a.outs = const_cast<void* const*>(recons);
+    a.met_partial = static_cast<double*>(scratch);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    for (const LaunchGroup& g : p->groups) {
+        TileArgs ga = a;
+        ga.sched_offset = g.lo;
+        ga.n_tiles = g.hi - g.lo;
+        hipError_t e = launch_metrics(ga, g.C, p->threads, s);
+        if (e != hipSuccess)
+            return dev_fail(e, "metrics launch");
+    }
+    hipError_t e = launch_metrics_reduce(a, out, s);
+    if (e != hipSuccess)
+        return dev_fail(e, "metrics reduce launch");
     return DPPIX_OK;
 }
 

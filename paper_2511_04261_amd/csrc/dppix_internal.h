@@ -82,6 +82,8 @@ struct TileArgs {
     // complexity label
     uint8_t* const* masks_out;
     int32_t edge_threshold;
+    // utility metrics: per tile (SSIM partial sum, squared-error sum)
+    double* met_partial;
 };
 
 // Host-side launchers (defined in dppix_kernels.hip).
@@ -94,6 +96,8 @@ hipError_t launch_backward(const TileArgs& a, int threads, size_t lds, int grid,
                            hipStream_t s);
 hipError_t launch_philox(const uint32_t* in, uint32_t* out, int64_t n, hipStream_t s);
 hipError_t launch_edge_mask(const TileArgs& a, int C, int threads, hipStream_t s);
+hipError_t launch_metrics(const TileArgs& a, int C, int threads, hipStream_t s);
+hipError_t launch_metrics_reduce(const TileArgs& a, double* out, hipStream_t s);
 hipError_t occupancy_forward(int layout, int C, int threads, size_t lds, int* blocks_per_cu);
 
 }  // namespace dppix

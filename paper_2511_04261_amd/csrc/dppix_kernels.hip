@@ -1173,6 +1173,147 @@ __global__ __launch_bounds__(kMaxThreads) void k_edge_mask(TileArgs a)
 }
 
 // ==========================================================================
+// Utility metrics of the paper's evaluation (Sec. VII-A): MSE and SSIM
+// (Wang et al. 2004; 7 x 7 equal-weight windows fully inside the frame,
+// sample covariances, K1 = 0.01, K2 = 0.03, range 255, channels averaged).
+// With uint8 inputs every window sum of x, y, x^2, y^2 and xy is an integer
+// below 2^24, so the sums are exact (uint32, separable: 7-wide row sums in
+// LDS, then 7-high column sums); only the SSIM expression is fp64.  Each
+// tile writes its partial sums; k_metrics_reduce adds them per frame in tile
+// order (deterministic).
+// ==========================================================================
+constexpr int kMetRows = 8;     // window-centre rows per chunk
+constexpr int kMetCols = 128;   // window-centre columns per chunk
+
+struct MetLds {
+    uint8_t x[kMetRows + 6][kMetCols + 8];
+    uint8_t y[kMetRows + 6][kMetCols + 8];
+    uint32_t h[5][kMetRows + 6][kMetCols];
+    double red[kMaxThreads / 64];
+    unsigned long long red_se[kMaxThreads / 64];
+};
+
+template <int C>
+__device__ void metrics_tile(const TileArgs& a, const FrameRec& F, const TileCoord& tc, MetLds& L)
+{
+    const int tid = threadIdx.x, NT = blockDim.x;
+    const int b = F.b, H = F.H, W = F.W;
+    const int x0c = tc.ct * F.K;
+    const int Kt = min(F.K, F.GC - x0c);
+    const int y0 = tc.r * b, y1 = min(y0 + b, H);
+    const int xa = x0c * b, xb = min((x0c + Kt) * b, W);
+    const uint8_t* X = static_cast<const uint8_t*>(a.images[tc.f]);
+    const uint8_t* Y = static_cast<const uint8_t*>(a.outs[tc.f]);
+    const int64_t pitch = F.pitch;
+    double ssim_acc = 0.0;
+    unsigned long long se = 0;
+    // squared error over the tile's real pixels
+    if (y0 < H && xa < W) {
+        const int wpx = (xb - xa) * C;
+        for (int64_t q = tid; q < (int64_t)(y1 - y0) * wpx; q += NT) {
+            const int yy = y0 + (int)(q / wpx), xx = (int)(q % wpx);
+            const int d = (int)X[(int64_t)yy * pitch + (int64_t)xa * C + xx] - (int)Y[(int64_t)yy * pitch + (int64_t)xa * C + xx];
+            se += (unsigned long long)(d * d);
+        }
+    }
+    // SSIM windows centred in this tile's real pixels, 3 away from every edge
+    const int cy0 = max(y0, 3), cy1 = min(y1, H - 3);
+    const int cx0 = max(xa, 3), cx1 = min(xb, W - 3);
+    const double R = 255.0, c1 = (0.01 * R) * (0.01 * R), c2 = (0.03 * R) * (0.03 * R);
+    for (int ch = 0; ch < C; ++ch)
+        for (int cy = cy0; cy < cy1; cy += kMetRows) {
+            const int rows = min(kMetRows, cy1 - cy);
+            for (int cx = cx0; cx < cx1; cx += kMetCols) {
+                const int cols = min(kMetCols, cx1 - cx);
+                for (int q = tid; q < (rows + 6) * (cols + 6); q += NT) {
+                    const int ly = q / (cols + 6), lx = q - ly * (cols + 6);
+                    const int64_t at = (int64_t)(cy - 3 + ly) * pitch + (int64_t)(cx - 3 + lx) * C + ch;
+                    L.x[ly][lx] = X[at];
+                    L.y[ly][lx] = Y[at];
+                }
+                lds_barrier();
+                for (int q = tid; q < (rows + 6) * cols; q += NT) {
+                    const int ly = q / cols, lx = q - ly * cols;
+                    uint32_t sx = 0, sy = 0, sxx = 0, syy = 0, sxy = 0;
+#pragma unroll
+                    for (int k = 0; k < 7; ++k) {
+                        const uint32_t u = L.x[ly][lx + k], v = L.y[ly][lx + k];
+                        sx += u; sy += v; sxx += u * u; syy += v * v; sxy += u * v;
+                    }
+                    L.h[0][ly][lx] = sx; L.h[1][ly][lx] = sy; L.h[2][ly][lx] = sxx;
+                    L.h[3][ly][lx] = syy; L.h[4][ly][lx] = sxy;
+                }
+                lds_barrier();
+                for (int q = tid; q < rows * cols; q += NT) {
+                    const int ly = q / cols, lx = q - ly * cols;
+                    uint32_t s[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+                    for (int k = 0; k < 7; ++k)
+#pragma unroll
+                        for (int t = 0; t < 5; ++t)
+                            s[t] += L.h[t][ly + k][lx];
+                    const double np = 49.0;
+                    const double ux = s[0] / np, uy = s[1] / np;
+                    const double vx = ((double)s[2] / np - ux * ux) * np / (np - 1.0);
+                    const double vy = ((double)s[3] / np - uy * uy) * np / (np - 1.0);
+                    const double vxy = ((double)s[4] / np - ux * uy) * np / (np - 1.0);
+                    ssim_acc += ((2.0 * ux * uy + c1) * (2.0 * vxy + c2)) / ((ux * ux + uy * uy + c1) * (vx + vy + c2));
+                }
+                lds_barrier();
+            }
+        }
+    // workgroup reduction in a fixed order
+    const int lane = tid & 63, wid = tid >> 6;
+    for (int d = 32; d > 0; d >>= 1) {
+        ssim_acc += __shfl_down(ssim_acc, d, 64);
+        se += __shfl_down(se, d, 64);
+    }
+    if (lane == 0) {
+        L.red[wid] = ssim_acc;
+        L.red_se[wid] = se;
+    }
+    lds_barrier();
+    if (tid == 0) {
+        double t = 0.0;
+        unsigned long long e = 0;
+        for (int w = 0; w < (NT + 63) / 64; ++w) {
+            t += L.red[w];
+            e += L.red_se[w];
+        }
+        a.met_partial[2 * tc.t] = t;
+        reinterpret_cast<unsigned long long*>(a.met_partial)[2 * tc.t + 1] = e;
+    }
+    lds_barrier();
+}
+
+template <int C>
+__global__ __launch_bounds__(kMaxThreads) void k_metrics(TileArgs a)
+{
+    __shared__ MetLds L;
+    extern __shared__ __align__(16) uint8_t lds[];
+    run_tiles(a, lds, [&](const FrameRec& F, const TileCoord& tc) { metrics_tile<C>(a, F, tc, L); });
+}
+
+// One thread per frame: MSE = sum of squared errors / (H W C); SSIM = sum of
+// window values / (windows * C), partials added in tile order.
+__global__ void k_metrics_reduce(TileArgs a, double* out)
+{
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= a.n_frames)
+        return;
+    const FrameRec F = a.frames[f];
+    double t = 0.0;
+    unsigned long long e = 0;
+    for (int64_t i = 0; i < (int64_t)F.GR * F.TX; ++i) {
+        t += a.met_partial[2 * (F.tile_base + i)];
+        e += reinterpret_cast<const unsigned long long*>(a.met_partial)[2 * (F.tile_base + i) + 1];
+    }
+    const double windows = (double)max(F.H - 6, 0) * (double)max(F.W - 6, 0) * F.C;
+    out[2 * f + 0] = (double)e / ((double)F.H * F.W * F.C);
+    out[2 * f + 1] = windows > 0 ? t / windows : 0.0;
+}
+
+// ==========================================================================
 // Diagnostics.
 // ==========================================================================
 __global__ void k_philox(const uint32_t* in, uint32_t* out, int64_t n)
@@ -1286,6 +1427,24 @@ hipError_t launch_edge_mask(const TileArgs& a, int C, int threads, hipStream_t s
     case 3: return launch_tiles(k_edge_mask<3>, b, threads, 0, (int)b.n_tiles, s);
     default: return launch_tiles(k_edge_mask<4>, b, threads, 0, (int)b.n_tiles, s);
     }
+}
+
+hipError_t launch_metrics(const TileArgs& a, int C, int threads, hipStream_t s)
+{
+    TileArgs b = a;
+    b.persistent = 0;
+    switch (C) {
+    case 1: return launch_tiles(k_metrics<1>, b, threads, 0, (int)b.n_tiles, s);
+    case 2: return launch_tiles(k_metrics<2>, b, threads, 0, (int)b.n_tiles, s);
+    case 3: return launch_tiles(k_metrics<3>, b, threads, 0, (int)b.n_tiles, s);
+    default: return launch_tiles(k_metrics<4>, b, threads, 0, (int)b.n_tiles, s);
+    }
+}
+
+hipError_t launch_metrics_reduce(const TileArgs& a, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_metrics_reduce, dim3((unsigned)((a.n_frames + 63) / 64)), dim3(64), 0, s, a, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_philox(const uint32_t* in, uint32_t* out, int64_t n, hipStream_t s)

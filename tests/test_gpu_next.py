@@ -1,0 +1,69 @@
+"""GPU tests of the rows after the hot path: utility metrics (MSE, SSIM) of a
+release against the oracle, and the storage study."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from tests.helpers import oracle_params
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+dp = pytest.importorskip("paper_2511_04261_amd")
+from paper_2511_04261_amd import synth  # noqa: E402
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def test_metrics_match_oracle(dev):
+    """MSE exact (integer squared errors), SSIM within 1e-9 of the oracle, on
+    a mixed batch of frames and their DP reconstructions."""
+    say("case: metrics")
+    r = np.random.Generator(np.random.PCG64(31))
+    shapes = [(64, 80, 3), (37, 300, 1), (270, 480, 3), (7, 7, 2), (5, 30, 3), (1080, 1920, 3)]
+    frames, imgs = [], []
+    for i, (H, W, C) in enumerate(shapes):
+        frames.append(dp.FrameParams(H, W, C, dp.U8_HWC, b=16, sb=4, m=16, eps_bg=1.0, eps_fg=0.3, tau=1, seed=4,
+                                     frame_index=i))
+        imgs.append(synth.gradient_image(r, H, W, C))
+    plan = dp.Plan(frames, device=dev)
+    ti = [torch.from_numpy(x).to(dev) for x in imgs]
+    outs = [torch.empty_like(t) for t in ti]
+    plan.plan(None)
+    plan.forward(ti, out=outs)
+    got = plan.metrics(ti, outs).cpu().numpy()
+    for i, (H, W, C) in enumerate(shapes):
+        rec = outs[i].cpu().numpy()
+        if H >= 7 and W >= 7:
+            mse, ssim = oracle.metrics(imgs[i], rec)
+            assert got[i, 0] == pytest.approx(mse, rel=1e-15, abs=0), i
+            assert abs(got[i, 1] - ssim) <= 1e-9, (i, got[i, 1], ssim)
+        else:
+            assert got[i, 0] == pytest.approx(((imgs[i].astype(float) - rec.astype(float)) ** 2).mean(), rel=1e-15)
+            assert got[i, 1] == 0.0
+    same = plan.metrics(ti, ti).cpu().numpy()
+    assert (same[:, 0] == 0).all() and np.allclose(same[[0, 1, 2, 3, 5], 1], 1.0, atol=1e-12)
+
+
+def test_storage_study_small(dev):
+    """Encoded store vs PNG of the reconstruction over grid sizes and subgrid
+    factors: the store shrinks with b, grows with n, and decodes exactly."""
+    say("case: storage study")
+    from paper_2511_04261_amd import store_codec as sc
+    specs = synth.region_batch(2, height=270, width=480)
+    rows = sc.storage_study(specs, grid_sizes=(4, 16, 64), factors=(1, 4), device=dev)
+    by = {(r["b"], r["n"]): r for r in rows}
+    assert by[(64, 1)]["store_u8"] < by[(16, 1)]["store_u8"] < by[(4, 1)]["store_u8"]
+    assert by[(16, 4)]["store_u8"] > by[(16, 1)]["store_u8"]
+    assert all(r["store_u8"] < r["png"] for r in rows if r["b"] >= 16)
