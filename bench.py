@@ -94,49 +94,54 @@ def alg_bytes(plan):
     return dict(image=px, mask=mask, recon=px, store=st, forward=2 * px + st, step=2 * px + mask + st)
 
 
-def time_steps(step_fn, warmup, steps, stream, fwd_events=None):
+def time_steps(step_fn, warmup, steps):
     import torch
     for _ in range(warmup):
-        step_fn(None)
+        step_fn()
     torch.cuda.synchronize()
-    evs = []
     t0 = time.perf_counter()
     for _ in range(steps):
-        step_fn(evs if fwd_events else None)
+        step_fn()
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    fwd_ms = None
-    if fwd_events and evs:
-        fwd_ms = sum(a.elapsed_time(b) for a, b in evs) / len(evs)
-    return dt, fwd_ms
+    return time.perf_counter() - t0
+
+
+def time_launches(call, n, stream):
+    """Average duration of one launch: n back-to-back launches of the same
+    call between two HIP events on the stream the kernels run on."""
+    import torch
+    call()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(n):
+        call()
+    b.record(stream)
+    b.synchronize()
+    return a.elapsed_time(b) / n
 
 
 def run_batched(frames_s, dev, warmup, steps, graph=False, threads=0, persistent=0):
     import torch
     plan, imgs, masks, outs = build_batch(frames_s, dev, persistent=persistent, threads=threads)
     stream = torch.cuda.current_stream()
-    g = plan.graph(masks, imgs, outs) if graph else None
+    plan_call, fwd_call = plan.bound_calls(masks, imgs, outs, stream)
+    g = plan.graph(masks, imgs, outs, stream) if graph else None
 
-    def step(evs):
-        if g is not None and evs is None:
-            g.launch()
-            return
-        plan.plan(masks)
-        if evs is not None:
-            a = torch.cuda.Event(enable_timing=True)
-            b = torch.cuda.Event(enable_timing=True)
-            a.record(stream)
-            plan.forward(imgs, out=outs)
-            b.record(stream)
-            evs.append((a, b))
+    def step():
+        if g is not None:
+            g.launch(stream)
         else:
-            plan.forward(imgs, out=outs)
+            plan_call()
+            fwd_call()
 
-    # graph replays for the step time; an eager pass with events for the kernel time
-    dt, _ = time_steps(step, warmup, steps, stream, fwd_events=False)
-    _, fwd_ms = time_steps(step, 1, steps, stream, fwd_events=True)
+    # the step time (plan + forward per step); then each kernel's launch time
+    dt = time_steps(step, warmup, steps)
+    fwd_ms = time_launches(fwd_call, max(steps, 10), stream)
+    plan_ms = time_launches(plan_call, max(steps, 10), stream)
     ab = alg_bytes(plan)
-    return dict(plan=plan, seconds=dt, step_ms=1e3 * dt / steps, fwd_ms=fwd_ms, bytes=ab,
+    return dict(plan=plan, seconds=dt, step_ms=1e3 * dt / steps, fwd_ms=fwd_ms, plan_ms=plan_ms, bytes=ab,
                 pixels=sum(fp.height * fp.width for fp in plan.frames))
 
 
@@ -146,12 +151,14 @@ def run_per_frame(frames_s, dev, warmup, steps):
     per = [build_batch([s], dev, persistent=False) for s in frames_s]
     stream = torch.cuda.current_stream()
 
-    def step(evs):
-        for plan, imgs, masks, outs in per:
-            plan.plan(masks)
-            plan.forward(imgs, out=outs)
+    calls = [p[0].bound_calls(p[2], p[1], p[3], stream) for p in per]
 
-    dt, _ = time_steps(step, warmup, steps, stream)
+    def step():
+        for plan_call, fwd_call in calls:
+            plan_call()
+            fwd_call()
+
+    dt = time_steps(step, warmup, steps)
     px = sum(s.height * s.width for s in frames_s)
     b = sum(alg_bytes(p[0])["step"] for p in per)
     return dict(seconds=dt, step_ms=1e3 * dt / steps, pixels=px, bytes=b)
@@ -188,10 +195,12 @@ def counters_run(frames_s, dev, launches=3, copy_bytes=1 << 30):
     (the calibration of FETCH_SIZE / WRITE_SIZE), then a few plan + forward
     launches of the headline workload."""
     import torch
-    src = torch.empty(copy_bytes, dtype=torch.uint8, device=dev).fill_(1)
+    # an elementwise kernel (bitwise_not over int32) reads and writes exactly
+    # copy_bytes; copy_() would be a runtime memcpy that the counters do not see
+    src = torch.empty(copy_bytes // 4, dtype=torch.int32, device=dev).fill_(1)
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
-    dst.copy_(src)
+    torch.bitwise_not(src, out=dst)
     torch.cuda.synchronize()
     del src, dst
     plan, imgs, masks, outs = build_batch(frames_s, dev)
@@ -290,8 +299,12 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(fwd_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(fwd_gbs / HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else round(traffic),
-                     "kernel": "k_forward", "alg_bytes_per_launch": ab["forward"],
-                     "avg_launch_ms": round(res["fwd_ms"], 4)},
+                     "kernel": "k_forward_u8<3>", "alg_bytes_per_launch": ab["forward"],
+                     "avg_launch_ms": round(res["fwd_ms"], 4),
+                     "timing": "HIP events around back-to-back launches on the library stream"},
+        "plan_kernel": {"kernel": "k_plan", "avg_launch_ms": round(res["plan_ms"], 4),
+                        "alg_bytes_per_launch": ab["mask"],
+                        "gbs": round(ab["mask"] / (res["plan_ms"] * 1e-3) / 1e9, 1)},
         "step_gbs_algorithmic": round(step_gbs, 1),
         "step_frac_hbm": round(step_gbs / HBM_PEAK_GBS, 4),
     }

@@ -253,6 +253,31 @@ class Plan:
         return (torch.empty(max(self.sizes.clip_bytes_bg, 1), dtype=torch.uint8, device=self.device),
                 torch.empty(max(self.sizes.clip_bytes_fg, 1), dtype=torch.uint8, device=self.device))
 
+    def bound_calls(self, masks, images, out=None, stream=None):
+        """Validate once and return zero-argument callables ``(plan, forward)``
+        that issue dp_pix_plan / dp_pix_forward on ``stream`` with the
+        arguments already marshalled (for back-to-back launches)."""
+        self._check_images(images, "images")
+        if out is not None:
+            self._check_images(out, "out")
+        mt = self.pointer_table(masks)
+        it = self.pointer_table(images)
+        ot = self.pointer_table(out)
+        lib, h, st, s = self.lib, self.handle, ctypes.byref(self.store), _stream_handle(stream)
+        mp = None if mt is None else ctypes.c_void_p(mt.data_ptr())
+        ip = ctypes.c_void_p(it.data_ptr())
+        op = None if ot is None else ctypes.c_void_p(ot.data_ptr())
+        keep = (mt, it, ot)
+
+        def plan_call():
+            _lib.check(lib.dp_pix_plan(h, mp, st, s))
+
+        def forward_call():
+            _lib.check(lib.dp_pix_forward(h, ip, st, None, None, op, s))
+
+        plan_call.keep = forward_call.keep = keep
+        return plan_call, forward_call
+
     def graph(self, masks, images, out=None, stream=None) -> "Graph":
         """Capture plan + forward (+ fused reconstruction) into a HIP graph."""
         return Graph(self, masks, images, out, stream)

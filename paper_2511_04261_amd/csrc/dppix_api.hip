@@ -32,7 +32,9 @@ dppix_status_t dev_fail(hipError_t e, const char* what)
 }
 
 constexpr int kDefaultThreads = 256;
-constexpr int64_t kTileBytesTarget = 4096;  // padded bytes per tile row (u8)
+constexpr int64_t kTileBytesTarget = 2048;  // padded bytes per tile row (u8)
+constexpr int64_t kPlanCellsMax = 2048;     // cells per band of one plan unit
+constexpr int64_t kPlanLdsMax = 32 * 1024;  // LDS of one plan unit
 constexpr int64_t kTileLdsTarget = 48 * 1024;
 constexpr int64_t kTileLdsMax = 150 * 1024;
 constexpr int kMaxDim = 1 << 24;
@@ -54,6 +56,7 @@ struct dppix_plan {
     std::vector<int32_t> sched_frame;
     std::vector<int64_t> sched_base;
     int64_t n_tiles = 0;
+    int64_t n_units = 0;
     int64_t total_cells = 0;
     int64_t total_fine = 0;
     int64_t total_pixels = 0;
@@ -158,7 +161,6 @@ void choose_tiles(FrameRec& F, int32_t requested)
     // keep every tile kind of this frame within the LDS target
     while (F.K > 1) {
         size_t need = std::max(frame_lds(kind_fwd(F), F), frame_lds(kind_rec(F), F));
-        need = std::max(need, frame_lds(kClassify, F));
         if (F.layout == DPPIX_F32_CHW)
             need = std::max(need, frame_lds(kBwd, F));
         if ((int64_t)need <= kTileLdsTarget)
@@ -166,6 +168,20 @@ void choose_tiles(FrameRec& F, int32_t requested)
         F.K = std::max(1, F.K / 2);
     }
     F.TX = (F.GC + F.K - 1) / F.K;
+    // Plan units: whole tiles of a band (at most kPlanCellsMax cells), and as
+    // many bands as keep about one 16-row strip item per lane of a 256-lane
+    // workgroup (several bands' worth of rows per lane when b < 16).
+    F.ctx = (int32_t)std::max<int64_t>(1, std::min<int64_t>(F.TX, kPlanCellsMax / F.K));
+    const int64_t kc = std::min<int64_t>((int64_t)F.ctx * F.K, F.GC);
+    const int64_t nstr = (kc * F.b + 15) / 16;
+    const int64_t rows = std::min<int64_t>(F.b, 16);
+    const int64_t items = nstr * ((F.b + rows - 1) / rows);
+    int64_t cnb = (int64_t)kDefaultThreads * std::max<int64_t>(1, 16 / F.b) / items;
+    cnb = std::max<int64_t>(1, std::min<int64_t>(cnb, F.GR));
+    while (cnb > 1 && plan_lds((int)cnb, F.ctx, F.K) > kPlanLdsMax)
+        --cnb;
+    F.cnb = (int32_t)cnb;
+    F.cunits = (int32_t)(((F.GR + cnb - 1) / cnb) * ((F.TX + F.ctx - 1) / F.ctx));
 }
 
 }  // namespace
@@ -230,6 +246,7 @@ dppix_status_t dp_pix_plan_create(const dppix_frame_desc_t* descs, int32_t n_fra
         F.key1 = (uint32_t)(d.seed >> 32);
         F.fi0 = (uint32_t)(d.frame_index & 0xFFFFFFFFu);
         F.fi1 = (uint32_t)(d.frame_index >> 32);
+        F.off32 = ((int64_t)d.b_bg + 1) * d.pitch * (d.layout == DPPIX_F32_CHW ? 4 : 1) < ((int64_t)1 << 31);
         choose_tiles(F, d.tile_cells);
         {
             size_t need = std::max(frame_lds(kind_fwd(F), F), frame_lds(kind_rec(F), F));
@@ -244,6 +261,8 @@ dppix_status_t dp_pix_plan_create(const dppix_frame_desc_t* descs, int32_t n_fra
         cell += (int64_t)F.GR * F.GC;
         fine += (int64_t)F.GR * F.n * F.GC * F.n;
         tile += (int64_t)F.GR * F.TX;
+        p->n_units += F.cunits;
+        p->lds[kPlan] = std::max<size_t>(p->lds[kPlan], plan_lds(F.cnb, F.ctx, F.K));
         p->bg_cap += (size_t)F.GR * F.GC * F.C;
         p->fg_cap += (size_t)F.GR * F.GC * F.n * F.n * F.C;
         p->total_pixels += (int64_t)F.H * F.W;
@@ -251,7 +270,7 @@ dppix_status_t dp_pix_plan_create(const dppix_frame_desc_t* descs, int32_t n_fra
             p->any_f32 = true;
         else
             p->any_u8 = true;
-        for (int k = 0; k < 6; ++k) {
+        for (int k = 1; k < 6; ++k) {
             if (k == kBwd && F.layout != DPPIX_F32_CHW)
                 continue;
             if ((k == kFwdU8 || k == kRecU8) && F.layout != DPPIX_U8_HWC)
@@ -264,7 +283,7 @@ dppix_status_t dp_pix_plan_create(const dppix_frame_desc_t* descs, int32_t n_fra
     p->total_cells = cell;
     p->total_fine = fine;
     p->n_tiles = tile;
-    if (tile > (int64_t)INT32_MAX) {
+    if (tile > (int64_t)INT32_MAX || p->n_units > (int64_t)INT32_MAX) {
         delete p;
         return fail(DPPIX_ENOTSUP, "more than 2^31 tiles");
     }
@@ -308,12 +327,13 @@ dppix_status_t dp_pix_plan_create(const dppix_frame_desc_t* descs, int32_t n_fra
     size_t o = 0;
     w.frames = o;      o = align256(o + sizeof(FrameRec) * n_frames);
     w.tile_map = o;    o = align256(o + sizeof(int32_t) * 2 * (size_t)p->n_tiles);
+    w.unit_map = o;    o = align256(o + sizeof(int32_t) * 2 * (size_t)p->n_units);
     w.flags = o;       o = align256(o + (size_t)p->total_cells);
     w.tile_cnt = o;    o = align256(o + sizeof(uint32_t) * (size_t)p->n_tiles);
     w.tile_fg = o;     o = align256(o + sizeof(uint32_t) * (size_t)p->n_tiles);
     w.frame_tot = o;   o = align256(o + sizeof(uint64_t) * 2 * n_frames);
     w.frame_base = o;  o = align256(o + sizeof(uint64_t) * 2 * n_frames);
-    w.counters = o;    o = align256(o + sizeof(uint32_t) * kTicketWords);
+    w.counters = o;    o = align256(o + sizeof(uint32_t) * (kTicketWords + (size_t)n_frames));
     w.total = o;
 
     // Host image of the static tables: frame records, and per scheduling index
@@ -325,6 +345,12 @@ dppix_status_t dp_pix_plan_create(const dppix_frame_desc_t* descs, int32_t n_fra
         for (int64_t i = p->sched_base[k]; i < p->sched_base[k + 1]; ++i) {
             map[2 * i] = order[k];
             map[2 * i + 1] = (int32_t)(i - p->sched_base[k]);
+        }
+    int32_t* umap = reinterpret_cast<int32_t*>(p->host_tables.data() + w.unit_map);
+    for (int32_t f = 0, u = 0; f < n_frames; ++f)
+        for (int32_t i = 0; i < p->frames[f].cunits; ++i, ++u) {
+            umap[2 * u] = f;
+            umap[2 * u + 1] = i;
         }
     *out = p;
     return DPPIX_OK;
@@ -399,9 +425,10 @@ dppix_status_t dp_pix_plan_bind(dppix_plan_t p, void* ws, size_t bytes, dppix_st
                                   reinterpret_cast<hipStream_t>(stream));
     if (e != hipSuccess)
         return dev_fail(e, "uploading plan tables");
-    // tickets start at zero; the scan kernel clears them again on every plan
-    e = hipMemsetAsync(static_cast<uint8_t*>(ws) + p->ws.counters, 0, sizeof(uint32_t) * kTicketWords,
-                       reinterpret_cast<hipStream_t>(stream));
+    // tickets and per-frame counters start at zero; the plan kernel clears
+    // them again on every plan
+    e = hipMemsetAsync(static_cast<uint8_t*>(ws) + p->ws.counters, 0,
+                       sizeof(uint32_t) * (kTicketWords + p->frames.size()), reinterpret_cast<hipStream_t>(stream));
     if (e != hipSuccess)
         return dev_fail(e, "clearing tickets");
     p->bound = static_cast<uint8_t*>(ws);
@@ -422,7 +449,9 @@ TileArgs base_args(dppix_plan_t p)
     a.tile_map = reinterpret_cast<const int32_t*>(w + p->ws.tile_map);
     a.n_frames = (int32_t)p->frames.size();
     a.n_tiles = p->n_tiles;
+    a.unit_map = reinterpret_cast<const int32_t*>(w + p->ws.unit_map);
     a.ticket = reinterpret_cast<uint32_t*>(w + p->ws.counters);
+    a.frame_done = a.ticket + kTicketWords;
     a.persistent = p->persistent;
     a.flags = w + p->ws.flags;
     a.tile_cnt = reinterpret_cast<uint32_t*>(w + p->ws.tile_cnt);
@@ -501,12 +530,9 @@ dppix_status_t dp_pix_plan(dppix_plan_t p, const uint8_t* const* masks, const dp
     TileArgs a = base_args(p);
     a.masks = masks;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    hipError_t e = launch_classify(a, p->threads, p->lds[kClassify], s);
+    hipError_t e = launch_plan(a, p->n_units, p->threads, p->lds[kPlan], store ? store->counts : nullptr, s);
     if (e != hipSuccess)
-        return dev_fail(e, "classify launch");
-    e = launch_scan(a, store ? store->counts : nullptr, s);
-    if (e != hipSuccess)
-        return dev_fail(e, "scan launch");
+        return dev_fail(e, "plan launch");
     return DPPIX_OK;
 }
 

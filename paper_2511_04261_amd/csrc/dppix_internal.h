@@ -17,7 +17,7 @@ constexpr int kStrip = 16;             // bytes one lane moves per row (dwordx4)
 constexpr int kMaxThreads = 512;
 constexpr int kMaxB = 256;             // 255 * 256 rows fits a 16-bit lane sum
 constexpr int kTicketWords = 16;       // two per launch group (at most 5 groups) ...
-constexpr int kScanWord = 15;          // ... and the finished-workgroup count of the scan
+constexpr int kScanWord = 15;          // ... and the plan's count of finished frames
 
 // One frame as the kernels see it (host computes everything derivable).
 struct FrameRec {
@@ -25,7 +25,8 @@ struct FrameRec {
     int64_t pitch;            // U8: bytes per row; F32: floats per row
     int32_t b, s, n, pad;     // b_bg, b_fg, n = b/s, pad mode
     int32_t GR, GC, K, TX;    // grid rows/cols, cells per tile, tiles per band
-    int32_t tau, noise_bg, noise_fg, aligned;  // aligned: image rows 16-B aligned
+    int32_t tau, noise_bg, noise_fg, off32;    // off32: (b + 1) rows of the frame span < 2^31 bytes
+    int32_t cnb, ctx, cunits, pad_;           // plan units: bands, tiles per band, units of the frame
     int64_t cell_base;        // first cell of the frame in batch-wide cell arrays
     int64_t fine_base;        // first subcell in dense fine arrays
     int64_t tile_base;        // first tile
@@ -37,22 +38,26 @@ struct FrameRec {
 struct WsLayout {
     size_t frames;        // FrameRec[n_frames]
     size_t tile_map;      // int32[n_tiles][2]: (frame, tile within frame) per scheduling index
+    size_t unit_map;      // int32[n_units][2]: (frame, plan unit within frame), frame-major
     size_t flags;         // uint8[total_cells] (classification)
     size_t tile_cnt;      // uint32[n_tiles]: complex cells per tile
     size_t tile_fg;       // uint32[n_tiles]: complex cells of the frame before the tile
     size_t frame_tot;     // uint64[n_frames][2]: n_bg, n_fg cells
     size_t frame_base;    // uint64[n_frames][2]: float offsets of the frame in bg, fg
-    size_t counters;      // uint32[kTicketWords]: tickets of persistent launches, two per group
+    size_t counters;      // uint32[kTicketWords + n_frames]: tickets of persistent launches (two per
+                          // group), the plan's finished-frame count, finished units per frame
     size_t total;
 };
 
 struct TileArgs {
     const FrameRec* frames;
     const int32_t* tile_map;
+    const int32_t* unit_map;
     int32_t n_frames;
     int64_t sched_offset;     // first scheduling index of this launch
     int64_t n_tiles;          // tiles of this launch
     uint32_t* ticket;         // [0]: next tile, [1]: finished workgroups
+    uint32_t* frame_done;     // plan units finished, per frame
     int32_t persistent;
     // per-frame pointer tables (device arrays of device pointers)
     const uint8_t* const* masks;
@@ -87,8 +92,8 @@ struct TileArgs {
 };
 
 // Host-side launchers (defined in dppix_kernels.hip).
-hipError_t launch_classify(const TileArgs& a, int threads, size_t lds, hipStream_t s);
-hipError_t launch_scan(const TileArgs& a, uint64_t* counts_out, hipStream_t s);
+hipError_t launch_plan(const TileArgs& a, int64_t n_units, int threads, size_t lds, uint64_t* counts_out,
+                       hipStream_t s);
 hipError_t launch_forward(const TileArgs& a, int layout, int C, int threads, size_t lds, int grid, hipStream_t s);
 hipError_t launch_reconstruct(const TileArgs& a, int layout, int C, int threads, size_t lds, int grid,
                               hipStream_t s);

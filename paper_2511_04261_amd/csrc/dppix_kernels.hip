@@ -23,11 +23,28 @@
 
 #include <math.h>
 
+// Register budget of the u8 forward kernel, as resident waves per SIMD: 4
+// leaves 128 VGPRs (no spills with all of a subgrid row's loads in flight).
+#ifndef DPPIX_FWD_WAVES_PER_EU
+#define DPPIX_FWD_WAVES_PER_EU 4
+#endif
+
 namespace dppix {
 namespace {
 
 typedef uint32_t v4u __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+
+// 16-byte streaming accesses through global (not flat) address space: frame
+// pointers come from device tables, so the compiler cannot infer the address
+// space, and flat accesses would make every wait cover LDS traffic as well.
+typedef __attribute__((address_space(1))) v4u g_v4u;
+typedef __attribute__((address_space(1))) v4f g_v4f;
+
+__device__ __forceinline__ v4u ld16_nt(const void* p) { return __builtin_nontemporal_load((const g_v4u*)p); }
+__device__ __forceinline__ v4f ld16f_nt(const void* p) { return __builtin_nontemporal_load((const g_v4f*)p); }
+__device__ __forceinline__ void st16_nt(void* p, v4u v) { __builtin_nontemporal_store(v, (g_v4u*)p); }
+__device__ __forceinline__ void st16f_nt(void* p, v4f v) { __builtin_nontemporal_store(v, (g_v4f*)p); }
 
 // --------------------------------------------------------------------------
 // Counter-based noise.  Philox4x32 with ten rounds (Salmon et al., SC'11):
@@ -121,16 +138,8 @@ __device__ __forceinline__ uint32_t nz_bytes(uint32_t w)
     return ((((w & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | w) >> 7) & 0x01010101u;
 }
 
-__device__ __forceinline__ void store_colsums(uint32_t* dst, const uint32_t (&e)[4], const uint32_t (&o)[4])
-{
-    v4u* d4 = reinterpret_cast<v4u*>(dst);
-#pragma unroll
-    for (int d = 0; d < 4; ++d)
-        d4[d] = v4u{e[d] & 0xFFFFu, o[d] & 0xFFFFu, e[d] >> 16, o[d] >> 16};
-}
-
-// Same, as 16-bit column sums in natural byte-column order (a subgrid row
-// has at most 256 rows of bytes, so 255 * 256 fits).
+// Column sums of a strip as 16-bit values in natural byte-column order (a
+// subgrid row has at most 256 rows of bytes, so 255 * 256 fits).
 __device__ __forceinline__ void store_colsums16(uint16_t* dst, const uint32_t (&e)[4], const uint32_t (&o)[4])
 {
     v4u* d4 = reinterpret_cast<v4u*>(dst);
@@ -224,109 +233,7 @@ __device__ __forceinline__ TileCoord tile_of(const TileArgs& a, int64_t sched_id
 }
 
 // ==========================================================================
-// Plan: classify cells from the mirror-padded mask (Algorithm 3 steps 3-6).
-// ==========================================================================
-__device__ void classify_tile(const TileArgs& a, const FrameRec& F, const TileCoord& tc, uint8_t* lds)
-{
-    const int tid = threadIdx.x, NT = blockDim.x;
-    const int b = F.b, H = F.H, W = F.W;
-    const int x0c = tc.ct * F.K;
-    const int Kt = min(F.K, F.GC - x0c);
-    const int64_t X0 = (int64_t)x0c * b;
-    const int WB = Kt * b;
-    const int nstr = (WB + 15) >> 4;
-    const int64_t tile_end = X0 + WB;
-    const uint8_t* mask = a.masks ? a.masks[tc.f] : nullptr;
-    __shared__ uint32_t s_count;
-    if (mask == nullptr) {
-        for (int kc = tid; kc < Kt; kc += NT)
-            a.flags[F.cell_base + (int64_t)tc.r * F.GC + x0c + kc] = 0;
-        if (tid == 0)
-            a.tile_cnt[tc.t] = 0;
-        return;
-    }
-    const LdsPlan L = lds_plan(kClassify, F.K, b, F.n, 1);
-    uint32_t* colcnt = reinterpret_cast<uint32_t*>(lds + L.colsum);
-    for (int i = tid; i < 16 * nstr; i += NT)
-        colcnt[i] = 0;
-    if (tid == 0)
-        s_count = 0;
-    lds_barrier();
-    // A mask row of a tile is narrow (K*b bytes), so lanes split the band's
-    // rows into `groups` interleaved sets; partial column counts meet in LDS.
-    const int groups = max(1, min(b, NT / nstr));
-    const bool aligned = ((reinterpret_cast<uintptr_t>(mask) | (uintptr_t)W | (uintptr_t)X0) & 15) == 0;
-    const int row0 = tc.r * b;
-    for (int item = tid; item < nstr * groups; item += NT) {
-        const int st = item % nstr, g = item / nstr;
-        const int64_t p0 = X0 + 16 * st;
-        uint32_t e[4] = {0, 0, 0, 0}, o[4] = {0, 0, 0, 0};
-        if (aligned && p0 + 16 <= min(tile_end, (int64_t)W)) {
-            int k = g;
-            for (; k + 3 * groups < b; k += 4 * groups) {
-                v4u w0 = __builtin_nontemporal_load(
-                    reinterpret_cast<const v4u*>(mask + (int64_t)fold(row0 + k, H, F.pad) * W + p0));
-                v4u w1 = __builtin_nontemporal_load(
-                    reinterpret_cast<const v4u*>(mask + (int64_t)fold(row0 + k + groups, H, F.pad) * W + p0));
-                v4u w2 = __builtin_nontemporal_load(
-                    reinterpret_cast<const v4u*>(mask + (int64_t)fold(row0 + k + 2 * groups, H, F.pad) * W + p0));
-                v4u w3 = __builtin_nontemporal_load(
-                    reinterpret_cast<const v4u*>(mask + (int64_t)fold(row0 + k + 3 * groups, H, F.pad) * W + p0));
-                w0 = v4u{nz_bytes(w0.x), nz_bytes(w0.y), nz_bytes(w0.z), nz_bytes(w0.w)};
-                w1 = v4u{nz_bytes(w1.x), nz_bytes(w1.y), nz_bytes(w1.z), nz_bytes(w1.w)};
-                w2 = v4u{nz_bytes(w2.x), nz_bytes(w2.y), nz_bytes(w2.z), nz_bytes(w2.w)};
-                w3 = v4u{nz_bytes(w3.x), nz_bytes(w3.y), nz_bytes(w3.z), nz_bytes(w3.w)};
-                acc_bytes(w0, e, o);
-                acc_bytes(w1, e, o);
-                acc_bytes(w2, e, o);
-                acc_bytes(w3, e, o);
-            }
-            for (; k < b; k += groups) {
-                v4u w = __builtin_nontemporal_load(
-                    reinterpret_cast<const v4u*>(mask + (int64_t)fold(row0 + k, H, F.pad) * W + p0));
-                acc_bytes(v4u{nz_bytes(w.x), nz_bytes(w.y), nz_bytes(w.z), nz_bytes(w.w)}, e, o);
-            }
-        } else {
-            for (int k = g; k < b; k += groups) {
-                v4u w = gather_strip_u8<1>(mask + (int64_t)fold(row0 + k, H, F.pad) * W, (int)p0, (int)tile_end,
-                                           W, F.pad);
-                acc_bytes(v4u{nz_bytes(w.x), nz_bytes(w.y), nz_bytes(w.z), nz_bytes(w.w)}, e, o);
-            }
-        }
-        uint32_t* cc = colcnt + 16 * st;
-#pragma unroll
-        for (int d = 0; d < 4; ++d) {
-            atomicAdd(cc + 4 * d + 0, e[d] & 0xFFFFu);
-            atomicAdd(cc + 4 * d + 1, o[d] & 0xFFFFu);
-            atomicAdd(cc + 4 * d + 2, e[d] >> 16);
-            atomicAdd(cc + 4 * d + 3, o[d] >> 16);
-        }
-    }
-    lds_barrier();
-    for (int kc = tid; kc < Kt; kc += NT) {
-        uint32_t cnt = 0;
-        for (int x = 0; x < b; ++x)
-            cnt += colcnt[kc * b + x];
-        const uint8_t fl = (uint8_t)(cnt >= (uint32_t)F.tau);
-        a.flags[F.cell_base + (int64_t)tc.r * F.GC + x0c + kc] = fl;
-        if (fl)
-            atomicAdd(&s_count, 1u);
-    }
-    lds_barrier();
-    if (tid == 0)
-        a.tile_cnt[tc.t] = s_count;
-}
-
-__global__ __launch_bounds__(kMaxThreads) void k_classify(TileArgs a)
-{
-    extern __shared__ __align__(16) uint8_t lds[];
-    FrameRec F;
-    const TileCoord tc = tile_of(a, blockIdx.x, F);
-    classify_tile(a, F, tc, lds);
-}
-
-// ==========================================================================
-// Plan: scan complex-cell counts into store offsets.
+// Scans of the plan.
 // ==========================================================================
 template <typename T>
 __device__ __forceinline__ T block_exclusive_scan(T v, T* wave_tot, T& total)
@@ -361,8 +268,8 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T* wave_tot, T& total)
 
 // Frame-level pass of the scan: store offsets of every frame (frames
 // concatenated in batch order), per-frame counts, ticket reset.  Run by the
-// last workgroup of k_scan; the per-frame totals written by the others are
-// read with agent-scope atomic loads after an acquire fence.
+// last workgroup of the plan kernel; the per-frame totals written by others
+// are read with agent-scope atomic loads after an acquire fence.
 __device__ void scan_frames(const TileArgs& a, uint64_t* frame_base, uint64_t* counts, uint64_t* wave_tot)
 {
     uint64_t carry_bg = 0, carry_fg = 0;
@@ -396,42 +303,213 @@ __device__ void scan_frames(const TileArgs& a, uint64_t* frame_base, uint64_t* c
         a.ticket[threadIdx.x] = 0;
 }
 
-// One workgroup per frame: exclusive scan of the per-tile complex counts into
-// each tile's count of complex cells before it; the last workgroup to finish
-// then runs the frame-level pass.
-__global__ __launch_bounds__(256) void k_scan(TileArgs a, uint64_t* frame_base, uint64_t* counts)
+// ==========================================================================
+// Plan (Algorithm 3 steps 3-6): classify every cell from the mirror-padded
+// mask and turn the complex counts into store offsets, in one kernel.
+// A plan unit is `cnb` bands x `ctx` tiles of one frame.  Each lane sums one
+// 16-byte strip of the mask down up to kPlanRows padded rows with all its
+// loads in flight, then hands the strip's column counts to per-cell counters
+// in LDS (at most two cells per strip when b >= 16).  The last unit of a frame
+// to finish scans the frame's tile counts; the last frame to finish runs the
+// frame-level pass (offsets of every frame in the store).
+// ==========================================================================
+constexpr int kPlanRows = 16;   // padded mask rows one lane sums per item
+constexpr int kPlanBatch = 8;   // row loads issued back to back
+
+__device__ __forceinline__ v4u nz_strip(const v4u& w)
 {
-    __shared__ uint32_t wave_tot[9];
-    __shared__ uint64_t wave_tot64[9];
-    __shared__ int s_last;
-    const int f = blockIdx.x;
-    const FrameRec F = a.frames[f];
+    return v4u{nz_bytes(w.x), nz_bytes(w.y), nz_bytes(w.z), nz_bytes(w.w)};
+}
+
+// Column x (0..15) of a strip's packed counts (see acc_bytes).
+template <int X>
+__device__ __forceinline__ uint32_t col_count(const uint32_t (&e)[4], const uint32_t (&o)[4])
+{
+    const uint32_t v = (X & 1) ? o[X >> 2] : e[X >> 2];
+    return (X & 2) ? (v >> 16) : (v & 0xFFFFu);
+}
+
+template <int X>
+__device__ __forceinline__ void spread_col(const uint32_t (&e)[4], const uint32_t (&o)[4], uint32_t* cc, int KC,
+                                           int b, int& cell, int& next, uint32_t& run)
+{
+    if (X == next) {
+        if (run != 0u && cell < KC)
+            atomicAdd(cc + cell, run);
+        run = 0u;
+        ++cell;
+        next += b;
+    }
+    run += col_count<X>(e, o);
+}
+
+// Add the 16 column counts of one strip that starts at padded column p0 of
+// the unit to the counters of the cells they fall in.
+__device__ __forceinline__ void spread_strip(const uint32_t (&e)[4], const uint32_t (&o)[4], uint32_t* cc, int KC,
+                                             int b, int p0)
+{
+    int cell = p0 / b;
+    int next = (cell + 1) * b - p0;
+    uint32_t run = 0u;
+    spread_col<0>(e, o, cc, KC, b, cell, next, run);
+    spread_col<1>(e, o, cc, KC, b, cell, next, run);
+    spread_col<2>(e, o, cc, KC, b, cell, next, run);
+    spread_col<3>(e, o, cc, KC, b, cell, next, run);
+    spread_col<4>(e, o, cc, KC, b, cell, next, run);
+    spread_col<5>(e, o, cc, KC, b, cell, next, run);
+    spread_col<6>(e, o, cc, KC, b, cell, next, run);
+    spread_col<7>(e, o, cc, KC, b, cell, next, run);
+    spread_col<8>(e, o, cc, KC, b, cell, next, run);
+    spread_col<9>(e, o, cc, KC, b, cell, next, run);
+    spread_col<10>(e, o, cc, KC, b, cell, next, run);
+    spread_col<11>(e, o, cc, KC, b, cell, next, run);
+    spread_col<12>(e, o, cc, KC, b, cell, next, run);
+    spread_col<13>(e, o, cc, KC, b, cell, next, run);
+    spread_col<14>(e, o, cc, KC, b, cell, next, run);
+    spread_col<15>(e, o, cc, KC, b, cell, next, run);
+    if (run != 0u && cell < KC)
+        atomicAdd(cc + cell, run);
+}
+
+// Mask counts of every cell of the unit into cellcnt[j * KCs + kc].
+__device__ void plan_count(const TileArgs& a, const FrameRec& F, const uint8_t* mask, int r0, int nb, int c0, int KC,
+                           int KCs, uint32_t* cellcnt)
+{
+    const int tid = threadIdx.x, NT = blockDim.x;
+    const int b = F.b, H = F.H, W = F.W, pad = F.pad;
+    const int64_t X0 = (int64_t)c0 * b;
+    const int WB = KC * b;
+    const int nstr = (WB + 15) >> 4;
+    const int RI = min(b, kPlanRows);
+    const int groups = (b + RI - 1) / RI;
+    const int per_band = nstr * groups;
+    const int64_t lim = min(X0 + WB, (int64_t)W);
+    const bool aligned = ((reinterpret_cast<uintptr_t>(mask) | (uintptr_t)W | (uintptr_t)X0) & 15) == 0;
+    for (int item = tid; item < nb * per_band; item += NT) {
+        const int j = item / per_band;
+        const int rem = item - j * per_band;
+        const int g = rem / nstr;
+        const int st = rem - g * nstr;
+        const int64_t p0 = X0 + 16 * st;
+        const int row0 = (r0 + j) * b;
+        const int k0 = g * RI, k1 = min(b, k0 + RI);
+        uint32_t e[4] = {0, 0, 0, 0}, o[4] = {0, 0, 0, 0};
+        if (aligned && p0 + 16 <= lim && row0 + k1 <= H) {
+            // rows inside the frame: no folding
+            const uint8_t* col = mask + (int64_t)row0 * W + p0;
+            int k = k0;
+            for (; k + kPlanBatch <= k1; k += kPlanBatch) {
+                v4u w[kPlanBatch];
+#pragma unroll
+                for (int i = 0; i < kPlanBatch; ++i)
+                    w[i] = ld16_nt(col + (int64_t)(k + i) * W);
+#pragma unroll
+                for (int i = 0; i < kPlanBatch; ++i)
+                    acc_bytes(nz_strip(w[i]), e, o);
+            }
+            for (; k < k1; ++k)
+                acc_bytes(nz_strip(ld16_nt(col + (int64_t)k * W)), e, o);
+        } else if (aligned && p0 + 16 <= lim) {
+            for (int k = k0; k < k1; ++k)
+                acc_bytes(nz_strip(ld16_nt(mask + (int64_t)fold(row0 + k, H, pad) * W + p0)), e, o);
+        } else {
+            for (int k = k0; k < k1; ++k)
+                acc_bytes(nz_strip(gather_strip_u8<1>(mask + (int64_t)fold(row0 + k, H, pad) * W, (int)p0,
+                                                      (int)(X0 + WB), W, pad)),
+                          e, o);
+        }
+        spread_strip(e, o, cellcnt + j * KCs, KC, b, 16 * st);
+    }
+}
+
+// Exclusive scan of one frame's tile counts into tile_fg; returns the
+// frame's complex-cell total.  Counts written by other workgroups of this
+// launch are read with agent-scope atomic loads.
+__device__ uint32_t scan_frame_tiles(const TileArgs& a, const FrameRec& F, uint32_t* wave_tot)
+{
     const int64_t nt = (int64_t)F.GR * F.TX;
     uint32_t carry = 0;
     for (int64_t base = 0; base < nt; base += blockDim.x) {
         const int64_t i = base + threadIdx.x;
-        const uint32_t v = i < nt ? a.tile_cnt[F.tile_base + i] : 0u;
+        const uint32_t v =
+            i < nt ? __hip_atomic_load(&a.tile_cnt[F.tile_base + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                   : 0u;
         uint32_t tot;
         const uint32_t ex = block_exclusive_scan<uint32_t>(v, wave_tot, tot);
         if (i < nt)
             a.tile_fg[F.tile_base + i] = carry + ex;
         carry += tot;
     }
-    if (threadIdx.x == 0) {
-        const uint64_t cells = (uint64_t)F.GR * F.GC;
-        a.frame_tot[2 * f + 0] = cells - carry;
-        a.frame_tot[2 * f + 1] = carry;
-        __threadfence();                                    // release the totals
-        const uint32_t done = atomicAdd(&a.ticket[kScanWord], 1u);
-        s_last = (done == gridDim.x - 1);
+    return carry;
+}
+
+__global__ __launch_bounds__(kMaxThreads) void k_plan(TileArgs a, uint64_t* frame_base, uint64_t* counts)
+{
+    extern __shared__ __align__(16) uint8_t lds[];
+    __shared__ uint32_t wave_tot[kMaxThreads / 64 + 1];
+    __shared__ uint64_t wave_tot64[kMaxThreads / 64 + 1];
+    __shared__ int s_last;
+    const int tid = threadIdx.x, NT = blockDim.x;
+    const int f = (int)uniform_u32((uint32_t)a.unit_map[2 * (int64_t)blockIdx.x]);
+    const int lu = (int)uniform_u32((uint32_t)a.unit_map[2 * (int64_t)blockIdx.x + 1]);
+    const FrameRec F = a.frames[f];
+    const int chunks = (F.TX + F.ctx - 1) / F.ctx;
+    const int band_grp = lu / chunks;
+    const int r0 = band_grp * F.cnb;
+    const int nb = min(F.cnb, F.GR - r0);
+    const int t0 = (lu - band_grp * chunks) * F.ctx;
+    const int nt = min(F.ctx, F.TX - t0);
+    const int c0 = t0 * F.K;
+    const int KC = min(nt * F.K, F.GC - c0);
+    const int KCs = F.ctx * F.K;
+    uint32_t* cellcnt = reinterpret_cast<uint32_t*>(lds);
+    uint32_t* tcnt = cellcnt + F.cnb * KCs;
+    for (int i = tid; i < F.cnb * (KCs + F.ctx); i += NT)
+        cellcnt[i] = 0u;
+    lds_barrier();
+    const uint8_t* mask = a.masks ? a.masks[f] : nullptr;
+    if (mask != nullptr)
+        plan_count(a, F, mask, r0, nb, c0, KC, KCs, cellcnt);
+    lds_barrier();
+    for (int i = tid; i < nb * KC; i += NT) {
+        const int j = i / KC, kc = i - j * KC;
+        const uint8_t fl = (uint8_t)(cellcnt[j * KCs + kc] >= (uint32_t)F.tau);
+        a.flags[F.cell_base + (int64_t)(r0 + j) * F.GC + c0 + kc] = fl;
+        if (fl)
+            atomicAdd(&tcnt[j * F.ctx + kc / F.K], 1u);
+    }
+    lds_barrier();
+    // wave 0 publishes the unit's tile counts, then counts the unit as done
+    if (tid < 64) {
+        for (int i = tid; i < nb * nt; i += 64) {
+            const int j = i / nt, ti = i - j * nt;
+            __hip_atomic_store(&a.tile_cnt[F.tile_base + (int64_t)(r0 + j) * F.TX + t0 + ti], tcnt[j * F.ctx + ti],
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __threadfence();
+        if (tid == 0)
+            s_last = atomicAdd(&a.frame_done[f], 1u) == (uint32_t)F.cunits - 1u;
     }
     __syncthreads();
     if (!s_last)
         return;
-    __threadfence();                                        // acquire the others' totals
+    __threadfence();
+    const uint32_t fg_cells = scan_frame_tiles(a, F, wave_tot);
+    if (tid == 0) {
+        const uint64_t cells = (uint64_t)F.GR * F.GC;
+        __hip_atomic_store(&a.frame_tot[2 * f + 0], cells - fg_cells, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&a.frame_tot[2 * f + 1], (uint64_t)fg_cells, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&a.frame_done[f], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        s_last = atomicAdd(&a.ticket[kScanWord], 1u) == (uint32_t)a.n_frames - 1u;
+    }
+    __syncthreads();
+    if (!s_last)
+        return;
+    __threadfence();
     scan_frames(a, frame_base, counts, wave_tot64);
     __syncthreads();
-    if (threadIdx.x == 0)
+    if (tid == 0)
         atomicExch(&a.ticket[kScanWord], 0u);
 }
 
@@ -456,6 +534,11 @@ __device__ void forward_tile_u8(const TileArgs& a, const FrameRec& F, const Tile
     const uint8_t* img = static_cast<const uint8_t*>(a.images[tc.f]);
     uint8_t* out = a.outs ? static_cast<uint8_t*>(a.outs[tc.f]) : nullptr;
     const bool in_aligned = ((reinterpret_cast<uintptr_t>(img) | (uintptr_t)pitch | (uintptr_t)X0) & 15) == 0;
+    // bands without vertical padding address rows by 32-bit offsets from the
+    // band's first byte of the tile (uniform base, one offset register)
+    const bool band_inside = F.off32 && (r + 1) * b <= H;
+    const uint32_t upitch = (uint32_t)pitch;
+    const uint8_t* band_in = img + (int64_t)r * b * pitch + X0;
 
     const LdsPlan L = lds_plan(kFwdU8, F.K, b, n, C);
     uint16_t* col16 = reinterpret_cast<uint16_t*>(lds + L.colsum);
@@ -480,40 +563,51 @@ __device__ void forward_tile_u8(const TileArgs& a, const FrameRec& F, const Tile
     // s_b columns per subgrid row and releases complex subcells ----
     for (int fr0 = 0; fr0 < n; fr0 += kRowGroup) {
         const int ng = min(kRowGroup, n - fr0);
-        for (int st = tid; st < nstr; st += NT) {
+        // one item per (subgrid row, strip): consecutive lanes read
+        // consecutive strips of a row, and all s_b rows of an item are loaded
+        // before they are added
+        for (int it = tid; it < nstr * ng; it += NT) {
+            const int g = it / nstr;
+            const int st = it - g * nstr;
             const int64_t p0 = X0 + 16 * st;
-            const bool fast = in_aligned && p0 + 16 <= lim;
-            for (int g = 0; g < ng; ++g) {
-                const int row0 = r * b + (fr0 + g) * s;
-                uint32_t e[4] = {0, 0, 0, 0}, o[4] = {0, 0, 0, 0};
-                if (fast) {
-                    int k = 0;
-                    for (; k + 4 <= s; k += 4) {
-                        const uint8_t* r0 = img + (int64_t)fold(row0 + k + 0, H, pad) * pitch + p0;
-                        const uint8_t* r1 = img + (int64_t)fold(row0 + k + 1, H, pad) * pitch + p0;
-                        const uint8_t* r2 = img + (int64_t)fold(row0 + k + 2, H, pad) * pitch + p0;
-                        const uint8_t* r3 = img + (int64_t)fold(row0 + k + 3, H, pad) * pitch + p0;
-                        const v4u w0 = __builtin_nontemporal_load(reinterpret_cast<const v4u*>(r0));
-                        const v4u w1 = __builtin_nontemporal_load(reinterpret_cast<const v4u*>(r1));
-                        const v4u w2 = __builtin_nontemporal_load(reinterpret_cast<const v4u*>(r2));
-                        const v4u w3 = __builtin_nontemporal_load(reinterpret_cast<const v4u*>(r3));
-                        acc_bytes(w0, e, o);
-                        acc_bytes(w1, e, o);
-                        acc_bytes(w2, e, o);
-                        acc_bytes(w3, e, o);
-                    }
-                    for (; k < s; ++k) {
-                        const uint8_t* rk = img + (int64_t)fold(row0 + k, H, pad) * pitch + p0;
-                        acc_bytes(__builtin_nontemporal_load(reinterpret_cast<const v4u*>(rk)), e, o);
-                    }
-                } else {
-                    for (int k = 0; k < s; ++k) {
-                        const uint8_t* rk = img + (int64_t)fold(row0 + k, H, pad) * pitch;
-                        acc_bytes(gather_strip_u8<C>(rk, (int)p0, (int)tile_end, W, pad), e, o);
-                    }
+            const int row0 = r * b + (fr0 + g) * s;
+            uint32_t e[4] = {0, 0, 0, 0}, o[4] = {0, 0, 0, 0};
+            if (in_aligned && p0 + 16 <= lim && band_inside) {
+                // rows r*b + (fr0+g)*s + k, all inside the frame: 32-bit
+                // offsets from the band's first row
+                const uint32_t off = (uint32_t)((fr0 + g) * s) * upitch + 16u * (uint32_t)st;
+                int k = 0;
+                for (; k + 8 <= s; k += 8) {
+                    v4u w[8];
+#pragma unroll
+                    for (int i = 0; i < 8; ++i)
+                        w[i] = ld16_nt(band_in + (off + (uint32_t)(k + i) * upitch));
+#pragma unroll
+                    for (int i = 0; i < 8; ++i)
+                        acc_bytes(w[i], e, o);
                 }
-                store_colsums16(col16 + g * rowbuf + 16 * st, e, o);
+                for (; k + 4 <= s; k += 4) {
+                    v4u w[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        w[i] = ld16_nt(band_in + (off + (uint32_t)(k + i) * upitch));
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        acc_bytes(w[i], e, o);
+                }
+                for (; k < s; ++k)
+                    acc_bytes(ld16_nt(band_in + (off + (uint32_t)k * upitch)), e, o);
+            } else if (in_aligned && p0 + 16 <= lim) {
+                const uint8_t* col = img + p0;
+                for (int k = 0; k < s; ++k)
+                    acc_bytes(ld16_nt(col + (int64_t)fold(row0 + k, H, pad) * pitch), e, o);
+            } else {
+                for (int k = 0; k < s; ++k) {
+                    const uint8_t* rk = img + (int64_t)fold(row0 + k, H, pad) * pitch;
+                    acc_bytes(gather_strip_u8<C>(rk, (int)p0, (int)tile_end, W, pad), e, o);
+                }
             }
+            store_colsums16(col16 + g * rowbuf + 16 * st, e, o);
         }
         lds_barrier();
         for (int j = tid; j < items; j += NT) {
@@ -575,6 +669,7 @@ __device__ void forward_tile_u8(const TileArgs& a, const FrameRec& F, const Tile
     // subgrid row suffices: a buffer is rewritten two rows later, after every
     // lane has passed the barrier that follows its last read.
     const bool out_aligned = ((reinterpret_cast<uintptr_t>(out) | (uintptr_t)pitch | (uintptr_t)X0) & 15) == 0;
+    uint8_t* band_out = out + (int64_t)r * b * pitch + X0;
     for (int fr = 0; fr < n; ++fr) {
         uint8_t* exb = ex + (fr & 1) * (16 * nstr);
         for (int j = tid; j < items; j += NT) {
@@ -588,17 +683,30 @@ __device__ void forward_tile_u8(const TileArgs& a, const FrameRec& F, const Tile
         lds_barrier();
         const int row0 = r * b + fr * s;
         const int rows = min(s, H - row0);
-        for (int st = tid; st < nstr; st += NT) {
+        // items (row part, strip): the s_b rows of a strip are split over
+        // `parts` lanes when the tile has fewer strips than lanes
+        const int parts = max(1, min(rows, NT / nstr));
+        const int per = (rows + parts - 1) / max(parts, 1);
+        for (int it = tid; it < nstr * parts; it += NT) {
+            const int part = it / nstr;
+            const int st = it - part * nstr;
             const int64_t p0 = X0 + 16 * st;
+            const int k0 = part * per, k1 = min(rows, k0 + per);
             if (p0 >= lim)
                 continue;
             const v4u v = *reinterpret_cast<const v4u*>(exb + 16 * st);
             if (out_aligned && p0 + 16 <= lim) {
-                for (int k = 0; k < rows; ++k)
-                    __builtin_nontemporal_store(v, reinterpret_cast<v4u*>(out + (int64_t)(row0 + k) * pitch + p0));
+                if (F.off32) {
+                    const uint32_t off = (uint32_t)(fr * s) * upitch + 16u * (uint32_t)st;
+                    for (int k = k0; k < k1; ++k)
+                        st16_nt(band_out + (off + (uint32_t)k * upitch), v);
+                } else {
+                    for (int k = k0; k < k1; ++k)
+                        st16_nt(out + (int64_t)(row0 + k) * pitch + p0, v);
+                }
             } else {
                 const uint8_t* vb = exb + 16 * st;
-                for (int k = 0; k < rows; ++k) {
+                for (int k = k0; k < k1; ++k) {
                     uint8_t* op = out + (int64_t)(row0 + k) * pitch;
                     for (int q = 0; q < 16 && p0 + q < lim; ++q)
                         op[p0 + q] = vb[q];
@@ -654,8 +762,7 @@ __device__ void forward_tile_f32(const TileArgs& a, const FrameRec& F, const Til
                 v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
                 if (in_aligned && p0 + 4 <= lim) {
                     for (int k = 0; k < s; ++k) {
-                        acc += __builtin_nontemporal_load(
-                            reinterpret_cast<const v4f*>(pl + (int64_t)fold(row0 + k, H, pad) * pitch + p0));
+                        acc += ld16f_nt(pl + (int64_t)fold(row0 + k, H, pad) * pitch + p0);
                     }
                 } else {
                     for (int k = 0; k < s; ++k) {
@@ -731,7 +838,7 @@ __device__ void forward_tile_f32(const TileArgs& a, const FrameRec& F, const Til
                 const v4f v = reinterpret_cast<const v4f*>(exf)[st];
                 if (out_aligned && p0 + 4 <= lim) {
                     for (int k = 0; k < rows; ++k)
-                        __builtin_nontemporal_store(v, reinterpret_cast<v4f*>(pl + (int64_t)(row0 + k) * pitch + p0));
+                        st16f_nt(pl + (int64_t)(row0 + k) * pitch + p0, v);
                 } else {
                     const float vv[4] = {v.x, v.y, v.z, v.w};
                     for (int k = 0; k < rows; ++k)
@@ -783,7 +890,8 @@ __device__ __forceinline__ void run_tiles(const TileArgs& a, uint8_t* lds, Body 
 // Five waves per SIMD: enough resident tiles per CU to keep HBM busy while
 // other waves are in their LDS phases (the register budget still fits).
 template <int C>
-__global__ __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(5))) void k_forward_u8(TileArgs a)
+__global__ __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(DPPIX_FWD_WAVES_PER_EU))) void
+k_forward_u8(TileArgs a)
 {
     extern __shared__ __align__(16) uint8_t lds[];
     run_tiles(a, lds, [&](const FrameRec& F, const TileCoord& tc) { forward_tile_u8<C>(a, F, tc, lds); });
@@ -839,6 +947,8 @@ __device__ void reconstruct_tile_u8(const TileArgs& a, const FrameRec& F, const 
     }
     lds_barrier();
     const bool out_aligned = ((reinterpret_cast<uintptr_t>(out) | (uintptr_t)pitch | (uintptr_t)X0) & 15) == 0;
+    const uint32_t upitch = (uint32_t)pitch;
+    uint8_t* band_out = out + (int64_t)r * b * pitch + X0;
     for (int fr = 0; fr < n; ++fr) {
         uint8_t* exb = ex + (fr & 1) * (16 * nstr);   // two alternating row buffers
         for (int j = tid; j < items; j += NT) {
@@ -852,17 +962,30 @@ __device__ void reconstruct_tile_u8(const TileArgs& a, const FrameRec& F, const 
         lds_barrier();
         const int row0 = r * b + fr * s;
         const int rows = min(s, H - row0);
-        for (int st = tid; st < nstr; st += NT) {
+        // items (row part, strip): the s_b rows of a strip are split over
+        // `parts` lanes when the tile has fewer strips than lanes
+        const int parts = max(1, min(rows, NT / nstr));
+        const int per = (rows + parts - 1) / max(parts, 1);
+        for (int it = tid; it < nstr * parts; it += NT) {
+            const int part = it / nstr;
+            const int st = it - part * nstr;
             const int64_t p0 = X0 + 16 * st;
+            const int k0 = part * per, k1 = min(rows, k0 + per);
             if (p0 >= lim)
                 continue;
             const v4u v = *reinterpret_cast<const v4u*>(exb + 16 * st);
             if (out_aligned && p0 + 16 <= lim) {
-                for (int k = 0; k < rows; ++k)
-                    __builtin_nontemporal_store(v, reinterpret_cast<v4u*>(out + (int64_t)(row0 + k) * pitch + p0));
+                if (F.off32) {
+                    const uint32_t off = (uint32_t)(fr * s) * upitch + 16u * (uint32_t)st;
+                    for (int k = k0; k < k1; ++k)
+                        st16_nt(band_out + (off + (uint32_t)k * upitch), v);
+                } else {
+                    for (int k = k0; k < k1; ++k)
+                        st16_nt(out + (int64_t)(row0 + k) * pitch + p0, v);
+                }
             } else {
                 const uint8_t* vb = exb + 16 * st;
-                for (int k = 0; k < rows; ++k) {
+                for (int k = k0; k < k1; ++k) {
                     uint8_t* op = out + (int64_t)(row0 + k) * pitch;
                     for (int q = 0; q < 16 && p0 + q < lim; ++q)
                         op[p0 + q] = vb[q];
@@ -931,7 +1054,7 @@ __device__ void reconstruct_tile_f32(const TileArgs& a, const FrameRec& F, const
                 const v4f v = reinterpret_cast<const v4f*>(exf)[st];
                 if (out_aligned && p0 + 4 <= lim) {
                     for (int k = 0; k < rows; ++k)
-                        __builtin_nontemporal_store(v, reinterpret_cast<v4f*>(pl + (int64_t)(row0 + k) * pitch + p0));
+                        st16f_nt(pl + (int64_t)(row0 + k) * pitch + p0, v);
                 } else {
                     const float vv[4] = {v.x, v.y, v.z, v.w};
                     for (int k = 0; k < rows; ++k)
@@ -1344,23 +1467,16 @@ hipError_t allow_lds(K kernel, size_t lds)
                                (int)lds);
 }
 
-hipError_t launch_classify(const TileArgs& a, int threads, size_t lds, hipStream_t s)
+hipError_t launch_plan(const TileArgs& a, int64_t n_units, int threads, size_t lds, uint64_t* counts_out,
+                       hipStream_t s)
 {
-    if (a.n_tiles == 0)
+    if (n_units == 0)
         return hipSuccess;
-    TileArgs b = a;
-    b.persistent = 0;
-    hipError_t e = allow_lds(k_classify, lds);
+    hipError_t e = allow_lds(k_plan, lds);
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(k_classify, dim3((unsigned)a.n_tiles), dim3(threads), lds, s, b);
-    return hipGetLastError();
-}
-
-hipError_t launch_scan(const TileArgs& a, uint64_t* counts_out, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_scan, dim3((unsigned)a.n_frames), dim3(256), 0, s, a, const_cast<uint64_t*>(a.frame_base),
-                       counts_out);
+    hipLaunchKernelGGL(k_plan, dim3((unsigned)n_units), dim3(threads), lds, s, a,
+                       const_cast<uint64_t*>(a.frame_base), counts_out);
     return hipGetLastError();
 }
 

@@ -10,7 +10,7 @@ namespace dppix {
 constexpr int kRowGroup = 8;   // subgrid rows summed per pass of the u8 forward
 
 enum TileKind : int {
-    kClassify = 0,   // mask counts per cell
+    kPlan = 0,       // plan unit: mask counts per cell, complex cells per tile
     kFwdU8 = 1,      // forward, uint8 HWC
     kFwdF32 = 2,     // forward, fp32 CHW
     kRecU8 = 3,      // reconstruction, uint8 HWC
@@ -33,8 +33,6 @@ __host__ __device__ inline uint32_t al16(uint32_t x) { return (x + 15u) & ~15u; 
 // Number of 16-byte strips covering K cells of one padded row of the tile.
 __host__ __device__ inline uint32_t tile_strips(int kind, int K, int b, int C)
 {
-    if (kind == kClassify)
-        return (uint32_t)((K * b + 15) / 16);
     if (kind == kFwdF32 || kind == kRecF32 || kind == kBwd)
         return (uint32_t)((K * b + 3) / 4);
     return (uint32_t)((K * b * C + 15) / 16);
@@ -46,13 +44,10 @@ __host__ __device__ inline LdsPlan lds_plan(int kind, int K, int b, int n, int C
     const uint32_t nstr = tile_strips(kind, K, b, C);
     uint32_t o = 0;
     p.colsum = o;
-    // classify: 32-bit column counts; u8 forward: 16-bit column sums of up to
-    // kRowGroup subgrid rows (reused as two expanded output rows); f32 forward
-    // and reconstruction: two expanded output rows; adjoint: one row of float
-    // column sums
-    if (kind == kClassify)
-        o += al16(64u * nstr);
-    else if (kind == kFwdU8)
+    // u8 forward: 16-bit column sums of up to kRowGroup subgrid rows (reused
+    // as two expanded output rows); f32 forward and reconstruction: two
+    // expanded output rows; adjoint: one row of float column sums
+    if (kind == kFwdU8)
         o += al16(32u * nstr * (uint32_t)(n < kRowGroup ? n : kRowGroup));
     else if (kind == kBwd)
         o += al16(16u * nstr);
@@ -79,6 +74,13 @@ __host__ __device__ inline LdsPlan lds_plan(int kind, int K, int b, int n, int C
         o += al16(4u * (uint32_t)(K * n * n * C));
     p.bytes = o;
     return p;
+}
+
+// LDS of one plan unit: a 32-bit mask count per cell of cnb bands x ctx
+// tiles of K cells, and a complex-cell count per tile.
+__host__ __device__ inline uint32_t plan_lds(int cnb, int ctx, int K)
+{
+    return 4u * (uint32_t)cnb * (uint32_t)(ctx * K + ctx);
 }
 
 }  // namespace dppix
