@@ -65,13 +65,24 @@ def read_traffic(bytes_per_launch_alg: float):
     return fetch + write
 
 
-def build_batch(frames_s, dev, persistent=0, threads=0):
+def build_batch(frames_s, dev, persistent=0, threads=0, host_render=False):
     import torch
     import paper_2511_04261_amd as dp
     frames = [dp.FrameParams.from_spec(s) for s in frames_s]
     plan = dp.Plan(frames, device=dev, threads=threads, persistent=persistent)
-    imgs = [s.image_torch(dev) for s in frames_s]
-    masks = [s.mask_torch(dev) for s in frames_s]
+    if host_render:
+        # byte-identical frames rendered on the host and copied over (no
+        # device kernels besides the library's, e.g. under a counter profiler)
+        imgs, masks = [], []
+        for i, s in enumerate(frames_s):
+            imgs.append(torch.from_numpy(s.image).to(dev))
+            masks.append(torch.from_numpy(s.mask).to(dev))
+            s.drop_host()
+            if i % 16 == 15:
+                log("inputs: %d of %d frames on the device" % (i + 1, len(frames_s)))
+    else:
+        imgs = [s.image_torch(dev) for s in frames_s]
+        masks = [s.mask_torch(dev) for s in frames_s]
     outs = [torch.empty_like(t) for t in imgs]
     return plan, imgs, masks, outs
 
@@ -195,22 +206,29 @@ def counters_run(frames_s, dev, launches=3, copy_bytes=1 << 30):
     (the calibration of FETCH_SIZE / WRITE_SIZE), then a few plan + forward
     launches of the headline workload."""
     import torch
-    # an elementwise kernel (bitwise_not over int32) reads and writes exactly
-    # copy_bytes; copy_() would be a runtime memcpy that the counters do not see
-    src = torch.empty(copy_bytes // 4, dtype=torch.int32, device=dev).fill_(1)
-    dst = torch.empty_like(src)
+    # a converting copy int32 -> uint8 is an elementwise kernel that reads
+    # 4 bytes and writes 1 byte per element (a same-dtype copy_() would be a
+    # runtime memcpy that the counters do not see)
+    n = copy_bytes // 4
+    src = torch.ones(n, dtype=torch.int32, device=dev)
+    dst = torch.empty(n, dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
-    torch.bitwise_not(src, out=dst)
+    log("counters run: calibration buffers ready")
+    dst.copy_(src)
     torch.cuda.synchronize()
+    log("counters run: calibration kernel done")
     del src, dst
-    plan, imgs, masks, outs = build_batch(frames_s, dev)
-    for _ in range(launches):
+    plan, imgs, masks, outs = build_batch(frames_s, dev, host_render=True)
+    torch.cuda.synchronize()
+    log("counters run: batch ready")
+    for i in range(launches):
         plan.plan(masks)
         plan.forward(imgs, out=outs)
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        log("counters run: launch %d done" % i)
     ab = alg_bytes(plan)
-    log("counters run: copy %d bytes; forward alg bytes %d per launch" % (copy_bytes, ab["forward"]))
-    print(json.dumps({"copy_bytes": copy_bytes, "forward_alg_bytes": ab["forward"],
+    log("counters run: calibration copy %d -> %d bytes; forward alg bytes %d per launch" % (4 * n, n, ab["forward"]))
+    print(json.dumps({"copy_read_bytes": 4 * n, "copy_write_bytes": n, "forward_alg_bytes": ab["forward"],
                       "kernel_source_sha256_16": kernel_source_hash()}), flush=True)
 
 

@@ -333,7 +333,7 @@ dppix_status_t dp_pix_plan_create(const dppix_frame_desc_t* descs, int32_t n_fra
     w.tile_fg = o;     o = align256(o + sizeof(uint32_t) * (size_t)p->n_tiles);
     w.frame_tot = o;   o = align256(o + sizeof(uint64_t) * 2 * n_frames);
     w.frame_base = o;  o = align256(o + sizeof(uint64_t) * 2 * n_frames);
-    w.counters = o;    o = align256(o + sizeof(uint32_t) * (kTicketWords + (size_t)n_frames));
+    w.counters = o;    o = align256(o + sizeof(uint32_t) * kTicketWords);
     w.total = o;
 
     // Host image of the static tables: frame records, and per scheduling index
@@ -425,10 +425,9 @@ dppix_status_t dp_pix_plan_bind(dppix_plan_t p, void* ws, size_t bytes, dppix_st
                                   reinterpret_cast<hipStream_t>(stream));
     if (e != hipSuccess)
         return dev_fail(e, "uploading plan tables");
-    // tickets and per-frame counters start at zero; the plan kernel clears
-    // them again on every plan
-    e = hipMemsetAsync(static_cast<uint8_t*>(ws) + p->ws.counters, 0,
-                       sizeof(uint32_t) * (kTicketWords + p->frames.size()), reinterpret_cast<hipStream_t>(stream));
+    // tickets start at zero; the scan kernel clears them again on every plan
+    e = hipMemsetAsync(static_cast<uint8_t*>(ws) + p->ws.counters, 0, sizeof(uint32_t) * kTicketWords,
+                       reinterpret_cast<hipStream_t>(stream));
     if (e != hipSuccess)
         return dev_fail(e, "clearing tickets");
     p->bound = static_cast<uint8_t*>(ws);
@@ -451,7 +450,6 @@ TileArgs base_args(dppix_plan_t p)
     a.n_tiles = p->n_tiles;
     a.unit_map = reinterpret_cast<const int32_t*>(w + p->ws.unit_map);
     a.ticket = reinterpret_cast<uint32_t*>(w + p->ws.counters);
-    a.frame_done = a.ticket + kTicketWords;
     a.persistent = p->persistent;
     a.flags = w + p->ws.flags;
     a.tile_cnt = reinterpret_cast<uint32_t*>(w + p->ws.tile_cnt);

@@ -17,7 +17,7 @@ constexpr int kStrip = 16;             // bytes one lane moves per row (dwordx4)
 constexpr int kMaxThreads = 512;
 constexpr int kMaxB = 256;             // 255 * 256 rows fits a 16-bit lane sum
 constexpr int kTicketWords = 16;       // two per launch group (at most 5 groups) ...
-constexpr int kScanWord = 15;          // ... and the plan's count of finished frames
+constexpr int kScanWord = 15;          // ... and the scan's count of finished frames
 
 // One frame as the kernels see it (host computes everything derivable).
 struct FrameRec {
@@ -44,8 +44,8 @@ struct WsLayout {
     size_t tile_fg;       // uint32[n_tiles]: complex cells of the frame before the tile
     size_t frame_tot;     // uint64[n_frames][2]: n_bg, n_fg cells
     size_t frame_base;    // uint64[n_frames][2]: float offsets of the frame in bg, fg
-    size_t counters;      // uint32[kTicketWords + n_frames]: tickets of persistent launches (two per
-                          // group), the plan's finished-frame count, finished units per frame
+    size_t counters;      // uint32[kTicketWords]: tickets of persistent launches (two per group) and
+                          // the scan's finished-frame count
     size_t total;
 };
 
@@ -57,7 +57,6 @@ struct TileArgs {
     int64_t sched_offset;     // first scheduling index of this launch
     int64_t n_tiles;          // tiles of this launch
     uint32_t* ticket;         // [0]: next tile, [1]: finished workgroups
-    uint32_t* frame_done;     // plan units finished, per frame
     int32_t persistent;
     // per-frame pointer tables (device arrays of device pointers)
     const uint8_t* const* masks;

@@ -100,12 +100,16 @@ __device__ __forceinline__ int fold(int x, int L, int mode)
     if (x < L)
         return x;
     if (mode == 0) {
+        if (x < 2 * L)          // first mirror image, the common case
+            return 2 * L - 1 - x;
         const int p = 2 * L;
         const int y = x % p;
         return y < L ? y : p - 1 - y;
     }
     if (L == 1)
         return 0;
+    if (x < 2 * L - 1)
+        return 2 * L - 2 - x;
     const int p = 2 * L - 2;
     const int y = x % p;
     return y < L ? y : p - y;
@@ -155,26 +159,27 @@ __device__ __forceinline__ void store_colsums16(uint16_t* dst, const uint32_t (&
 template <int C>
 __device__ __noinline__ v4u gather_strip_u8(const uint8_t* row, int p0, int tile_end, int W, int pad)
 {
-    uint64_t lo = 0, hi = 0;
-    int x = p0 / C;
-    int ch = p0 - x * C;
-    int sx = fold(x, W, pad);
-#pragma unroll 1
+    typedef __attribute__((address_space(1))) const uint8_t g_u8;
+    const g_u8* src = (const g_u8*)row;
+    // source offsets first (folding branches), then 16 unconditional byte
+    // loads issued back to back; bytes past the tile end are masked after
+    int idx[16];
+#pragma unroll
     for (int q = 0; q < 16; ++q) {
-        if (p0 + q < tile_end) {
-            const uint64_t byte = row[sx * C + ch];
-            if (q < 8)
-                lo |= byte << (8 * q);
-            else
-                hi |= byte << (8 * (q - 8));
-        }
-        if (++ch == C) {
-            ch = 0;
-            ++x;
-            sx = fold(x, W, pad);
-        }
+        const int p = p0 + q;
+        const int x = p / C, ch = p - x * C;
+        idx[q] = p < tile_end ? fold(x, W, pad) * C + ch : 0;
     }
-    return v4u{(uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32)};
+    uint32_t v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+        v[q] = src[idx[q]];
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+        v[q] = p0 + q < tile_end ? v[q] : 0u;
+    return v4u{v[0] | (v[1] << 8) | (v[2] << 16) | (v[3] << 24), v[4] | (v[5] << 8) | (v[6] << 16) | (v[7] << 24),
+               v[8] | (v[9] << 8) | (v[10] << 16) | (v[11] << 24),
+               v[12] | (v[13] << 8) | (v[14] << 16) | (v[15] << 24)};
 }
 
 // Cell classes and class-local indices of the tile's cells (wave 0):
@@ -305,13 +310,11 @@ __device__ void scan_frames(const TileArgs& a, uint64_t* frame_base, uint64_t* c
 
 // ==========================================================================
 // Plan (Algorithm 3 steps 3-6): classify every cell from the mirror-padded
-// mask and turn the complex counts into store offsets, in one kernel.
+// mask (k_plan), then scan the complex counts into store offsets (k_scan).
 // A plan unit is `cnb` bands x `ctx` tiles of one frame.  Each lane sums one
 // 16-byte strip of the mask down up to kPlanRows padded rows with all its
 // loads in flight, then hands the strip's column counts to per-cell counters
-// in LDS (at most two cells per strip when b >= 16).  The last unit of a frame
-// to finish scans the frame's tile counts; the last frame to finish runs the
-// frame-level pass (offsets of every frame in the store).
+// in LDS (at most two cells per strip when b >= 16).
 // ==========================================================================
 constexpr int kPlanRows = 16;   // padded mask rows one lane sums per item
 constexpr int kPlanBatch = 8;   // row loads issued back to back
@@ -382,19 +385,24 @@ __device__ void plan_count(const TileArgs& a, const FrameRec& F, const uint8_t* 
     const int nstr = (WB + 15) >> 4;
     const int RI = min(b, kPlanRows);
     const int groups = (b + RI - 1) / RI;
-    const int per_band = nstr * groups;
     const int64_t lim = min(X0 + WB, (int64_t)W);
     const bool aligned = ((reinterpret_cast<uintptr_t>(mask) | (uintptr_t)W | (uintptr_t)X0) & 15) == 0;
+    // strips [0, nfast) are whole 16-byte vectors inside the frame; the rest
+    // (right edge, or every strip of a misaligned mask) are gathered byte by
+    // byte, one padded row per item so that their latencies overlap
+    const int nfast = aligned ? (int)min((int64_t)nstr, (lim - X0) >> 4) : 0;
+    const int nslow = nstr - nfast;
+    const int per_band = nfast * groups;
     for (int item = tid; item < nb * per_band; item += NT) {
         const int j = item / per_band;
         const int rem = item - j * per_band;
-        const int g = rem / nstr;
-        const int st = rem - g * nstr;
+        const int g = rem / nfast;
+        const int st = rem - g * nfast;
         const int64_t p0 = X0 + 16 * st;
         const int row0 = (r0 + j) * b;
         const int k0 = g * RI, k1 = min(b, k0 + RI);
         uint32_t e[4] = {0, 0, 0, 0}, o[4] = {0, 0, 0, 0};
-        if (aligned && p0 + 16 <= lim && row0 + k1 <= H) {
+        if (row0 + k1 <= H) {
             // rows inside the frame: no folding
             const uint8_t* col = mask + (int64_t)row0 * W + p0;
             int k = k0;
@@ -409,46 +417,28 @@ __device__ void plan_count(const TileArgs& a, const FrameRec& F, const uint8_t* 
             }
             for (; k < k1; ++k)
                 acc_bytes(nz_strip(ld16_nt(col + (int64_t)k * W)), e, o);
-        } else if (aligned && p0 + 16 <= lim) {
-            for (int k = k0; k < k1; ++k)
-                acc_bytes(nz_strip(ld16_nt(mask + (int64_t)fold(row0 + k, H, pad) * W + p0)), e, o);
         } else {
             for (int k = k0; k < k1; ++k)
-                acc_bytes(nz_strip(gather_strip_u8<1>(mask + (int64_t)fold(row0 + k, H, pad) * W, (int)p0,
-                                                      (int)(X0 + WB), W, pad)),
-                          e, o);
+                acc_bytes(nz_strip(ld16_nt(mask + (int64_t)fold(row0 + k, H, pad) * W + p0)), e, o);
         }
+        spread_strip(e, o, cellcnt + j * KCs, KC, b, 16 * st);
+    }
+    for (int item = tid; item < nb * b * nslow; item += NT) {
+        const int st = nfast + item % nslow;
+        const int rest = item / nslow;
+        const int k = rest % b, j = rest / b;
+        const int64_t p0 = X0 + 16 * st;
+        uint32_t e[4] = {0, 0, 0, 0}, o[4] = {0, 0, 0, 0};
+        acc_bytes(nz_strip(gather_strip_u8<1>(mask + (int64_t)fold((r0 + j) * b + k, H, pad) * W, (int)p0,
+                                              (int)(X0 + WB), W, pad)),
+                  e, o);
         spread_strip(e, o, cellcnt + j * KCs, KC, b, 16 * st);
     }
 }
 
-// Exclusive scan of one frame's tile counts into tile_fg; returns the
-// frame's complex-cell total.  Counts written by other workgroups of this
-// launch are read with agent-scope atomic loads.
-__device__ uint32_t scan_frame_tiles(const TileArgs& a, const FrameRec& F, uint32_t* wave_tot)
-{
-    const int64_t nt = (int64_t)F.GR * F.TX;
-    uint32_t carry = 0;
-    for (int64_t base = 0; base < nt; base += blockDim.x) {
-        const int64_t i = base + threadIdx.x;
-        const uint32_t v =
-            i < nt ? __hip_atomic_load(&a.tile_cnt[F.tile_base + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                   : 0u;
-        uint32_t tot;
-        const uint32_t ex = block_exclusive_scan<uint32_t>(v, wave_tot, tot);
-        if (i < nt)
-            a.tile_fg[F.tile_base + i] = carry + ex;
-        carry += tot;
-    }
-    return carry;
-}
-
-__global__ __launch_bounds__(kMaxThreads) void k_plan(TileArgs a, uint64_t* frame_base, uint64_t* counts)
+__global__ __launch_bounds__(kMaxThreads) void k_plan(TileArgs a)
 {
     extern __shared__ __align__(16) uint8_t lds[];
-    __shared__ uint32_t wave_tot[kMaxThreads / 64 + 1];
-    __shared__ uint64_t wave_tot64[kMaxThreads / 64 + 1];
-    __shared__ int s_last;
     const int tid = threadIdx.x, NT = blockDim.x;
     const int f = (int)uniform_u32((uint32_t)a.unit_map[2 * (int64_t)blockIdx.x]);
     const int lu = (int)uniform_u32((uint32_t)a.unit_map[2 * (int64_t)blockIdx.x + 1]);
@@ -479,38 +469,110 @@ __global__ __launch_bounds__(kMaxThreads) void k_plan(TileArgs a, uint64_t* fram
             atomicAdd(&tcnt[j * F.ctx + kc / F.K], 1u);
     }
     lds_barrier();
-    // wave 0 publishes the unit's tile counts, then counts the unit as done
-    if (tid < 64) {
-        for (int i = tid; i < nb * nt; i += 64) {
-            const int j = i / nt, ti = i - j * nt;
-            __hip_atomic_store(&a.tile_cnt[F.tile_base + (int64_t)(r0 + j) * F.TX + t0 + ti], tcnt[j * F.ctx + ti],
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        __threadfence();
-        if (tid == 0)
-            s_last = atomicAdd(&a.frame_done[f], 1u) == (uint32_t)F.cunits - 1u;
+    for (int i = tid; i < nb * nt; i += NT) {
+        const int j = i / nt, ti = i - j * nt;
+        a.tile_cnt[F.tile_base + (int64_t)(r0 + j) * F.TX + t0 + ti] = tcnt[j * F.ctx + ti];
     }
-    __syncthreads();
-    if (!s_last)
-        return;
-    __threadfence();
-    const uint32_t fg_cells = scan_frame_tiles(a, F, wave_tot);
-    if (tid == 0) {
+}
+
+// One workgroup per frame: exclusive scan of the per-tile complex counts into
+// each tile's count of complex cells before it; the last workgroup to finish
+// then runs the frame-level pass.  (A separate launch: electing a last
+// workgroup per plan unit would need an agent-scope fence — an L2 write-back
+// and invalidate — in every unit.)
+__global__ __launch_bounds__(256) void k_scan(TileArgs a, uint64_t* frame_base, uint64_t* counts)
+{
+    __shared__ uint32_t wave_tot[9];
+    __shared__ uint64_t wave_tot64[9];
+    __shared__ int s_last;
+    const int f = blockIdx.x;
+    const FrameRec F = a.frames[f];
+    const int64_t nt = (int64_t)F.GR * F.TX;
+    uint32_t carry = 0;
+    for (int64_t base = 0; base < nt; base += blockDim.x) {
+        const int64_t i = base + threadIdx.x;
+        const uint32_t v = i < nt ? a.tile_cnt[F.tile_base + i] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_exclusive_scan<uint32_t>(v, wave_tot, tot);
+        if (i < nt)
+            a.tile_fg[F.tile_base + i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) {
         const uint64_t cells = (uint64_t)F.GR * F.GC;
-        __hip_atomic_store(&a.frame_tot[2 * f + 0], cells - fg_cells, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&a.frame_tot[2 * f + 1], (uint64_t)fg_cells, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&a.frame_done[f], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        s_last = atomicAdd(&a.ticket[kScanWord], 1u) == (uint32_t)a.n_frames - 1u;
+        __hip_atomic_store(&a.frame_tot[2 * f + 0], cells - carry, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&a.frame_tot[2 * f + 1], (uint64_t)carry, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();                                    // release the totals
+        s_last = atomicAdd(&a.ticket[kScanWord], 1u) == gridDim.x - 1;
     }
     __syncthreads();
     if (!s_last)
         return;
-    __threadfence();
+    __threadfence();                                        // acquire the others' totals
     scan_frames(a, frame_base, counts, wave_tot64);
     __syncthreads();
-    if (tid == 0)
+    if (threadIdx.x == 0)
         atomicExch(&a.ticket[kScanWord], 0u);
+}
+
+// Subgrid rows per phase-1 item: with short subgrid rows an item takes
+// several, so that every lane has about eight row loads in flight.
+__device__ __forceinline__ int rows_per_item(int s) { return s == 2 ? 4 : ((s == 3 || s == 4) ? 2 : 1); }
+
+// Column sums of up to 8 / S consecutive subgrid rows of S rows each (qq of
+// them), one 16-byte strip: every load is issued before the first add.
+template <int S>
+__device__ __forceinline__ void strip_rows_q(const uint8_t* base, uint32_t off, uint32_t upitch, int qq,
+                                             uint16_t* dst, int rowbuf)
+{
+    constexpr int Q = 8 / S;
+    uint32_t e[Q][4], o[Q][4];
+#pragma unroll
+    for (int j = 0; j < Q; ++j)
+#pragma unroll
+        for (int d = 0; d < 4; ++d)
+            e[j][d] = o[j][d] = 0u;
+    v4u w[Q * S];
+#pragma unroll
+    for (int i = 0; i < Q * S; ++i)
+        if (i < qq * S)
+            w[i] = ld16_nt(base + (off + (uint32_t)i * upitch));
+#pragma unroll
+    for (int i = 0; i < Q * S; ++i)
+        if (i < qq * S)
+            acc_bytes(w[i], e[i / S], o[i / S]);
+#pragma unroll
+    for (int j = 0; j < Q; ++j)
+        if (j < qq)
+            store_colsums16(dst + j * rowbuf, e[j], o[j]);
+}
+
+// Column sums of one subgrid row of s rows, one strip, loads in batches of 8.
+__device__ __forceinline__ void strip_rows_1(const uint8_t* base, uint32_t off, uint32_t upitch, int s, uint16_t* dst)
+{
+    uint32_t e[4] = {0, 0, 0, 0}, o[4] = {0, 0, 0, 0};
+    int k = 0;
+    for (; k + 8 <= s; k += 8) {
+        v4u w[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            w[i] = ld16_nt(base + (off + (uint32_t)(k + i) * upitch));
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            acc_bytes(w[i], e, o);
+    }
+    for (; k + 4 <= s; k += 4) {
+        v4u w[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            w[i] = ld16_nt(base + (off + (uint32_t)(k + i) * upitch));
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            acc_bytes(w[i], e, o);
+    }
+    for (; k < s; ++k)
+        acc_bytes(ld16_nt(base + (off + (uint32_t)k * upitch)), e, o);
+    store_colsums16(dst, e, o);
 }
 
 // ==========================================================================
@@ -563,51 +625,62 @@ __device__ void forward_tile_u8(const TileArgs& a, const FrameRec& F, const Tile
     // s_b columns per subgrid row and releases complex subcells ----
     for (int fr0 = 0; fr0 < n; fr0 += kRowGroup) {
         const int ng = min(kRowGroup, n - fr0);
-        // one item per (subgrid row, strip): consecutive lanes read
-        // consecutive strips of a row, and all s_b rows of an item are loaded
-        // before they are added
-        for (int it = tid; it < nstr * ng; it += NT) {
-            const int g = it / nstr;
-            const int st = it - g * nstr;
-            const int64_t p0 = X0 + 16 * st;
-            const int row0 = r * b + (fr0 + g) * s;
-            uint32_t e[4] = {0, 0, 0, 0}, o[4] = {0, 0, 0, 0};
-            if (in_aligned && p0 + 16 <= lim && band_inside) {
-                // rows r*b + (fr0+g)*s + k, all inside the frame: 32-bit
-                // offsets from the band's first row
-                const uint32_t off = (uint32_t)((fr0 + g) * s) * upitch + 16u * (uint32_t)st;
-                int k = 0;
-                for (; k + 8 <= s; k += 8) {
-                    v4u w[8];
-#pragma unroll
-                    for (int i = 0; i < 8; ++i)
-                        w[i] = ld16_nt(band_in + (off + (uint32_t)(k + i) * upitch));
-#pragma unroll
-                    for (int i = 0; i < 8; ++i)
-                        acc_bytes(w[i], e, o);
-                }
-                for (; k + 4 <= s; k += 4) {
-                    v4u w[4];
-#pragma unroll
-                    for (int i = 0; i < 4; ++i)
-                        w[i] = ld16_nt(band_in + (off + (uint32_t)(k + i) * upitch));
-#pragma unroll
-                    for (int i = 0; i < 4; ++i)
-                        acc_bytes(w[i], e, o);
-                }
-                for (; k < s; ++k)
-                    acc_bytes(ld16_nt(band_in + (off + (uint32_t)k * upitch)), e, o);
-            } else if (in_aligned && p0 + 16 <= lim) {
-                const uint8_t* col = img + p0;
-                for (int k = 0; k < s; ++k)
-                    acc_bytes(ld16_nt(col + (int64_t)fold(row0 + k, H, pad) * pitch), e, o);
-            } else {
-                for (int k = 0; k < s; ++k) {
-                    const uint8_t* rk = img + (int64_t)fold(row0 + k, H, pad) * pitch;
-                    acc_bytes(gather_strip_u8<C>(rk, (int)p0, (int)tile_end, W, pad), e, o);
-                }
+        // Whole-vector strips inside the band ([0, nfast)): one item per (q
+        // subgrid rows, strip); consecutive lanes read consecutive strips of a
+        // row and all q * s_b rows of an item (8 or fewer) are loaded before
+        // they are added.  Other strips (right edge, folded rows of the last
+        // band, misaligned rows): one padded row per item, added into the
+        // column sums with LDS atomics so that their latencies overlap.
+        const int nfast = (in_aligned && band_inside) ? (int)min((int64_t)nstr, (lim - X0) >> 4) : 0;
+        const int nslow = nstr - nfast;
+        if (nslow > 0) {
+            uint32_t* c32 = reinterpret_cast<uint32_t*>(col16);
+            for (int i = tid; i < ng * nslow * 8; i += NT) {
+                const int g = i / (nslow * 8);
+                c32[(g * rowbuf + 16 * nfast) / 2 + (i - g * nslow * 8)] = 0u;
             }
-            store_colsums16(col16 + g * rowbuf + 16 * st, e, o);
+            lds_barrier();
+        }
+        const int q = rows_per_item(s);
+        const int ngq = (ng + q - 1) / q;
+        for (int it = tid; it < nfast * ngq; it += NT) {
+            const int gq = it / nfast;
+            const int st = it - gq * nfast;
+            const int g0 = gq * q;
+            const int qq = min(q, ng - g0);
+            uint16_t* dst = col16 + g0 * rowbuf + 16 * st;
+            // rows inside the frame: 32-bit offsets from the band's first row
+            const uint32_t off = (uint32_t)((fr0 + g0) * s) * upitch + 16u * (uint32_t)st;
+            switch (q) {
+            case 4: strip_rows_q<2>(band_in, off, upitch, qq, dst, rowbuf); break;
+            case 2:
+                if (s == 4)
+                    strip_rows_q<4>(band_in, off, upitch, qq, dst, rowbuf);
+                else
+                    strip_rows_q<3>(band_in, off, upitch, qq, dst, rowbuf);
+                break;
+            default: strip_rows_1(band_in, off, upitch, s, dst); break;
+            }
+        }
+        for (int it = tid; it < nslow * ng * s; it += NT) {
+            const int st = nfast + it % nslow;
+            const int rest = it / nslow;
+            const int k = rest % s, g = rest / s;
+            const int64_t p0 = X0 + 16 * st;
+            const uint8_t* rp = img + (int64_t)fold(r * b + (fr0 + g) * s + k, H, pad) * pitch;
+            const v4u v = (in_aligned && p0 + 16 <= lim) ? ld16_nt(rp + p0)
+                                                         : gather_strip_u8<C>(rp, (int)p0, (int)tile_end, W, pad);
+            // column pairs (2m, 2m+1) packed as in store_colsums16; a 16-bit
+            // half holds at most 255 * 256, so no carry crosses into the other
+            uint32_t* cw = reinterpret_cast<uint32_t*>(col16 + g * rowbuf + 16 * st);
+            atomicAdd(cw + 0, (v.x & 0xFFu) | ((v.x & 0xFF00u) << 8));
+            atomicAdd(cw + 1, ((v.x >> 16) & 0xFFu) | ((v.x >> 24) << 16));
+            atomicAdd(cw + 2, (v.y & 0xFFu) | ((v.y & 0xFF00u) << 8));
+            atomicAdd(cw + 3, ((v.y >> 16) & 0xFFu) | ((v.y >> 24) << 16));
+            atomicAdd(cw + 4, (v.z & 0xFFu) | ((v.z & 0xFF00u) << 8));
+            atomicAdd(cw + 5, ((v.z >> 16) & 0xFFu) | ((v.z >> 24) << 16));
+            atomicAdd(cw + 6, (v.w & 0xFFu) | ((v.w & 0xFF00u) << 8));
+            atomicAdd(cw + 7, ((v.w >> 16) & 0xFFu) | ((v.w >> 24) << 16));
         }
         lds_barrier();
         for (int j = tid; j < items; j += NT) {
@@ -1475,8 +1548,12 @@ hipError_t launch_plan(const TileArgs& a, int64_t n_units, int threads, size_t l
     hipError_t e = allow_lds(k_plan, lds);
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(k_plan, dim3((unsigned)n_units), dim3(threads), lds, s, a,
-                       const_cast<uint64_t*>(a.frame_base), counts_out);
+    hipLaunchKernelGGL(k_plan, dim3((unsigned)n_units), dim3(threads), lds, s, a);
+    e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_scan, dim3((unsigned)a.n_frames), dim3(256), 0, s, a, const_cast<uint64_t*>(a.frame_base),
+                       counts_out);
     return hipGetLastError();
 }
 

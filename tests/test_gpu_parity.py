@@ -80,6 +80,14 @@ CASES = [
     (200, 120, 1, 1, 1, 0, 1, 0.2),   # b = 1
     (61, 57, 3, 20, 5, 0, 0, 0.5),
     (96, 1000, 3, 32, 4, 0, 1, 0.02), # several tiles per band
+    # 16-byte aligned rows (the vector path), short subgrid rows: one item
+    # covers q = 2 or 4 subgrid rows, including a partial last group
+    (70, 96, 3, 12, 3, 0, 1, 0.2),    # s_b = 3, n = 4
+    (66, 128, 3, 8, 2, 0, 1, 0.2),    # s_b = 2, n = 4
+    (45, 80, 1, 6, 2, 1, 1, 0.3),     # s_b = 2, n = 3: partial group
+    (50, 64, 3, 24, 3, 0, 1, 0.1),    # s_b = 3, n = 8
+    (33, 112, 2, 32, 4, 0, 1, 0.2),   # s_b = 4, n = 8, padded second band
+    (40, 48, 1, 4, 1, 0, 1, 0.3),     # s_b = 1
 ]
 
 
