@@ -261,6 +261,58 @@ def cpu_baseline(frames_s, budget_s=15.0, dev=None):
                            done, len(frames_s), frames_s[0].width, frames_s[0].height, dt))
 
 
+def cpu_worker(frames_s, k, procs, budget_s):
+    """One worker of the parallel oracle baseline: frames k, k+procs, ...
+    rendered on the host (untimed), then the oracle over them until about
+    budget_s of oracle time.  Prints one JSON line."""
+    import oracle
+    mine = frames_s[k::procs]
+    inputs = [(s.image, s.mask) for s in mine]
+    dt, px, done = 0.0, 0, 0
+    while dt < budget_s:
+        for s, (img, mask) in zip(mine, inputs):
+            t1 = time.perf_counter()
+            oracle.forward(img, mask, oracle.Params(s.height, s.width, s.channels, b=s.b, sb=s.sb, m=s.m,
+                                                    eps_simple=s.eps_simple, eps_complex=s.eps_complex, tau=s.tau,
+                                                    seed=s.seed, frame_index=s.frame_index))
+            dt += time.perf_counter() - t1
+            px += s.height * s.width
+            done += 1
+    print(json.dumps({"px": px, "seconds": dt, "frames": done}), flush=True)
+
+
+def cpu_baseline_parallel(n_frames, budget_s=10.0):
+    """The same oracle, one process per host core (at most 16), frames
+    distributed round-robin: the all-cores reference.  Workers are child
+    processes that never touch the GPU."""
+    import subprocess
+    import oracle
+    oracle.build()
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    procs = max(1, min(16, cores, n_frames))
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-worker", "--cpu-procs", str(procs),
+           "--cpu-budget", str(budget_s), "--frames", str(n_frames)]
+    env = dict(os.environ, OMP_NUM_THREADS="1", HIP_VISIBLE_DEVICES="")
+    workers = [subprocess.Popen(cmd + ["--cpu-index", str(k)], stdout=subprocess.PIPE, env=env, text=True)
+               for k in range(procs)]
+    rate, frames, seconds = 0.0, 0, 0.0
+    for w in workers:
+        out, _ = w.communicate()
+        if w.returncode != 0:
+            raise RuntimeError("CPU oracle worker failed with status %d" % w.returncode)
+        r = json.loads(out.strip().splitlines()[-1])
+        rate += r["px"] / r["seconds"]
+        frames += r["frames"]
+        seconds = max(seconds, r["seconds"])
+    return dict(value=round(rate / 1e6, 3), unit="megapixels/s", cores=procs, kind="oracle",
+                sample="%d processes, one per host core, over the %d-frame batch (frames round-robin, host-rendered, "
+                       "untimed); %d frame passes, about %.1f s of oracle time each" % (procs, n_frames, frames,
+                                                                                      seconds))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -273,11 +325,20 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="seconds of camera-stream arrivals for the latency leg (0 skips it)")
     ap.add_argument("--counters", action="store_true", help="short run for rocprofv3 --pmc")
+    ap.add_argument("--cpu-worker", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-index", type=int, default=0, help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-procs", type=int, default=1, help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-budget", type=float, default=10.0, help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the method shards by frame with no collective, "
               "so --gpus N>1 is not run here", file=sys.stderr)
         sys.exit(2)
+
+    if args.cpu_worker:
+        from paper_2511_04261_amd import synth
+        cpu_worker(synth.region_batch(args.frames), args.cpu_index, args.cpu_procs, args.cpu_budget)
+        return
 
     import torch
     from paper_2511_04261_amd import synth
@@ -355,6 +416,8 @@ def main():
     if not args.skip_cpu:
         log("bench: CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline(frames_s, dev=dev)
+        log("bench: CPU oracle sample on all host cores")
+        out["cpu_baseline_all_cores"] = cpu_baseline_parallel(args.frames)
     print(json.dumps(out), flush=True)
 
 

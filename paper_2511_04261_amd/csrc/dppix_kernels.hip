@@ -56,10 +56,10 @@ __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1)
 {
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
-        const uint32_t ma = 0xD2511F53u, mb = 0xCD9E8D57u;
-        const uint32_t a_lo = ma * c.x, a_hi = __umulhi(ma, c.x);
-        const uint32_t b_lo = mb * c.z, b_hi = __umulhi(mb, c.z);
-        c = make_uint4(b_hi ^ c.y ^ k0, b_lo, a_hi ^ c.w ^ k1, a_lo);
+        // one 32x32 -> 64-bit product per multiplier gives both halves
+        const uint64_t pa = (uint64_t)0xD2511F53u * c.x;
+        const uint64_t pb = (uint64_t)0xCD9E8D57u * c.z;
+        c = make_uint4((uint32_t)(pb >> 32) ^ c.y ^ k0, (uint32_t)pb, (uint32_t)(pa >> 32) ^ c.w ^ k1, (uint32_t)pa);
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
@@ -547,6 +547,27 @@ __device__ __forceinline__ void strip_rows_q(const uint8_t* base, uint32_t off, 
             store_colsums16(dst + j * rowbuf, e[j], o[j]);
 }
 
+// Column sums of one subgrid row of s padded rows from row0 on, folded into
+// the frame (last band), one strip; loads in batches of 4.
+__device__ __forceinline__ void strip_rows_fold(const uint8_t* col, int64_t pitch, int row0, int s, int H, int pad,
+                                                uint16_t* dst)
+{
+    uint32_t e[4] = {0, 0, 0, 0}, o[4] = {0, 0, 0, 0};
+    int k = 0;
+    for (; k + 4 <= s; k += 4) {
+        v4u w[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            w[i] = ld16_nt(col + (int64_t)fold(row0 + k + i, H, pad) * pitch);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            acc_bytes(w[i], e, o);
+    }
+    for (; k < s; ++k)
+        acc_bytes(ld16_nt(col + (int64_t)fold(row0 + k, H, pad) * pitch), e, o);
+    store_colsums16(dst, e, o);
+}
+
 // Column sums of one subgrid row of s rows, one strip, loads in batches of 8.
 __device__ __forceinline__ void strip_rows_1(const uint8_t* base, uint32_t off, uint32_t upitch, int s, uint16_t* dst)
 {
@@ -617,7 +638,6 @@ __device__ void forward_tile_u8(const TileArgs& a, const FrameRec& F, const Tile
     const int items = Kt * n * C;
     const int nn = n * n;
     const int rowbuf = 16 * nstr;           // 16-bit column sums of one subgrid row
-    lds_barrier();
 
     // ---- subgrid rows, up to kRowGroup at a time: each lane streams its strip
     // down all rows of the group (exact 16-bit column sums per subgrid row,
@@ -625,13 +645,13 @@ __device__ void forward_tile_u8(const TileArgs& a, const FrameRec& F, const Tile
     // s_b columns per subgrid row and releases complex subcells ----
     for (int fr0 = 0; fr0 < n; fr0 += kRowGroup) {
         const int ng = min(kRowGroup, n - fr0);
-        // Whole-vector strips inside the band ([0, nfast)): one item per (q
-        // subgrid rows, strip); consecutive lanes read consecutive strips of a
-        // row and all q * s_b rows of an item (8 or fewer) are loaded before
-        // they are added.  Other strips (right edge, folded rows of the last
-        // band, misaligned rows): one padded row per item, added into the
-        // column sums with LDS atomics so that their latencies overlap.
-        const int nfast = (in_aligned && band_inside) ? (int)min((int64_t)nstr, (lim - X0) >> 4) : 0;
+        // Whole-vector strips ([0, nfast)): one item per (q subgrid rows,
+        // strip); consecutive lanes read consecutive strips of a row and all
+        // q * s_b rows of an item (8 or fewer) are loaded before they are
+        // added.  Other strips (right edge, misaligned rows): one padded row
+        // per item, added into the column sums with LDS atomics so that their
+        // latencies overlap.
+        const int nfast = in_aligned ? (int)min((int64_t)nstr, (lim - X0) >> 4) : 0;
         const int nslow = nstr - nfast;
         if (nslow > 0) {
             uint32_t* c32 = reinterpret_cast<uint32_t*>(col16);
@@ -641,7 +661,7 @@ __device__ void forward_tile_u8(const TileArgs& a, const FrameRec& F, const Tile
             }
             lds_barrier();
         }
-        const int q = rows_per_item(s);
+        const int q = band_inside ? rows_per_item(s) : 1;
         const int ngq = (ng + q - 1) / q;
         for (int it = tid; it < nfast * ngq; it += NT) {
             const int gq = it / nfast;
@@ -649,6 +669,11 @@ __device__ void forward_tile_u8(const TileArgs& a, const FrameRec& F, const Tile
             const int g0 = gq * q;
             const int qq = min(q, ng - g0);
             uint16_t* dst = col16 + g0 * rowbuf + 16 * st;
+            if (!band_inside) {
+                // last band: padded rows fold back into the frame
+                strip_rows_fold(img + X0 + 16 * st, pitch, r * b + (fr0 + g0) * s, s, H, pad, dst);
+                continue;
+            }
             // rows inside the frame: 32-bit offsets from the band's first row
             const uint32_t off = (uint32_t)((fr0 + g0) * s) * upitch + 16u * (uint32_t)st;
             switch (q) {
@@ -682,6 +707,8 @@ __device__ void forward_tile_u8(const TileArgs& a, const FrameRec& F, const Tile
             atomicAdd(cw + 6, (v.w & 0xFFu) | ((v.w & 0xFF00u) << 8));
             atomicAdd(cw + 7, ((v.w >> 16) & 0xFFu) | ((v.w >> 24) << 16));
         }
+        // classes and store indices of the tile's cells (wave 0), read while
+        // the row loads above are still in flight
         lds_barrier();
         for (int j = tid; j < items; j += NT) {
             const int fc = j / C, ch = j - fc * C;
