@@ -27,6 +27,7 @@ _LIB = os.path.join(_HERE, "libdppix_oracle.so")
 
 PAD_SYMMETRIC = 0
 PAD_REFLECT = 1
+PAD_NONE = 2          # Algorithm 1: border cells keep only their real pixels
 
 
 def build(force: bool = False) -> str:

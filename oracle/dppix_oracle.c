@@ -80,7 +80,8 @@ double orc_sigma(int32_t b, int32_t m, double eps)
 }
 
 /* Mirror padding (Algorithm 2 step 4 / Algorithm 3 step 3).  Symmetric mode
- * repeats the edge pixel (period 2L); reflect mode does not (period 2L-2). */
+ * repeats the edge pixel (period 2L); reflect mode does not (period 2L-2).
+ * Not defined for the unpadded mode, which never folds. */
 int64_t orc_fold(int64_t x, int64_t L, int32_t mode)
 {
     if (mode == ORC_PAD_SYMMETRIC) {
@@ -105,7 +106,7 @@ int32_t orc_check(const orc_params_t* p)
         return 1;
     if (p->tau < 0 || (int64_t)p->tau > (int64_t)p->b * p->b)
         return 1;
-    if (p->pad_mode != ORC_PAD_SYMMETRIC && p->pad_mode != ORC_PAD_REFLECT)
+    if (p->pad_mode != ORC_PAD_SYMMETRIC && p->pad_mode != ORC_PAD_REFLECT && p->pad_mode != ORC_PAD_NONE)
         return 1;
     return 0;
 }
@@ -157,35 +158,48 @@ int32_t orc_forward(const orc_params_t* p, const double* img, const uint8_t* mas
     /* Step 1-2: grid dimensions and padding sizes. */
     const int64_t HP = (int64_t)GR * b, WP = (int64_t)GC * b; /* M + P_R, N + P_C */
 
-    /* Step 3: mirror-pad image and mask to (M+P_R, N+P_C). */
+    /* Step 3: mirror-pad image and mask to (M+P_R, N+P_C).  In the unpadded
+     * mode (Algorithm 1) positions outside the frame stay empty: Rpad marks
+     * the real ones, and an empty position adds nothing to any sum or count. */
+    const int unpadded = p->pad_mode == ORC_PAD_NONE;
     double* Ipad = (double*)malloc(sizeof(double) * HP * WP * C);
     uint8_t* Fpad = (uint8_t*)malloc((size_t)(HP * WP));
+    uint8_t* Rpad = (uint8_t*)malloc((size_t)(HP * WP));
     double* Opad = (double*)malloc(sizeof(double) * HP * WP * C); /* I_grid after assignment */
     double* Dpad = (double*)malloc(sizeof(double) * HP * WP * C); /* same, before fp32 rounding */
-    if (!Ipad || !Fpad || !Opad || !Dpad) {
-        free(Ipad); free(Fpad); free(Opad); free(Dpad);
+    if (!Ipad || !Fpad || !Rpad || !Opad || !Dpad) {
+        free(Ipad); free(Fpad); free(Rpad); free(Opad); free(Dpad);
         return 2;
     }
-    for (int64_t i = 0; i < HP; ++i) {
-        int64_t si = orc_fold(i, M, p->pad_mode);
+    for (int64_t i = 0; i < HP; ++i)
         for (int64_t j = 0; j < WP; ++j) {
-            int64_t sj = orc_fold(j, N, p->pad_mode);
+            const int real = i < M && j < N;
+            Rpad[i * WP + j] = (uint8_t)(unpadded ? real : 1);
+            if (unpadded && !real) {
+                for (int64_t ch = 0; ch < C; ++ch)
+                    Ipad[(i * WP + j) * C + ch] = 0.0;
+                Fpad[i * WP + j] = 0;
+                continue;
+            }
+            int64_t si = unpadded ? i : orc_fold(i, M, p->pad_mode);
+            int64_t sj = unpadded ? j : orc_fold(j, N, p->pad_mode);
             for (int64_t ch = 0; ch < C; ++ch)
                 Ipad[(i * WP + j) * C + ch] = img[(si * N + sj) * C + ch];
             Fpad[i * WP + j] = mask ? (uint8_t)(mask[si * N + sj] != 0) : 0;
         }
-    }
 
     /* Steps 4-6: view as (G_R, G_C, b, b); mask statistic per grid; classify.
      * The mask here marks the foreground (the complement of the paper's simple
      * mask); a cell is complex when its foreground count reaches tau. */
-    const int64_t tau = p->tau > 0 ? p->tau : (b * b + 1) / 2;
     for (int64_t r = 0; r < GR; ++r)
         for (int64_t c = 0; c < GC; ++c) {
-            int64_t cnt = 0;
+            int64_t cnt = 0, area = 0;
             for (int64_t di = 0; di < b; ++di)
-                for (int64_t dj = 0; dj < b; ++dj)
+                for (int64_t dj = 0; dj < b; ++dj) {
                     cnt += Fpad[(r * b + di) * WP + (c * b + dj)];
+                    area += Rpad[(r * b + di) * WP + (c * b + dj)];
+                }
+            const int64_t tau = p->tau > 0 ? p->tau : (area + 1) / 2;
             flags[r * GC + c] = (uint8_t)(mask != NULL && cnt >= tau);
         }
 
@@ -223,11 +237,13 @@ int32_t orc_forward(const orc_params_t* p, const double* img, const uint8_t* mas
             if (flags[r * GC + c])
                 continue;
             for (int64_t ch = 0; ch < C; ++ch) {
-                double s = 0.0;
+                double s = 0.0, area = 0.0;
                 for (int64_t di = 0; di < b; ++di)
-                    for (int64_t dj = 0; dj < b; ++dj)
+                    for (int64_t dj = 0; dj < b; ++dj) {
                         s += Ipad[((r * b + di) * WP + (c * b + dj)) * C + ch];
-                double mu = s / (double)(b * b);
+                        area += Rpad[(r * b + di) * WP + (c * b + dj)];
+                    }
+                double mu = s / area;   /* b*b, or h*w real pixels (Algorithm 1) */
                 double eta = noise_for(p, (uint32_t)(r * GC + c), (int32_t)ch, 0, sigma_s,
                                        p->eps_simple);
                 double z = mu + eta;
@@ -258,18 +274,23 @@ int32_t orc_forward(const orc_params_t* p, const double* img, const uint8_t* mas
                 for (int64_t j = 0; j < n; ++j) {
                     uint32_t id = (uint32_t)((r * n + i) * ((int64_t)GC * n) + (c * n + j));
                     for (int64_t ch = 0; ch < C; ++ch) {
-                        double s = 0.0;
+                        double s = 0.0, area = 0.0;
                         for (int64_t di = 0; di < sb; ++di)
-                            for (int64_t dj = 0; dj < sb; ++dj)
+                            for (int64_t dj = 0; dj < sb; ++dj) {
                                 s += Ipad[((r * b + i * sb + di) * WP + (c * b + j * sb + dj)) * C + ch];
-                        double mu = s / (double)(sb * sb);
-                        double eta = noise_for(p, id, (int32_t)ch, 1, sigma_c, p->eps_complex);
-                        double z = mu + eta;
-                        double v = clip255(z);
+                                area += Rpad[(r * b + i * sb + di) * WP + (c * b + j * sb + dj)];
+                            }
                         int64_t at = (k * nn + i * n + j) * C + ch;
+                        double v = 0.0, z = 0.0;
+                        if (area > 0.0) {
+                            double mu = s / area;
+                            double eta = noise_for(p, id, (int32_t)ch, 1, sigma_c, p->eps_complex);
+                            z = mu + eta;
+                            v = clip255(z);
+                        }
                         fg[at] = (float)v;
                         if (pass_fg)
-                            pass_fg[at] = (uint8_t)(z >= 0.0 && z <= 255.0);
+                            pass_fg[at] = (uint8_t)(area > 0.0 && z >= 0.0 && z <= 255.0);
                         for (int64_t di = 0; di < sb; ++di)
                             for (int64_t dj = 0; dj < sb; ++dj) {
                                 int64_t o = ((r * b + i * sb + di) * WP + (c * b + j * sb + dj)) * C + ch;
@@ -298,14 +319,18 @@ int32_t orc_forward(const orc_params_t* p, const double* img, const uint8_t* mas
 
     free(Ipad);
     free(Fpad);
+    free(Rpad);
     free(Opad);
     free(Dpad);
     return 0;
 }
 
-/* Mirror index of a coordinate that may be -1 (one step before the start). */
+/* Mirror index of a coordinate that may be -1 (one step before the start);
+ * the unpadded mode mirrors like the symmetric one here. */
 static int64_t edge_fold(int64_t x, int64_t L, int32_t mode)
 {
+    if (mode == ORC_PAD_NONE)
+        mode = ORC_PAD_SYMMETRIC;
     if (x < 0) {
         if (mode == ORC_PAD_SYMMETRIC || L == 1)
             return 0;
@@ -476,12 +501,25 @@ int32_t orc_backward(const orc_params_t* p, const double* img, const uint8_t* ma
                                 if (y < M && x < N)
                                     G += grad_out[(y * N + x) * C + ch];
                             }
-                        double g = pass ? G / (double)(side * side) : 0.0;
-                        /* spread over every padded position, folded to its source */
+                        /* area: the full side^2, or the real pixels (Algorithm 1) */
+                        double area = (double)(side * side);
+                        if (p->pad_mode == ORC_PAD_NONE) {
+                            int64_t h = M - i0 < side ? M - i0 : side, w = N - j0 < side ? N - j0 : side;
+                            area = (h > 0 && w > 0) ? (double)(h * w) : 0.0;
+                        }
+                        double g = (pass && area > 0.0) ? G / area : 0.0;
+                        /* spread over every padded position, folded to its source
+                         * (unpadded mode: only the real positions themselves) */
                         for (int64_t di = 0; di < side; ++di)
                             for (int64_t dj = 0; dj < side; ++dj) {
-                                int64_t y = orc_fold(i0 + di, M, p->pad_mode);
-                                int64_t x = orc_fold(j0 + dj, N, p->pad_mode);
+                                int64_t y = i0 + di, x = j0 + dj;
+                                if (p->pad_mode == ORC_PAD_NONE) {
+                                    if (y >= M || x >= N)
+                                        continue;
+                                } else {
+                                    y = orc_fold(y, M, p->pad_mode);
+                                    x = orc_fold(x, N, p->pad_mode);
+                                }
                                 grad_in[(y * N + x) * C + ch] += g;
                             }
                     }

@@ -35,7 +35,12 @@
 extern "C" {
 #endif
 
-enum { ORC_PAD_SYMMETRIC = 0, ORC_PAD_REFLECT = 1 };
+/* Border handling.  SYMMETRIC / REFLECT: the frame is mirror-padded to whole
+ * cells (Algorithm 2 step 4, Algorithm 3 step 3) and every mean divides by
+ * the full cell area.  NONE: Algorithm 1 — a border cell (or subcell) holds
+ * only its h x w real pixels and its mean divides by h*w; a subcell with no
+ * real pixel releases nothing (value 0, no noise drawn). */
+enum { ORC_PAD_SYMMETRIC = 0, ORC_PAD_REFLECT = 1, ORC_PAD_NONE = 2 };
 
 typedef struct {
     int32_t  height, width, channels; /* M, N, C                                    */
@@ -45,9 +50,11 @@ typedef struct {
     double   eps_simple;              /* budget of simple cells; +inf = no noise     */
     double   eps_complex;             /* budget of complex subcells; +inf = no noise */
     int32_t  tau;                     /* complex iff foreground count >= tau;
-                                         0 selects ceil(b*b/2), the paper's
-                                         "simple iff simple-mask mean > 0.5" rule    */
-    int32_t  pad_mode;                /* ORC_PAD_SYMMETRIC or ORC_PAD_REFLECT        */
+                                         0 selects ceil(area/2) with area = b*b
+                                         (padded modes) or the cell's real pixel
+                                         count (NONE): the paper's "simple iff
+                                         simple-mask mean > 0.5" rule                */
+    int32_t  pad_mode;                /* ORC_PAD_SYMMETRIC, _REFLECT or _NONE        */
     uint64_t seed;                    /* Philox key                                  */
     uint64_t frame_index;             /* Philox counter words 2..3                   */
 } orc_params_t;
@@ -108,7 +115,7 @@ int32_t orc_forward(const orc_params_t* p, const double* img, const uint8_t* mas
  * Complexity label from the image itself (the paper's Sec. VI-A names the
  * Sobel operator as one way to obtain the mask).  S(i,j) = sum of the C
  * channels; Gx, Gy = 3x3 Sobel responses of S with neighbours past the border
- * mirrored (pad_mode); a pixel is an edge pixel (mask byte 1) when
+ * mirrored (pad_mode; NONE mirrors like SYMMETRIC); a pixel is an edge pixel (mask byte 1) when
  * |Gx| + |Gy| >= threshold * C.  img: M*N*C doubles (HWC, integer-valued);
  * out: M*N bytes.
  */
