@@ -53,7 +53,11 @@ typedef enum {
 
 typedef enum {
     DPPIX_PAD_SYMMETRIC = 0, /* mirror with the edge pixel repeated (default) */
-    DPPIX_PAD_REFLECT = 1    /* mirror without repeating the edge pixel       */
+    DPPIX_PAD_REFLECT = 1,   /* mirror without repeating the edge pixel       */
+    DPPIX_PAD_NONE = 2       /* no padding (Algorithm 1): a border cell or
+                                subcell holds only its h x w real pixels and
+                                its mean divides by h*w; a subcell with no
+                                real pixel releases 0 with no noise drawn     */
 } dppix_pad_t;
 
 /*
@@ -66,16 +70,19 @@ typedef enum {
  *   pitch              U8_HWC: bytes between rows (>= width*channels);
  *                      F32_CHW: floats between rows (>= width); channel planes
  *                      are pitch*height floats apart
- *   pad_mode           dppix_pad_t (Algorithm 2 step 4 / Algorithm 3 step 3)
+ *   pad_mode           dppix_pad_t (Algorithm 2 step 4 / Algorithm 3 step 3;
+ *                      NONE: Algorithm 1's border cells)
  *   b_bg               b, grid size of simple cells, 1..256
  *   b_fg               s_b, subgrid size of complex cells; b_bg % b_fg == 0 (Eq. 16)
  *   m                  pixels neighbouring images may differ in (Eq. 11), >= 1
  *   eps_bg, eps_fg     budgets of simple cells and complex subcells, > 0;
  *                      +INFINITY releases the exact mean (no noise)
  *   fg_min_count       tau: a cell is complex iff at least tau of its b*b
- *                      mirror-padded mask pixels are nonzero; 0 selects
- *                      ceil(b*b/2), the paper's "mean of the simple-region mask
- *                      <= 0.5" rule (Algorithm 3 step 6) for binary masks
+ *                      mirror-padded mask pixels (NONE: of its real mask
+ *                      pixels) are nonzero; 0 selects ceil(area/2), area = b*b
+ *                      (NONE: the cell's real pixel count), the paper's "mean
+ *                      of the simple-region mask <= 0.5" rule (Algorithm 3
+ *                      step 6) for binary masks
  *   tile_cells         coarse cells per work tile (0 = library default);
  *                      a tuning knob that never changes results
  *   seed               Philox4x32-10 key
@@ -134,7 +141,7 @@ typedef struct {
     int32_t grid_rows, grid_cols, n;   /* G_R, G_C, n                        */
     int32_t pad_rows, pad_cols;        /* P_R, P_C                           */
     int32_t tile_cells, tiles_per_band;
-    int32_t fg_min_count;              /* effective tau                      */
+    int32_t fg_min_count;              /* effective tau (0: per-cell majority of the real pixels, unpadded mode) */
     int64_t cell_offset;               /* first flag byte of this frame      */
     int64_t fine_offset;               /* first subcell in dense fine arrays */
     double sigma_bg, sigma_fg;         /* Eq. (11) scales; 0 when noise off  */
@@ -173,7 +180,8 @@ dppix_status_t dp_pix_plan(dppix_plan_t plan, const uint8_t* const* masks, const
 /* Region mask from the frames themselves (Sec. VI-A: the mask may come from an
  * edge detector such as the Sobel operator): for every real pixel, the 3x3
  * Sobel responses Gx, Gy of the sum of its channels, neighbours past the
- * border mirrored as pad_mode says; the mask byte is 1 when
+ * border mirrored as pad_mode says (NONE mirrors like SYMMETRIC); the mask
+ * byte is 1 when
  * |Gx| + |Gy| >= threshold * channels, else 0.
  *   images     device array of n_frames device pointers (U8_HWC frames only)
  *   threshold  0..4096, per-channel units

@@ -19,10 +19,10 @@ from dataclasses import dataclass, field
 from typing import List, Optional, Sequence
 
 from . import _lib
-from ._lib import DppixError, F32_CHW, PAD_REFLECT, PAD_SYMMETRIC, U8_HWC
+from ._lib import DppixError, F32_CHW, PAD_NONE, PAD_REFLECT, PAD_SYMMETRIC, U8_HWC
 
 __all__ = ["FrameParams", "Plan", "Graph", "DppixError", "pixelize", "DPPixFn", "debug_philox",
-           "U8_HWC", "F32_CHW", "PAD_SYMMETRIC", "PAD_REFLECT"]
+           "U8_HWC", "F32_CHW", "PAD_SYMMETRIC", "PAD_REFLECT", "PAD_NONE"]
 
 
 def _torch():

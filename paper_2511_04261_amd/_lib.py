@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(_HERE, "libdppix.so")
 
 DPPIX_OK, DPPIX_EINVAL, DPPIX_ENOMEM, DPPIX_EDEVICE, DPPIX_ENOTSUP = 0, 1, 2, 3, 4
 U8_HWC, F32_CHW = 0, 1
-PAD_SYMMETRIC, PAD_REFLECT = 0, 1
+PAD_SYMMETRIC, PAD_REFLECT, PAD_NONE = 0, 1, 2
 
 
 class DppixError(RuntimeError):

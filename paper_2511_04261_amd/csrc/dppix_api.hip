@@ -102,7 +102,7 @@ dppix_status_t validate(const dppix_frame_desc_t& d, int32_t f)
         return bad("pitch must be >= width*channels bytes");
     if (d.layout == DPPIX_F32_CHW && d.pitch < (int64_t)d.width)
         return bad("pitch must be >= width floats");
-    if (d.pad_mode != DPPIX_PAD_SYMMETRIC && d.pad_mode != DPPIX_PAD_REFLECT)
+    if (d.pad_mode != DPPIX_PAD_SYMMETRIC && d.pad_mode != DPPIX_PAD_REFLECT && d.pad_mode != DPPIX_PAD_NONE)
         return bad("unknown pad_mode");
     if (d.b_fg < 1 || d.b_bg < d.b_fg)
         return bad("need 1 <= b_fg <= b_bg");
@@ -237,7 +237,9 @@ dppix_status_t dp_pix_plan_create(const dppix_frame_desc_t* descs, int32_t n_fra
         F.pad = d.pad_mode;
         F.GR = (d.height + d.b_bg - 1) / d.b_bg;   // G_R = ceil(M / b)
         F.GC = (d.width + d.b_bg - 1) / d.b_bg;    // G_C = ceil(N / b)
-        F.tau = d.fg_min_count > 0 ? d.fg_min_count : (d.b_bg * d.b_bg + 1) / 2;
+        // tau = 0 in the unpadded mode: majority of each cell's real pixels
+        F.tau = d.fg_min_count > 0 ? d.fg_min_count
+                                   : (d.pad_mode == DPPIX_PAD_NONE ? 0 : (d.b_bg * d.b_bg + 1) / 2);
         F.noise_bg = std::isinf(d.eps_bg) ? 0 : 1;
         F.noise_fg = std::isinf(d.eps_fg) ? 0 : 1;
         F.sigma_bg = F.noise_bg ? sigma_of(F.b, d.m, d.eps_bg) : 0.0;

@@ -85,6 +85,10 @@ __device__ __forceinline__ double laplace_sample(const FrameRec& F, uint32_t id,
 __device__ __forceinline__ float release(double sum, double area, int noisy, double sigma, const FrameRec& F,
                                          uint32_t id, int ch, int level, uint8_t& pass)
 {
+    if (area == 0.0) {   // unpadded mode: a subcell with no real pixel releases nothing
+        pass = 0;
+        return 0.f;
+    }
     const double mu = sum / area;
     const double z = noisy ? mu + laplace_sample(F, id, ch, level, sigma) : mu;
     pass = (uint8_t)(z >= 0.0 && z <= 255.0);
@@ -113,6 +117,22 @@ __device__ __forceinline__ int fold(int x, int L, int mode)
     const int p = 2 * L - 2;
     const int y = x % p;
     return y < L ? y : p - y;
+}
+
+// Unpadded border mode (Algorithm 1): positions past the frame are absent —
+// they add nothing to sums or mask counts, and each (sub)cell's mean divides
+// by its real pixel count.
+constexpr int kPadNone = 2;
+
+// Real-pixel area of the statistic whose (sub)cell starts at padded (y0, x0)
+// with the given side: side^2 when the frame is mirror-padded; h*w real
+// pixels in the unpadded mode (0 for a subcell wholly past the frame).
+__device__ __forceinline__ double stat_area(const FrameRec& F, int y0, int x0, int side)
+{
+    if (F.pad != kPadNone)
+        return (double)side * (double)side;
+    const int h = min(side, F.H - y0), w = min(side, F.W - x0);
+    return (h > 0 && w > 0) ? (double)h * (double)w : 0.0;
 }
 
 __device__ __forceinline__ uint32_t uniform_u32(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -154,8 +174,9 @@ __device__ __forceinline__ void store_colsums16(uint16_t* dst, const uint32_t (&
 }
 
 // Gather one 16-byte strip of a padded row byte by byte: columns past the
-// image fold back (mirror), bytes past the tile end read as zero.  Only the
-// strips that cross the right edge or a misaligned row take this path.
+// image fold back (mirror; zero in the unpadded mode), bytes past the tile
+// end read as zero.  Only the strips that cross the right edge or a
+// misaligned row take this path.
 template <int C>
 __device__ __noinline__ v4u gather_strip_u8(const uint8_t* row, int p0, int tile_end, int W, int pad)
 {
@@ -163,12 +184,14 @@ __device__ __noinline__ v4u gather_strip_u8(const uint8_t* row, int p0, int tile
     const g_u8* src = (const g_u8*)row;
     // source offsets first (folding branches), then 16 unconditional byte
     // loads issued back to back; bytes past the tile end are masked after
+    // (the unpadded mode reads columns past the frame as zero)
+    const int end = pad == kPadNone ? min(tile_end, W * C) : tile_end;
     int idx[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
         const int p = p0 + q;
         const int x = p / C, ch = p - x * C;
-        idx[q] = p < tile_end ? fold(x, W, pad) * C + ch : 0;
+        idx[q] = p < end ? fold(x, W, pad) * C + ch : 0;
     }
     uint32_t v[16];
 #pragma unroll
@@ -176,7 +199,7 @@ __device__ __noinline__ v4u gather_strip_u8(const uint8_t* row, int p0, int tile
         v[q] = src[idx[q]];
 #pragma unroll
     for (int q = 0; q < 16; ++q)
-        v[q] = p0 + q < tile_end ? v[q] : 0u;
+        v[q] = p0 + q < end ? v[q] : 0u;
     return v4u{v[0] | (v[1] << 8) | (v[2] << 16) | (v[3] << 24), v[4] | (v[5] << 8) | (v[6] << 16) | (v[7] << 24),
                v[8] | (v[9] << 8) | (v[10] << 16) | (v[11] << 24),
                v[12] | (v[13] << 8) | (v[14] << 16) | (v[15] << 24)};
@@ -419,7 +442,8 @@ __device__ void plan_count(const TileArgs& a, const FrameRec& F, const uint8_t* 
                 acc_bytes(nz_strip(ld16_nt(col + (int64_t)k * W)), e, o);
         } else {
             for (int k = k0; k < k1; ++k)
-                acc_bytes(nz_strip(ld16_nt(mask + (int64_t)fold(row0 + k, H, pad) * W + p0)), e, o);
+                if (row0 + k < H || pad != kPadNone)
+                    acc_bytes(nz_strip(ld16_nt(mask + (int64_t)fold(row0 + k, H, pad) * W + p0)), e, o);
         }
         spread_strip(e, o, cellcnt + j * KCs, KC, b, 16 * st);
     }
@@ -428,6 +452,8 @@ __device__ void plan_count(const TileArgs& a, const FrameRec& F, const uint8_t* 
         const int rest = item / nslow;
         const int k = rest % b, j = rest / b;
         const int64_t p0 = X0 + 16 * st;
+        if ((r0 + j) * b + k >= H && pad == kPadNone)
+            continue;
         uint32_t e[4] = {0, 0, 0, 0}, o[4] = {0, 0, 0, 0};
         acc_bytes(nz_strip(gather_strip_u8<1>(mask + (int64_t)fold((r0 + j) * b + k, H, pad) * W, (int)p0,
                                               (int)(X0 + WB), W, pad)),
@@ -463,7 +489,10 @@ __global__ __launch_bounds__(kMaxThreads) void k_plan(TileArgs a)
     lds_barrier();
     for (int i = tid; i < nb * KC; i += NT) {
         const int j = i / KC, kc = i - j * KC;
-        const uint8_t fl = (uint8_t)(cellcnt[j * KCs + kc] >= (uint32_t)F.tau);
+        // tau = 0 (unpadded mode only): majority of the cell's real pixels
+        const uint32_t tau = F.tau > 0 ? (uint32_t)F.tau
+                                       : ((uint32_t)stat_area(F, (r0 + j) * F.b, (c0 + kc) * F.b, F.b) + 1u) / 2u;
+        const uint8_t fl = (uint8_t)(cellcnt[j * KCs + kc] >= tau);
         a.flags[F.cell_base + (int64_t)(r0 + j) * F.GC + c0 + kc] = fl;
         if (fl)
             atomicAdd(&tcnt[j * F.ctx + kc / F.K], 1u);
@@ -553,6 +582,8 @@ __device__ __forceinline__ void strip_rows_fold(const uint8_t* col, int64_t pitc
                                                 uint16_t* dst)
 {
     uint32_t e[4] = {0, 0, 0, 0}, o[4] = {0, 0, 0, 0};
+    if (pad == kPadNone)   // rows past the frame are absent
+        s = max(0, min(s, H - row0));
     int k = 0;
     for (; k + 4 <= s; k += 4) {
         v4u w[4];
@@ -692,6 +723,8 @@ __device__ void forward_tile_u8(const TileArgs& a, const FrameRec& F, const Tile
             const int rest = it / nslow;
             const int k = rest % s, g = rest / s;
             const int64_t p0 = X0 + 16 * st;
+            if (r * b + (fr0 + g) * s + k >= H && pad == kPadNone)
+                continue;
             const uint8_t* rp = img + (int64_t)fold(r * b + (fr0 + g) * s + k, H, pad) * pitch;
             const v4u v = (in_aligned && p0 + 16 <= lim) ? ld16_nt(rp + p0)
                                                          : gather_strip_u8<C>(rp, (int)p0, (int)tile_end, W, pad);
@@ -728,7 +761,8 @@ __device__ void forward_tile_u8(const TileArgs& a, const FrameRec& F, const Tile
                 if (cx) {
                     const uint32_t id = (uint32_t)(r * n + fr) * (uint32_t)(F.GC * n) + (uint32_t)(x0c * n + fc);
                     uint8_t pass;
-                    const float v = release((double)S, (double)(s * s), F.noise_fg, F.sigma_fg, F, id, ch, 1, pass);
+                    const double area = stat_area(F, r * b + fr * s, x0c * b + fc * s, s);
+                    const float v = release((double)S, area, F.noise_fg, F.sigma_fg, F, id, ch, 1, pass);
                     const uint64_t at = fg_base + ((uint64_t)cidx[kc] * nn + fr * n + jj) * C + ch;
                     a.fg[at] = v;
                     if (a.clip_fg)
@@ -752,7 +786,8 @@ __device__ void forward_tile_u8(const TileArgs& a, const FrameRec& F, const Tile
         if (!cflag[kc]) {
             const uint32_t id = (uint32_t)(r * F.GC + x0c + kc);
             uint8_t pass;
-            const float v = release((double)S, (double)(b * b), F.noise_bg, F.sigma_bg, F, id, ch, 0, pass);
+            const float v = release((double)S, stat_area(F, r * b, (x0c + kc) * b, b), F.noise_bg, F.sigma_bg, F,
+                                    id, ch, 0, pass);
             const uint64_t at = bg_base + (uint64_t)cidx[kc] * C + ch;
             a.bg[at] = v;
             if (a.clip_bg)
@@ -860,17 +895,20 @@ __device__ void forward_tile_f32(const TileArgs& a, const FrameRec& F, const Til
             for (int st = tid; st < nstr; st += NT) {
                 const int64_t p0 = X0 + 4 * st;
                 v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
+                // rows past the frame are absent in the unpadded mode
+                const int srows = pad == kPadNone ? max(0, min(s, H - row0)) : s;
+                const int64_t cend = pad == kPadNone ? lim : tile_end;
                 if (in_aligned && p0 + 4 <= lim) {
-                    for (int k = 0; k < s; ++k) {
+                    for (int k = 0; k < srows; ++k) {
                         acc += ld16f_nt(pl + (int64_t)fold(row0 + k, H, pad) * pitch + p0);
                     }
                 } else {
-                    for (int k = 0; k < s; ++k) {
+                    for (int k = 0; k < srows; ++k) {
                         const float* rk = pl + (int64_t)fold(row0 + k, H, pad) * pitch;
                         float v[4];
 #pragma unroll
                         for (int q = 0; q < 4; ++q)
-                            v[q] = (p0 + q < tile_end) ? rk[fold((int)(p0 + q), W, pad)] : 0.f;
+                            v[q] = (p0 + q < cend) ? rk[fold((int)(p0 + q), W, pad)] : 0.f;
                         acc.x += v[0]; acc.y += v[1]; acc.z += v[2]; acc.w += v[3];
                     }
                 }
@@ -887,7 +925,8 @@ __device__ void forward_tile_f32(const TileArgs& a, const FrameRec& F, const Til
                 if (cflag[kc]) {
                     const uint32_t id = (uint32_t)(r * n + fr) * (uint32_t)(F.GC * n) + (uint32_t)(x0c * n + fc);
                     uint8_t pass;
-                    const float v = release(S, (double)(s * s), F.noise_fg, F.sigma_fg, F, id, ch, 1, pass);
+                    const float v = release(S, stat_area(F, row0, x0c * b + fc * s, s), F.noise_fg, F.sigma_fg, F, id,
+                                            ch, 1, pass);
                     const uint64_t at = fg_base + ((uint64_t)cidx[kc] * nn + fr * n + jj) * C + ch;
                     a.fg[at] = v;
                     if (a.clip_fg)
@@ -907,7 +946,8 @@ __device__ void forward_tile_f32(const TileArgs& a, const FrameRec& F, const Til
             S += cspart[(kc * n + jj) * C + ch];
         const uint32_t id = (uint32_t)(r * F.GC + x0c + kc);
         uint8_t pass;
-        const float v = release(S, (double)(b * b), F.noise_bg, F.sigma_bg, F, id, ch, 0, pass);
+        const float v = release(S, stat_area(F, r * b, (x0c + kc) * b, b), F.noise_bg, F.sigma_bg, F, id, ch, 0,
+                                pass);
         const uint64_t at = bg_base + (uint64_t)cidx[kc] * C + ch;
         a.bg[at] = v;
         if (a.clip_bg)
@@ -1241,7 +1281,8 @@ __device__ void backward_reduce_tile(const TileArgs& a, const FrameRec& F, const
                 cspart[ci] = (fr == 0 ? 0.0 : cspart[ci]) + G;
                 if (cflag[kc]) {
                     const uint64_t at = fg_base + ((uint64_t)cidx[kc] * nn + fr * n + jj) * C + ch;
-                    a.g_fg[at] = a.clip_fg[at] ? (float)(G / (double)(s * s)) : 0.f;
+                    const double area = stat_area(F, row0, x0c * b + fc * s, s);
+                    a.g_fg[at] = (a.clip_fg[at] && area > 0.0) ? (float)(G / area) : 0.f;
                 }
             }
             lds_barrier();
@@ -1255,7 +1296,7 @@ __device__ void backward_reduce_tile(const TileArgs& a, const FrameRec& F, const
         for (int jj = 0; jj < n; ++jj)
             G += cspart[(kc * n + jj) * C + ch];
         const uint64_t at = bg_base + (uint64_t)cidx[kc] * C + ch;
-        a.g_bg[at] = a.clip_bg[at] ? (float)(G / (double)(b * b)) : 0.f;
+        a.g_bg[at] = a.clip_bg[at] ? (float)(G / stat_area(F, r * b, (x0c + kc) * b, b)) : 0.f;
     }
 }
 
@@ -1288,7 +1329,8 @@ __device__ void backward_spread_tile(const TileArgs& a, const FrameRec& F, const
     const int xa = x0c * b, xb = min((x0c + Kt) * b, W);
     if (y0 >= H || xa >= W)
         return;
-    const int PR = F.GR * b - H, PC = F.GC * b - W;
+    // padded rows / columns past the frame (none count in the unpadded mode)
+    const int PR = pad == kPadNone ? 0 : F.GR * b - H, PC = pad == kPadNone ? 0 : F.GC * b - W;
     // rows at or above lo_r (columns at or above lo_c) may have mirror preimages
     const int lo_r = (PR > 0) ? ((PR <= H - 1) ? H - 1 - PR : 0) : H;
     const int lo_c = (PC > 0) ? ((PC <= W - 1) ? W - 1 - PC : 0) : W;
@@ -1338,6 +1380,8 @@ constexpr int kEdgeCols = 512;
 // Mirror index of a coordinate in [-1, 2L).
 __device__ __forceinline__ int edge_fold(int x, int L, int mode)
 {
+    if (mode == kPadNone)   // the Sobel stencil mirrors like the symmetric mode
+        mode = 0;
     if (x < 0)
         return (mode == 0 || L == 1) ? 0 : 1;
     return fold(x, L, mode);

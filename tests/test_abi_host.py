@@ -103,7 +103,7 @@ def info(h, L, f=0):
     (dict(height=10, width=10, eps_bg=float("nan")), _lib.DPPIX_EINVAL),
     (dict(height=10, width=10, tau=257, b=16), _lib.DPPIX_EINVAL),
     (dict(height=10, width=10, pitch=5), _lib.DPPIX_EINVAL),
-    (dict(height=10, width=10, pad_mode=2), _lib.DPPIX_EINVAL),
+    (dict(height=10, width=10, pad_mode=3), _lib.DPPIX_EINVAL),
     (dict(height=10, width=10, layout=7), _lib.DPPIX_EINVAL),
     (dict(height=10, width=10, b=512, sb=512), _lib.DPPIX_ENOTSUP),
     (dict(height=1 << 25, width=10), _lib.DPPIX_ENOTSUP),

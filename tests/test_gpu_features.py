@@ -207,7 +207,7 @@ def test_serving_alone_equals_mix(dev):
 
 @pytest.mark.parametrize("H,W,C,b,sb,T,pad", [(75, 97, 3, 16, 4, 60, 0), (270, 480, 3, 32, 8, 40, 0),
                                               (33, 40, 1, 8, 2, 30, 1), (1080, 1920, 3, 32, 8, 48, 0),
-                                              (5, 3, 3, 8, 4, 10, 0)])
+                                              (5, 3, 3, 8, 4, 10, 0), (45, 70, 3, 16, 4, 40, 2)])
 def test_edge_mask_label_matches_oracle(dev, H, W, C, b, sb, T, pad):
     """Sobel complexity labels bit-exact against the oracle, then the whole
     path driven by them against the oracle driven by the oracle's labels."""

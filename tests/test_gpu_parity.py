@@ -88,6 +88,16 @@ CASES = [
     (50, 64, 3, 24, 3, 0, 1, 0.1),    # s_b = 3, n = 8
     (33, 112, 2, 32, 4, 0, 1, 0.2),   # s_b = 4, n = 8, padded second band
     (40, 48, 1, 4, 1, 0, 1, 0.3),     # s_b = 1
+    # unpadded border mode (Algorithm 1): partial cells, empty subcells
+    (75, 97, 3, 16, 4, 2, 1, 0.1),    # misaligned rows
+    (70, 96, 3, 12, 3, 2, 0, 0.3),    # majority rule over real pixels, partial last band
+    (45, 80, 1, 6, 2, 2, 1, 0.3),
+    (33, 112, 2, 32, 4, 2, 1, 0.2),   # right-edge cells with subcells past the frame
+    (129, 300, 3, 64, 16, 2, 1, 0.1),
+    (5, 3, 1, 8, 2, 2, 1, 0.3),       # frame smaller than one cell
+    (96, 1000, 3, 32, 4, 2, 1, 0.02),
+    (1080, 1920, 3, 32, 8, 2, 1, 0.05),  # partial last band at full width
+    (400, 6000, 3, 32, 8, 2, 1, 0.05),   # partial right-edge cells, vector path elsewhere
 ]
 
 
@@ -192,13 +202,14 @@ def test_region_batch_1080p_sampled(dev):
         assert st["bg"].min() >= 0 and st["fg"].max() <= 255
 
 
-def test_fp32_chw_forward_and_reconstruct(dev):
-    say("case: fp32 CHW")
+@pytest.mark.parametrize("pad", [dp.PAD_SYMMETRIC, dp.PAD_NONE])
+def test_fp32_chw_forward_and_reconstruct(dev, pad):
+    say("case: fp32 CHW", pad)
     r = rng(12)
     C, H, W = 3, 61, 57
     x = synth.uniform_f32(r, (C, H, W))
     mask = synth.rect_mask(r, H, W, n_rects=3, rect_frac=0.05, cover=(0.05, 0.4))
-    fp = dp.FrameParams(H, W, C, dp.F32_CHW, b=16, sb=8, m=8, eps_bg=1.0, eps_fg=0.5, tau=1, seed=3)
+    fp = dp.FrameParams(H, W, C, dp.F32_CHW, b=16, sb=8, m=8, eps_bg=1.0, eps_fg=0.5, tau=1, seed=3, pad_mode=pad)
     res = run_gpu([fp], [x], [mask], dev)
     want = oracle.forward(chw_to_hwc(x), mask, oracle_params(fp))
     compare_frame(res["store"][0], want, chw_to_hwc(res["fused"][0]), "fused f32")
@@ -206,7 +217,7 @@ def test_fp32_chw_forward_and_reconstruct(dev):
 
 
 @pytest.mark.parametrize("C,H,W,b,sb,pad", [(3, 64, 64, 16, 8, 0), (3, 61, 57, 16, 8, 0), (1, 13, 29, 8, 4, 1),
-                                          (2, 5, 3, 8, 2, 0)])
+                                          (2, 5, 3, 8, 2, 0), (3, 61, 57, 16, 8, 2), (1, 13, 29, 8, 2, 2)])
 def test_backward_matches_oracle_gradient(dev, C, H, W, b, sb, pad):
     say("case: backward", C, H, W, b, sb, pad)
     r = rng(C * H * W)
