@@ -209,13 +209,17 @@ __device__ __noinline__ v4u gather_strip_u8(const uint8_t* row, int p0, int tile
 // complex cells count from the number of complex cells of the frame before
 // the tile, simple cells from the simple ones — row-major order, which is the
 // order of the compact store.
+// With cxl, also the list of the tile's complex cells in order (cxl[q] = kc
+// of the q-th complex cell) and their number in *ncx.
 __device__ __forceinline__ void tile_cells(const TileArgs& a, const FrameRec& F, int64_t t, int r, int x0c, int Kt,
-                                           uint32_t* cidx, uint8_t* cflag, bool write_store_flags)
+                                           uint32_t* cidx, uint8_t* cflag, bool write_store_flags,
+                                           uint16_t* cxl = nullptr, uint32_t* ncx = nullptr)
 {
     if (threadIdx.x >= 64)
         return;
     const int lane = threadIdx.x;
     uint32_t run_fg = a.tile_fg[t];
+    const uint32_t fg0 = run_fg;
     const uint32_t before = (uint32_t)(r * F.GC + x0c);
     uint32_t run_bg = before - run_fg;
     for (int base = 0; base < Kt; base += 64) {
@@ -228,6 +232,8 @@ __device__ __forceinline__ void tile_cells(const TileArgs& a, const FrameRec& F,
         if (in) {
             cflag[kc] = fl;
             cidx[kc] = fl ? run_fg + pc : run_bg + (uint32_t)lane - pc;
+            if (cxl && fl)
+                cxl[run_fg - fg0 + pc] = (uint16_t)kc;
             if (write_store_flags && a.store_flags)
                 a.store_flags[F.cell_base + before + kc] = fl;
             if (a.cell_index)
@@ -238,6 +244,8 @@ __device__ __forceinline__ void tile_cells(const TileArgs& a, const FrameRec& F,
         run_fg += nf;
         run_bg += nv - nf;
     }
+    if (ncx && lane == 0)
+        *ncx = run_fg - fg0;
 }
 
 struct TileCoord {
@@ -662,8 +670,10 @@ __device__ void forward_tile_u8(const TileArgs& a, const FrameRec& F, const Tile
     uint8_t* cflag = lds + L.cflag;
     uint8_t* vgs = lds + L.vgs;
     uint8_t* vgc = lds + L.vgc;
+    uint16_t* cxl = reinterpret_cast<uint16_t*>(lds + L.cxl);
+    __shared__ uint32_t s_ncx;
 
-    tile_cells(a, F, tc.t, r, x0c, Kt, cidx, cflag, true);
+    tile_cells(a, F, tc.t, r, x0c, Kt, cidx, cflag, true, cxl, &s_ncx);
     const uint64_t bg_base = a.frame_base[2 * tc.f + 0];
     const uint64_t fg_base = a.frame_base[2 * tc.f + 1];
     const int items = Kt * n * C;
@@ -743,34 +753,49 @@ __device__ void forward_tile_u8(const TileArgs& a, const FrameRec& F, const Tile
         // classes and store indices of the tile's cells (wave 0), read while
         // the row loads above are still in flight
         lds_barrier();
+        // running sums of every (subcell column, channel) for the coarse cells
         for (int j = tid; j < items; j += NT) {
             const int fc = j / C, ch = j - fc * C;
-            const int kc = fc / n, jj = fc - kc * n;
-            const bool cx = cflag[kc] != 0;
             uint32_t total = fr0 == 0 ? 0u : cspart[j];
             for (int g = 0; g < ng; ++g) {
-                const int fr = fr0 + g;
                 const uint16_t* cp = col16 + g * rowbuf + fc * s * C + ch;
                 uint32_t S = 0;
                 for (int x = 0; x < s; ++x)
                     S += cp[x * C];
                 total += S;
                 if (a.dbg_fine)
-                    a.dbg_fine[(F.fine_base + (int64_t)(r * n + fr) * ((int64_t)F.GC * n) + (int64_t)x0c * n + fc) * C +
-                               ch] = S;
-                if (cx) {
-                    const uint32_t id = (uint32_t)(r * n + fr) * (uint32_t)(F.GC * n) + (uint32_t)(x0c * n + fc);
-                    uint8_t pass;
-                    const double area = stat_area(F, r * b + fr * s, x0c * b + fc * s, s);
-                    const float v = release((double)S, area, F.noise_fg, F.sigma_fg, F, id, ch, 1, pass);
-                    const uint64_t at = fg_base + ((uint64_t)cidx[kc] * nn + fr * n + jj) * C + ch;
-                    a.fg[at] = v;
-                    if (a.clip_fg)
-                        a.clip_fg[at] = pass;
-                    vgc[(fr * Kt * n + fc) * C + ch] = to_u8(v);
-                }
+                    a.dbg_fine[(F.fine_base + (int64_t)(r * n + fr0 + g) * ((int64_t)F.GC * n) + (int64_t)x0c * n +
+                                fc) * C + ch] = S;
             }
             cspart[j] = total;
+        }
+        // releases of the complex cells' subcells, spread evenly over the
+        // lanes (only complex cells draw noise, so a lane-per-subcell loop
+        // would leave the lanes of simple cells idle); each sum is re-read
+        // from the column sums
+        const int ncx = (int)s_ncx;
+        const int per_cx = ng * n * C;
+        for (int it = tid; it < ncx * per_cx; it += NT) {
+            const int q = it / per_cx;
+            const int rem = it - q * per_cx;
+            const int g = rem / (n * C);
+            const int rem2 = rem - g * (n * C);
+            const int jj = rem2 / C, ch = rem2 - jj * C;
+            const int kc = cxl[q];
+            const int fc = kc * n + jj, fr = fr0 + g;
+            const uint16_t* cp = col16 + g * rowbuf + fc * s * C + ch;
+            uint32_t S = 0;
+            for (int x = 0; x < s; ++x)
+                S += cp[x * C];
+            const uint32_t id = (uint32_t)(r * n + fr) * (uint32_t)(F.GC * n) + (uint32_t)(x0c * n + fc);
+            uint8_t pass;
+            const double area = stat_area(F, r * b + fr * s, x0c * b + fc * s, s);
+            const float v = release((double)S, area, F.noise_fg, F.sigma_fg, F, id, ch, 1, pass);
+            const uint64_t at = fg_base + ((uint64_t)cidx[kc] * nn + fr * n + jj) * C + ch;
+            a.fg[at] = v;
+            if (a.clip_fg)
+                a.clip_fg[at] = pass;
+            vgc[(fr * Kt * n + fc) * C + ch] = to_u8(v);
         }
         lds_barrier();
     }

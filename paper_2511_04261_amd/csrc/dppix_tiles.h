@@ -25,6 +25,7 @@ struct LdsPlan {
     uint32_t cflag;   // per cell: 1 = complex
     uint32_t vgs;     // per (cell, channel): value of a simple cell
     uint32_t vgc;     // per (subcell row, subcell column, channel): value of a complex subcell
+    uint32_t cxl;     // u8 forward: the tile's complex cells in order (uint16 each)
     uint32_t bytes;
 };
 
@@ -72,6 +73,9 @@ __host__ __device__ inline LdsPlan lds_plan(int kind, int K, int b, int n, int C
         o += al16((uint32_t)(K * n * n * C));
     else if (kind == kFwdF32 || kind == kRecF32)
         o += al16(4u * (uint32_t)(K * n * n * C));
+    p.cxl = o;
+    if (kind == kFwdU8)
+        o += al16(2u * (uint32_t)K);
     p.bytes = o;
     return p;
 }
