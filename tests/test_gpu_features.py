@@ -90,12 +90,13 @@ def test_autotuned_shapes_are_bitwise_identical(dev, tmp_path):
 
 def test_uneven_batch_full_size_sampled(dev):
     """256 frames of 768x576 .. 6000x4000, per-frame grids and budgets, one
-    persistent graph-replayed launch; one frame of each resolution checked
-    in full against the oracle, all frames for store invariants."""
+    graph-replayed launch in the benchmark's configuration (one workgroup per
+    tile); one frame of each resolution checked in full against the oracle,
+    all frames for store invariants."""
     say("case: uneven 256-frame batch")
     specs = synth.uneven_batch(256)
     frames = [dp.FrameParams.from_spec(s) for s in specs]
-    plan = dp.Plan(frames, device=dev, persistent=True)
+    plan = dp.Plan(frames, device=dev)
     imgs = [s.image_torch(dev) for s in specs]
     masks = [s.mask_torch(dev) for s in specs]
     outs = [torch.empty_like(t) for t in imgs]

@@ -96,6 +96,10 @@ CASES = [
     (129, 300, 3, 64, 16, 2, 1, 0.1),
     (5, 3, 1, 8, 2, 2, 1, 0.3),       # frame smaller than one cell
     (96, 1000, 3, 32, 4, 2, 1, 0.02),
+    (300, 520, 3, 256, 32, 0, 1, 0.1),   # largest grid (b = 256): 16-bit column sums at their limit
+    (256, 256, 1, 256, 256, 1, 1, 0.5),  # one 256 x 256 cell per frame, n = 1
+    (200, 304, 3, 16, 4, 0, 1, 1.0),     # every cell complex
+    (200, 304, 1, 16, 4, 0, 1, 0.0),     # a mask with no foreground: every cell simple
     (1080, 1920, 3, 32, 8, 2, 1, 0.05),  # partial last band at full width
     (400, 6000, 3, 32, 8, 2, 1, 0.05),   # partial right-edge cells, vector path elsewhere
 ]
@@ -182,16 +186,26 @@ def test_launch_shapes_are_bitwise_identical(dev, threads, persistent, tile):
 def test_region_batch_1080p_sampled(dev):
     """64 RGB 1920x1080 frames, 8-rectangle masks, b=32/eps=1.0 simple,
     s_b=8/eps=0.3 complex, m=16, in the launch configuration the benchmark
-    times (persistent); three frames checked in full against the oracle and
+    times (default workgroups, one per tile, plan + forward captured in a
+    graph and replayed); three frames checked in full against the oracle and
     every frame for invariants."""
     say("case: 64x1080p batch")
     frames_s = synth.region_batch(64)
     frames = [dp.FrameParams.from_spec(s) for s in frames_s]
-    res = run_gpu(frames, [s.image for s in frames_s], [s.mask for s in frames_s], dev, persistent=True,
-                  reconstruct=False)
+    plan = dp.Plan(frames, device=dev)
+    imgs = [s.image_torch(dev) for s in frames_s]
+    masks = [s.mask_torch(dev) for s in frames_s]
+    outs = [torch.empty_like(t) for t in imgs]
+    g = plan.graph(masks, imgs, outs)
+    g.launch()
+    g.launch()
+    torch.cuda.synchronize()
+    store = plan.store_host()
     for i in (0, 31, 63):
-        want = oracle.forward(frames_s[i].image, frames_s[i].mask, oracle_params(frames[i]))
-        compare_frame(res["store"][i], want, res["fused"][i], "frame %d" % i)
+        want = oracle.forward(imgs[i].cpu().numpy(), frames_s[i].mask, oracle_params(frames[i]))
+        compare_frame(store[i], want, outs[i].cpu().numpy(), "frame %d" % i)
+    g.close()
+    res = {"store": store}
     off_b = off_f = 0
     for i, st in enumerate(res["store"]):
         nb, nf = st["counts"]
