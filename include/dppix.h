@@ -242,7 +242,9 @@ dppix_status_t dp_pix_backward(dppix_plan_t plan, const dppix_store_t* store, co
  * ------------------------------------------------------------------------- */
 
 /* Launch shape of the tile kernels: threads per workgroup (64..512, multiple
- * of 64; 0 = default) and the work distribution: persistent = 0 launches one
+ * of 64; 0 = the default: 256, except forward and reconstruction tiles with
+ * few row items per tile, which run 128 per workgroup in a launch of their
+ * own) and the work distribution: persistent = 0 launches one
  * workgroup per tile (the hardware dispatcher feeds the CUs; the default);
  * persistent = 1 launches as many workgroups as the CUs hold at once and
  * persistent = k in 2..64 launches k per CU — those workgroups stay resident

@@ -22,7 +22,8 @@ from . import F32_CHW, U8_HWC, FrameParams, Plan
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "dppix", "autotune.json")
 TILE_BYTES = (1024, 2048, 4096, 8192)
-THREADS = (128, 192, 256, 512)
+#: 0: the library's per-class choice (128 for tiles with few row items, else 256)
+THREADS = (0, 128, 192, 256, 512)
 #: 0: one workgroup per tile; 1: resident grid pulling tiles from a ticket
 LAUNCH_MODES = (0, 1)
 

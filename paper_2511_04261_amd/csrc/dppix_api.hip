@@ -43,9 +43,10 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 }  // namespace
 
-// Frames sharing layout and channel count, launched together.
+// Frames sharing layout, channel count and workgroup size, launched together.
 struct LaunchGroup {
     int layout, C;
+    int threads;          // workgroup size chosen for the group's tiles
     int64_t lo, hi;       // scheduling-index range
     size_t lds_fwd, lds_rec;
 };
@@ -65,7 +66,7 @@ struct dppix_plan {
     size_t lds[6] = {0, 0, 0, 0, 0, 0};
     std::vector<LaunchGroup> groups;
     bool any_f32 = false, any_u8 = false;
-    int threads = kDefaultThreads;
+    int threads = 0;                    // 0: per launch group (forward, reconstruct), else fixed
     int persistent = 0;
     int cus = 0;                        // compute units of the device (queried once)
     uint8_t* bound = nullptr;
@@ -184,6 +185,20 @@ void choose_tiles(FrameRec& F, int32_t requested)
     F.cunits = (int32_t)(((F.GR + cnb - 1) / cnb) * ((F.TX + F.ctx - 1) / F.ctx));
 }
 
+// Workgroup size of a frame's forward and reconstruction tiles.  A u8 tile
+// with few phase-1 items (strips x groups of subgrid rows, e.g. b = 16 or
+// narrow frames) keeps more tiles in flight per CU with 128 lanes; larger
+// tiles fill 256 (measured on 64 x 1080p and 300 x 768x576 batches).
+int tile_threads(const FrameRec& F)
+{
+    if (F.layout != DPPIX_U8_HWC)
+        return kDefaultThreads;
+    const int64_t nstr = ((int64_t)F.K * F.b * F.C + 15) / 16;
+    const int q = F.s == 2 ? 4 : ((F.s == 3 || F.s == 4) ? 2 : 1);
+    const int64_t ngq = (std::min(F.n, kRowGroup) + q - 1) / q;
+    return nstr * ngq <= 320 ? 128 : kDefaultThreads;
+}
+
 }  // namespace
 
 extern "C" {
@@ -298,8 +313,12 @@ dppix_status_t dp_pix_plan_create(const dppix_frame_desc_t* descs, int32_t n_fra
         const int64_t bpp = F.layout == DPPIX_F32_CHW ? 4 : 1;
         return (int64_t)F.b * F.K * F.b * F.C * bpp;
     };
-    // group-major (one kernel instantiation per layout and channel count)
-    auto group_key = [&](int32_t f) { return p->frames[f].layout * 8 + p->frames[f].C; };
+    // group-major (one kernel instantiation per layout and channel count, one
+    // launch per workgroup size)
+    auto group_key = [&](int32_t f) {
+        const FrameRec& F = p->frames[f];
+        return (F.layout * 8 + F.C) * 2 + (tile_threads(F) == kDefaultThreads ? 0 : 1);
+    };
     std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
         if (group_key(x) != group_key(y))
             return group_key(x) < group_key(y);
@@ -316,12 +335,19 @@ dppix_status_t dp_pix_plan_create(const dppix_frame_desc_t* descs, int32_t n_fra
     p->sched_base[n_frames] = acc;
     for (int32_t k = 0; k < n_frames; ++k) {
         const FrameRec& F = p->frames[order[k]];
-        if (p->groups.empty() || p->groups.back().layout != F.layout || p->groups.back().C != F.C)
-            p->groups.push_back(LaunchGroup{F.layout, F.C, p->sched_base[k], p->sched_base[k], 0, 0});
+        const int th = tile_threads(F);
+        if (p->groups.empty() || p->groups.back().layout != F.layout || p->groups.back().C != F.C ||
+            p->groups.back().threads != th)
+            p->groups.push_back(LaunchGroup{F.layout, F.C, th, p->sched_base[k], p->sched_base[k], 0, 0});
         LaunchGroup& g = p->groups.back();
         g.hi = p->sched_base[k + 1];
         g.lds_fwd = std::max(g.lds_fwd, frame_lds(kind_fwd(F), F));
         g.lds_rec = std::max(g.lds_rec, frame_lds(kind_rec(F), F));
+    }
+
+    if (p->groups.size() > (size_t)kMaxGroups) {   // 2 layouts x 4 channel counts x 2 sizes at most
+        delete p;
+        return fail(DPPIX_ENOTSUP, "too many launch groups");
     }
 
     // Workspace layout.
@@ -403,10 +429,8 @@ dppix_status_t dp_pix_plan_set_launch(dppix_plan_t p, int32_t threads, int32_t p
 {
     if (p == nullptr)
         return fail(DPPIX_EINVAL, "NULL plan");
-    if (threads == 0)
-        threads = kDefaultThreads;
-    if (threads < 64 || threads > kMaxThreads || threads % 64 != 0)
-        return fail(DPPIX_EINVAL, "threads must be a multiple of 64 in 64..512");
+    if (threads != 0 && (threads < 64 || threads > kMaxThreads || threads % 64 != 0))
+        return fail(DPPIX_EINVAL, "threads must be 0 (chosen per frame class) or a multiple of 64 in 64..512");
     if (persistent < 0 || persistent > 64)
         return fail(DPPIX_EINVAL, "persistent must be 0 (one workgroup per tile), 1 (resident grid) or 2..64 "
                                   "(workgroups per CU)");
@@ -479,7 +503,13 @@ dppix_status_t check_store(const dppix_store_t* s, bool need_stats)
     return DPPIX_OK;
 }
 
-int grid_for(dppix_plan_t p, int layout, int C, int64_t tiles, size_t lds)
+// Workgroup size of the kernels outside the launch groups.
+int plain_threads(dppix_plan_t p) { return p->threads ? p->threads : kDefaultThreads; }
+
+// Workgroup size of a launch group's forward and reconstruction tiles.
+int group_threads(dppix_plan_t p, const LaunchGroup& g) { return p->threads ? p->threads : g.threads; }
+
+int grid_for(dppix_plan_t p, int layout, int C, int threads, int64_t tiles, size_t lds)
 {
     if (!p->persistent)
         return (int)tiles;
@@ -493,7 +523,7 @@ int grid_for(dppix_plan_t p, int layout, int C, int64_t tiles, size_t lds)
     }
     const int cus = p->cus;
     int per_cu = p->persistent;
-    if (per_cu == 1 && (occupancy_forward(layout, C, p->threads, lds, &per_cu) != hipSuccess || per_cu < 1))
+    if (per_cu == 1 && (occupancy_forward(layout, C, threads, lds, &per_cu) != hipSuccess || per_cu < 1))
         per_cu = 1;
     const int64_t g = std::min<int64_t>((int64_t)cus * per_cu, tiles);
     return (int)std::max<int64_t>(1, g);
@@ -510,7 +540,7 @@ hipError_t for_groups(dppix_plan_t p, const TileArgs& base, bool rec, Launch lau
         a.n_tiles = g.hi - g.lo;
         a.ticket = base.ticket + 2 * gi;
         const size_t lds = rec ? g.lds_rec : g.lds_fwd;
-        hipError_t e = launch(a, g, lds, grid_for(p, g.layout, g.C, a.n_tiles, lds));
+        hipError_t e = launch(a, g, lds, grid_for(p, g.layout, g.C, group_threads(p, g), a.n_tiles, lds));
         if (e != hipSuccess)
             return e;
     }
@@ -530,7 +560,7 @@ dppix_status_t dp_pix_plan(dppix_plan_t p, const uint8_t* const* masks, const dp
     TileArgs a = base_args(p);
     a.masks = masks;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    hipError_t e = launch_plan(a, p->n_units, p->threads, p->lds[kPlan], store ? store->counts : nullptr, s);
+    hipError_t e = launch_plan(a, p->n_units, plain_threads(p), p->lds[kPlan], store ? store->counts : nullptr, s);
     if (e != hipSuccess)
         return dev_fail(e, "plan launch");
     return DPPIX_OK;
@@ -558,7 +588,7 @@ dppix_status_t dp_pix_forward(dppix_plan_t p, const void* const* images, const d
     a.clip_fg = clip_fg;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     hipError_t e = for_groups(p, a, false, [&](const TileArgs& ga, const LaunchGroup& g, size_t lds, int grid) {
-        return launch_forward(ga, g.layout, g.C, p->threads, lds, grid, s);
+        return launch_forward(ga, g.layout, g.C, group_threads(p, g), lds, grid, s);
     });
     if (e != hipSuccess)
         return dev_fail(e, "forward launch");
@@ -580,7 +610,7 @@ dppix_status_t dp_pix_reconstruct(dppix_plan_t p, const dppix_store_t* store, vo
     a.fg = store->fg;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     hipError_t e = for_groups(p, a, true, [&](const TileArgs& ga, const LaunchGroup& g, size_t lds, int grid) {
-        return launch_reconstruct(ga, g.layout, g.C, p->threads, lds, grid, s);
+        return launch_reconstruct(ga, g.layout, g.C, group_threads(p, g), lds, grid, s);
     });
     if (e != hipSuccess)
         return dev_fail(e, "reconstruct launch");
@@ -612,7 +642,8 @@ dppix_status_t dp_pix_backward(dppix_plan_t p, const dppix_store_t* store, const
     a.g_bg = reinterpret_cast<float*>(sc);
     a.g_fg = reinterpret_cast<float*>(sc + align256(4 * p->bg_cap));
     a.cell_index = reinterpret_cast<uint32_t*>(sc + align256(4 * p->bg_cap) + align256(4 * p->fg_cap));
-    hipError_t e = launch_backward(a, p->threads, p->lds[kBwd], grid_for(p, 1, 1, p->n_tiles, p->lds[kBwd]),
+    hipError_t e = launch_backward(a, plain_threads(p), p->lds[kBwd],
+                                   grid_for(p, 1, 1, plain_threads(p), p->n_tiles, p->lds[kBwd]),
                                    p->total_pixels,
                                    reinterpret_cast<hipStream_t>(stream));
     if (e != hipSuccess)
@@ -641,7 +672,7 @@ dppix_status_t dp_pix_debug_sums(dppix_plan_t p, const void* const* images, cons
     a.dbg_fine = fine;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     hipError_t e = for_groups(p, a, false, [&](const TileArgs& ga, const LaunchGroup& g, size_t lds, int grid) {
-        return launch_forward(ga, g.layout, g.C, p->threads, lds, grid, s);
+        return launch_forward(ga, g.layout, g.C, group_threads(p, g), lds, grid, s);
     });
     if (e != hipSuccess)
         return dev_fail(e, "forward launch");
@@ -669,7 +700,7 @@ dppix_status_t dp_pix_edge_mask(dppix_plan_t p, const void* const* images, int32
         TileArgs ga = a;
         ga.sched_offset = g.lo;
         ga.n_tiles = g.hi - g.lo;
-        hipError_t e = launch_edge_mask(ga, g.C, p->threads, s);
+        hipError_t e = launch_edge_mask(ga, g.C, plain_threads(p), s);
         if (e != hipSuccess)
             return dev_fail(e, "edge mask launch");
     }
@@ -697,7 +728,7 @@ dppix_status_t dp_pix_metrics(dppix_plan_t p, const void* const* images, const v
         TileArgs ga = a;
         ga.sched_offset = g.lo;
         ga.n_tiles = g.hi - g.lo;
-        hipError_t e = launch_metrics(ga, g.C, p->threads, s);
+        hipError_t e = launch_metrics(ga, g.C, plain_threads(p), s);
         if (e != hipSuccess)
             return dev_fail(e, "metrics launch");
     }

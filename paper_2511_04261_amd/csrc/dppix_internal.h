@@ -16,8 +16,9 @@ namespace dppix {
 constexpr int kStrip = 16;             // bytes one lane moves per row (dwordx4)
 constexpr int kMaxThreads = 512;
 constexpr int kMaxB = 256;             // 255 * 256 rows fits a 16-bit lane sum
-constexpr int kTicketWords = 16;       // two per launch group (at most 5 groups) ...
-constexpr int kScanWord = 15;          // ... and the scan's count of finished frames
+constexpr int kMaxGroups = 16;         // launch groups: layout x channels x workgroup size
+constexpr int kTicketWords = 2 * kMaxGroups + 1;  // two per launch group ...
+constexpr int kScanWord = 2 * kMaxGroups;         // ... and the scan's count of finished frames
 
 // One frame as the kernels see it (host computes everything derivable).
 struct FrameRec {
