@@ -175,6 +175,69 @@ def run_per_frame(frames_s, dev, warmup, steps):
     return dict(seconds=dt, step_ms=1e3 * dt / steps, pixels=px, bytes=b)
 
 
+def run_single_frame(dev, calls=200):
+    """One 256x256 grayscale frame, b = 16, m = 16, eps = 0.5, no mask: the
+    latency of one plan + forward (GPU time from HIP events over back-to-back
+    calls, and host wall time per call including the launch)."""
+    import torch
+    import paper_2511_04261_amd as dp
+    from paper_2511_04261_amd import synth
+    img = torch.from_numpy(synth.single_gray()[:, :, 0].copy()).to(dev)
+    out = torch.empty_like(img)
+    plan = dp.Plan([dp.FrameParams(256, 256, 1, dp.U8_HWC, b=16, sb=16, m=16, eps_bg=0.5, seed=0)], device=dev)
+    stream = torch.cuda.current_stream()
+    pc, fc = plan.bound_calls(None, [img], [out], stream)
+
+    def call():
+        pc()
+        fc()
+
+    gpu_ms = time_launches(call, calls, stream)
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        call()
+        torch.cuda.synchronize()
+    wall_ms = 1e3 * (time.perf_counter() - t0) / calls
+    plan.close()
+    return dict(us_per_frame_gpu=round(1e3 * gpu_ms, 2), us_per_call_synchronous=round(1e3 * wall_ms, 2),
+                frame="256x256x1", b=16, m=16, eps=0.5)
+
+
+def run_autograd_batch(dev, reps=20):
+    """32 x 3 x 512 x 512 fp32 frames with rectangle masks, b_fg = 8,
+    b_bg = 16, m = 8, eps_fg = 0.5, eps_bg = 1.0: forward (with the clip
+    flags the adjoint needs) and adjoint, algorithmic GB/s of each."""
+    import torch
+    import paper_2511_04261_amd as dp
+    from paper_2511_04261_amd import synth
+    x, masks, w = synth.autograd_batch()
+    B, C, H, W = x.shape
+    tx = torch.from_numpy(x).to(dev)
+    tm = [torch.from_numpy(m).to(dev) for m in masks]
+    gy = torch.from_numpy(w).to(dev)
+    y = torch.empty_like(tx)
+    gx = torch.empty_like(tx)
+    frames = [dp.FrameParams(H, W, C, dp.F32_CHW, b=16, sb=8, m=8, eps_bg=1.0, eps_fg=0.5, tau=1, seed=4,
+                             frame_index=i) for i in range(B)]
+    plan = dp.Plan(frames, device=dev)
+    clip = plan.clip_buffers()
+    scratch = torch.empty(max(plan.sizes.grad_scratch_bytes, 256), dtype=torch.uint8, device=dev)
+    xs, ys = [tx[i] for i in range(B)], [y[i] for i in range(B)]
+    gys, gxs = [gy[i] for i in range(B)], [gx[i] for i in range(B)]
+    stream = torch.cuda.current_stream()
+    plan_call, fwd_call = plan.bound_calls(tm, xs, ys, stream, clip=clip)
+    bwd_call = plan.bound_backward(gys, gxs, clip, scratch, stream)
+    plan_call()
+    fwd_ms = time_launches(fwd_call, reps, stream)
+    bwd_ms = time_launches(bwd_call, reps, stream)
+    nbytes = 4 * tx.numel()
+    st = store_bytes(plan)
+    plan.close()
+    return dict(shape="32x3x512x512 fp32", forward_ms=round(fwd_ms, 4), backward_ms=round(bwd_ms, 4),
+                forward_gbs=round((2 * nbytes + st) / (fwd_ms * 1e-3) / 1e9, 1),
+                backward_gbs=round((2 * nbytes + st) / (bwd_ms * 1e-3) / 1e9, 1))
+
+
 SERVE_PARAMS = dict(b=32, sb=8, m=16, eps_bg=1.0, eps_fg=0.3, tau=1)
 
 
@@ -406,6 +469,12 @@ def main():
                                "step_frac_hbm": round(u_gbs / HBM_PEAK_GBS, 4),
                                "forward_frac_hbm": round(uf_gbs / HBM_PEAK_GBS, 4)}
         del ur, ub
+        torch.cuda.empty_cache()
+    if not args.skip_extra:
+        log("bench: single 256x256 frame latency")
+        out["single_frame"] = run_single_frame(dev)
+        log("bench: fp32 autograd batch (forward + adjoint)")
+        out["autograd_batch"] = run_autograd_batch(dev)
         torch.cuda.empty_cache()
     if args.serve_seconds > 0 and not args.skip_extra:
         log("bench: serving %.0f s of 16 camera streams" % args.serve_seconds)

@@ -253,7 +253,7 @@ class Plan:
         return (torch.empty(max(self.sizes.clip_bytes_bg, 1), dtype=torch.uint8, device=self.device),
                 torch.empty(max(self.sizes.clip_bytes_fg, 1), dtype=torch.uint8, device=self.device))
 
-    def bound_calls(self, masks, images, out=None, stream=None):
+    def bound_calls(self, masks, images, out=None, stream=None, clip=None):
         """Validate once and return zero-argument callables ``(plan, forward)``
         that issue dp_pix_plan / dp_pix_forward on ``stream`` with the
         arguments already marshalled (for back-to-back launches)."""
@@ -267,16 +267,36 @@ class Plan:
         mp = None if mt is None else ctypes.c_void_p(mt.data_ptr())
         ip = ctypes.c_void_p(it.data_ptr())
         op = None if ot is None else ctypes.c_void_p(ot.data_ptr())
-        keep = (mt, it, ot)
+        cb = None if clip is None else ctypes.c_void_p(clip[0].data_ptr())
+        cf = None if clip is None else ctypes.c_void_p(clip[1].data_ptr())
+        keep = (mt, it, ot, clip)
 
         def plan_call():
             _lib.check(lib.dp_pix_plan(h, mp, st, s))
 
         def forward_call():
-            _lib.check(lib.dp_pix_forward(h, ip, st, None, None, op, s))
+            _lib.check(lib.dp_pix_forward(h, ip, st, cb, cf, op, s))
 
         plan_call.keep = forward_call.keep = keep
         return plan_call, forward_call
+
+    def bound_backward(self, grad_out, grad_in, clip, scratch, stream=None):
+        """Validate once and return a zero-argument callable issuing
+        dp_pix_backward with the arguments already marshalled."""
+        self._check_images(grad_out, "grad_out")
+        self._check_images(grad_in, "grad_in")
+        gt = self.pointer_table(grad_out)
+        it = self.pointer_table(grad_in)
+        lib, h, st, s = self.lib, self.handle, ctypes.byref(self.store), _stream_handle(stream)
+        args = (ctypes.c_void_p(gt.data_ptr()), ctypes.c_void_p(clip[0].data_ptr()),
+                ctypes.c_void_p(clip[1].data_ptr()), ctypes.c_void_p(it.data_ptr()),
+                ctypes.c_void_p(scratch.data_ptr()), scratch.numel())
+
+        def backward_call():
+            _lib.check(lib.dp_pix_backward(h, st, args[0], args[1], args[2], args[3], args[4], args[5], s))
+
+        backward_call.keep = (gt, it, clip, scratch)
+        return backward_call
 
     def graph(self, masks, images, out=None, stream=None) -> "Graph":
         """Capture plan + forward (+ fused reconstruction) into a HIP graph."""
