@@ -97,8 +97,8 @@ hipError_t launch_plan(const TileArgs& a, int64_t n_units, int threads, size_t l
 hipError_t launch_forward(const TileArgs& a, int layout, int C, int threads, size_t lds, int grid, hipStream_t s);
 hipError_t launch_reconstruct(const TileArgs& a, int layout, int C, int threads, size_t lds, int grid,
                               hipStream_t s);
-hipError_t launch_backward(const TileArgs& a, int threads, size_t lds, int grid, int64_t total_pixels,
-                           hipStream_t s);
+hipError_t launch_backward_reduce(const TileArgs& a, int threads, size_t lds, int grid, hipStream_t s);
+hipError_t launch_backward_mirror(const TileArgs& a, int threads, int grid, hipStream_t s);
 hipError_t launch_philox(const uint32_t* in, uint32_t* out, int64_t n, hipStream_t s);
 hipError_t launch_edge_mask(const TileArgs& a, int C, int threads, hipStream_t s);
 hipError_t launch_metrics(const TileArgs& a, int C, int threads, hipStream_t s);

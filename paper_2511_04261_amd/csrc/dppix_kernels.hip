@@ -1342,53 +1342,69 @@ __device__ __forceinline__ float g_at(const TileArgs& a, const FrameRec& F, int 
     return a.g_fg[a.frame_base[2 * f + 1] + ((uint64_t)idx * n * n + i * n + j) * F.C + ch];
 }
 
-// One workgroup per (tile): every real pixel of the tile's cells collects its
-// own statistic's gradient plus those of the padded positions mirroring onto it.
-__device__ void backward_spread_tile(const TileArgs& a, const FrameRec& F, const TileCoord& tc)
+// Mirror terms of the adjoint: a real pixel near the bottom or right border is
+// also the source of the padded positions that fold onto it, and collects
+// their statistics' gradients too.  Its own statistic's gradient is already in
+// grad_in (the gradient statistics broadcast like a reconstruction), so only
+// the pixels that have mirror preimages are visited, and only the mirror
+// terms are added.  Nothing to do in the unpadded mode.
+__device__ void backward_mirror_tile(const TileArgs& a, const FrameRec& F, const TileCoord& tc)
 {
     const int tid = threadIdx.x, NT = blockDim.x;
     const int b = F.b, H = F.H, W = F.W, C = F.C, pad = F.pad;
+    if (pad == kPadNone)
+        return;
     const int x0c = tc.ct * F.K;
     const int Kt = min(F.K, F.GC - x0c);
     const int y0 = tc.r * b, y1 = min(y0 + b, H);
     const int xa = x0c * b, xb = min((x0c + Kt) * b, W);
     if (y0 >= H || xa >= W)
         return;
-    // padded rows / columns past the frame (none count in the unpadded mode)
-    const int PR = pad == kPadNone ? 0 : F.GR * b - H, PC = pad == kPadNone ? 0 : F.GC * b - W;
+    const int PR = F.GR * b - H, PC = F.GC * b - W;
     // rows at or above lo_r (columns at or above lo_c) may have mirror preimages
     const int lo_r = (PR > 0) ? ((PR <= H - 1) ? H - 1 - PR : 0) : H;
     const int lo_c = (PC > 0) ? ((PC <= W - 1) ? W - 1 - PC : 0) : W;
+    if (y1 <= lo_r && xb <= lo_c)
+        return;
+    // region A: rows [ra, y1) x columns [xa, xb); region B: rows [y0, rb) x columns [ca, xb)
+    const int ra = max(y0, lo_r), rb = min(y1, lo_r), ca = max(xa, lo_c);
+    const int wA = xb - xa, wB = xb - ca;
+    const int64_t nA = ra < y1 ? (int64_t)(y1 - ra) * wA : 0;
+    const int64_t nB = (rb > y0 && wB > 0) ? (int64_t)(rb - y0) * wB : 0;
     const int64_t pitch = F.pitch, plane = pitch * H;
     float* gi = a.grad_in[tc.f];
-    const int wcols = xb - xa;
-    const int64_t npx = (int64_t)(y1 - y0) * wcols;
     for (int ch = 0; ch < C; ++ch) {
-        for (int64_t q = tid; q < npx; q += NT) {
-            const int y = y0 + (int)(q / wcols), x = xa + (int)(q % wcols);
-            float acc = g_at(a, F, tc.f, y, x, ch);
-            if (y >= lo_r || x >= lo_c) {
-                // mirror rows / columns (padded coordinates >= H, >= W) folding onto y / x
-                for (int yy = (y >= lo_r ? H : F.GR * b); yy < F.GR * b; ++yy)
-                    if (fold(yy, H, pad) == y) {
-                        acc += g_at(a, F, tc.f, yy, x, ch);
-                        for (int xx = (x >= lo_c ? W : F.GC * b); xx < F.GC * b; ++xx)
-                            if (fold(xx, W, pad) == x)
-                                acc += g_at(a, F, tc.f, yy, xx, ch);
-                    }
-                for (int xx = (x >= lo_c ? W : F.GC * b); xx < F.GC * b; ++xx)
-                    if (fold(xx, W, pad) == x)
-                        acc += g_at(a, F, tc.f, y, xx, ch);
+        for (int64_t q = tid; q < nA + nB; q += NT) {
+            int y, x;
+            if (q < nA) {
+                y = ra + (int)(q / wA);
+                x = xa + (int)(q % wA);
+            } else {
+                y = y0 + (int)((q - nA) / wB);
+                x = ca + (int)((q - nA) % wB);
             }
-            gi[plane * ch + (int64_t)y * pitch + x] = acc;
+            float acc = 0.f;
+            // padded rows folding onto y, each also with the padded columns folding onto x
+            for (int yy = (y >= lo_r ? H : F.GR * b); yy < F.GR * b; ++yy)
+                if (fold(yy, H, pad) == y) {
+                    acc += g_at(a, F, tc.f, yy, x, ch);
+                    for (int xx = (x >= lo_c ? W : F.GC * b); xx < F.GC * b; ++xx)
+                        if (fold(xx, W, pad) == x)
+                            acc += g_at(a, F, tc.f, yy, xx, ch);
+                }
+            for (int xx = (x >= lo_c ? W : F.GC * b); xx < F.GC * b; ++xx)
+                if (fold(xx, W, pad) == x)
+                    acc += g_at(a, F, tc.f, y, xx, ch);
+            if (acc != 0.f)
+                gi[plane * ch + (int64_t)y * pitch + x] += acc;
         }
     }
 }
 
-__global__ __launch_bounds__(kMaxThreads) void k_backward_spread(TileArgs a)
+__global__ __launch_bounds__(kMaxThreads) void k_backward_mirror(TileArgs a)
 {
     extern __shared__ __align__(16) uint8_t lds[];
-    run_tiles(a, lds, [&](const FrameRec& F, const TileCoord& tc) { backward_spread_tile(a, F, tc); });
+    run_tiles(a, lds, [&](const FrameRec& F, const TileCoord& tc) { backward_mirror_tile(a, F, tc); });
 }
 
 // ==========================================================================
@@ -1690,20 +1706,14 @@ hipError_t launch_reconstruct(const TileArgs& a, int layout, int C, int threads,
     }
 }
 
-hipError_t launch_backward(const TileArgs& a, int threads, size_t lds, int grid, int64_t, hipStream_t s)
+hipError_t launch_backward_reduce(const TileArgs& a, int threads, size_t lds, int grid, hipStream_t s)
 {
-    if (a.n_tiles == 0)
-        return hipSuccess;
-    const unsigned g = a.persistent ? (unsigned)grid : (unsigned)a.n_tiles;
-    hipError_t e = allow_lds(k_backward_reduce, lds);
-    if (e != hipSuccess)
-        return e;
-    hipLaunchKernelGGL(k_backward_reduce, dim3(g), dim3(threads), lds, s, a);
-    e = hipGetLastError();
-    if (e != hipSuccess)
-        return e;
-    hipLaunchKernelGGL(k_backward_spread, dim3(g), dim3(threads), 0, s, a);
-    return hipGetLastError();
+    return launch_tiles(k_backward_reduce, a, threads, lds, grid, s);
+}
+
+hipError_t launch_backward_mirror(const TileArgs& a, int threads, int grid, hipStream_t s)
+{
+    return launch_tiles(k_backward_mirror, a, threads, 0, grid, s);
 }
 
 hipError_t launch_edge_mask(const TileArgs& a, int C, int threads, hipStream_t s)
