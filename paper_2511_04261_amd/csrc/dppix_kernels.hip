@@ -913,41 +913,65 @@ __device__ void forward_tile_f32(const TileArgs& a, const FrameRec& F, const Til
     const int kn = Kt * n;
     lds_barrier();
 
-    for (int ch = 0; ch < C; ++ch) {
-        const float* pl = img + plane * ch;
-        for (int fr = 0; fr < n; ++fr) {
-            const int row0 = r * b + fr * s;
-            for (int st = tid; st < nstr; st += NT) {
-                const int64_t p0 = X0 + 4 * st;
-                v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
-                // rows past the frame are absent in the unpadded mode
-                const int srows = pad == kPadNone ? max(0, min(s, H - row0)) : s;
-                const int64_t cend = pad == kPadNone ? lim : tile_end;
-                if (in_aligned && p0 + 4 <= lim) {
-                    for (int k = 0; k < srows; ++k) {
-                        acc += ld16f_nt(pl + (int64_t)fold(row0 + k, H, pad) * pitch + p0);
-                    }
-                } else {
-                    for (int k = 0; k < srows; ++k) {
-                        const float* rk = pl + (int64_t)fold(row0 + k, H, pad) * pitch;
-                        float v[4];
+    // Subgrid rows in groups of kRowGroupF: one item per (channel, subgrid
+    // row, 4-float strip), consecutive lanes on consecutive strips of a row,
+    // rows added in order (fp32) with up to four loads in flight; then one
+    // lane per (channel, subcell column) adds the s_b column sums (fp64) per
+    // subgrid row and releases the complex subcells.
+    const int kn4 = 4 * nstr;                 // floats of one row buffer
+    for (int fr0 = 0; fr0 < n; fr0 += kRowGroupF) {
+        const int ng = min(kRowGroupF, n - fr0);
+        for (int it = tid; it < C * ng * nstr; it += NT) {
+            const int st = it % nstr;
+            const int rest = it / nstr;
+            const int g = rest % ng, ch = rest / ng;
+            const float* pl = img + plane * ch;
+            const int row0 = r * b + (fr0 + g) * s;
+            const int64_t p0 = X0 + 4 * st;
+            // rows past the frame are absent in the unpadded mode
+            const int srows = pad == kPadNone ? max(0, min(s, H - row0)) : s;
+            const int64_t cend = pad == kPadNone ? lim : tile_end;
+            v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
+            if (in_aligned && p0 + 4 <= lim) {
+                int k = 0;
+                for (; k + 4 <= srows; k += 4) {
+                    v4f w[4];
 #pragma unroll
-                        for (int q = 0; q < 4; ++q)
-                            v[q] = (p0 + q < cend) ? rk[fold((int)(p0 + q), W, pad)] : 0.f;
-                        acc.x += v[0]; acc.y += v[1]; acc.z += v[2]; acc.w += v[3];
-                    }
+                    for (int i = 0; i < 4; ++i)
+                        w[i] = ld16f_nt(pl + (int64_t)fold(row0 + k + i, H, pad) * pitch + p0);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        acc += w[i];
                 }
-                reinterpret_cast<v4f*>(colsum)[st] = acc;
+                for (; k < srows; ++k)
+                    acc += ld16f_nt(pl + (int64_t)fold(row0 + k, H, pad) * pitch + p0);
+            } else {
+                for (int k = 0; k < srows; ++k) {
+                    const float* rk = pl + (int64_t)fold(row0 + k, H, pad) * pitch;
+                    float v[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        v[q] = (p0 + q < cend) ? rk[fold((int)(p0 + q), W, pad)] : 0.f;
+                    acc.x += v[0]; acc.y += v[1]; acc.z += v[2]; acc.w += v[3];
+                }
             }
-            lds_barrier();
-            for (int fc = tid; fc < kn; fc += NT) {
+            reinterpret_cast<v4f*>(colsum)[(ch * ng + g) * nstr + st] = acc;
+        }
+        lds_barrier();
+        for (int j = tid; j < C * kn; j += NT) {
+            const int ch = j / kn, fc = j - ch * kn;
+            const int kc = fc / n, jj = fc - kc * n;
+            const int ci = fc * C + ch;
+            double part = fr0 == 0 ? 0.0 : cspart[ci];
+            for (int g = 0; g < ng; ++g) {
+                const float* cs = colsum + (ch * ng + g) * kn4 + fc * s;
                 double S = 0.0;
                 for (int x = 0; x < s; ++x)
-                    S += (double)colsum[fc * s + x];
-                const int kc = fc / n, jj = fc - kc * n;
-                const int ci = fc * C + ch;
-                cspart[ci] = (fr == 0 ? 0.0 : cspart[ci]) + S;
+                    S += (double)cs[x];
+                part += S;
                 if (cflag[kc]) {
+                    const int fr = fr0 + g;
+                    const int row0 = r * b + fr * s;
                     const uint32_t id = (uint32_t)(r * n + fr) * (uint32_t)(F.GC * n) + (uint32_t)(x0c * n + fc);
                     uint8_t pass;
                     const float v = release(S, stat_area(F, row0, x0c * b + fc * s, s), F.noise_fg, F.sigma_fg, F, id,
@@ -959,8 +983,9 @@ __device__ void forward_tile_f32(const TileArgs& a, const FrameRec& F, const Til
                     vgc[(fr * kn + fc) * C + ch] = v;
                 }
             }
-            lds_barrier();
+            cspart[ci] = part;
         }
+        lds_barrier();
     }
     for (int j = tid; j < Kt * C; j += NT) {
         const int kc = j / C, ch = j - kc * C;

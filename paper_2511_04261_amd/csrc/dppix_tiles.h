@@ -8,6 +8,7 @@
 namespace dppix {
 
 constexpr int kRowGroup = 8;   // subgrid rows summed per pass of the u8 forward
+constexpr int kRowGroupF = 4;  // subgrid rows summed per pass of the fp32 forward (all channels)
 
 enum TileKind : int {
     kPlan = 0,       // plan unit: mask counts per cell, complex cells per tile
@@ -46,11 +47,18 @@ __host__ __device__ inline LdsPlan lds_plan(int kind, int K, int b, int n, int C
     uint32_t o = 0;
     p.colsum = o;
     // u8 forward: 16-bit column sums of up to kRowGroup subgrid rows (reused
-    // as two expanded output rows); f32 forward and reconstruction: two
-    // expanded output rows; adjoint: one row of float column sums
+    // as two expanded output rows); f32 forward: float column sums of every
+    // channel for up to kRowGroupF subgrid rows (reused likewise); f32
+    // reconstruction: two expanded output rows; adjoint: one row of float
+    // column sums
     if (kind == kFwdU8)
         o += al16(32u * nstr * (uint32_t)(n < kRowGroup ? n : kRowGroup));
-    else if (kind == kBwd)
+    else if (kind == kFwdF32) {
+        // float4 column sums per (channel, subgrid row of a group), at least
+        // the two expanded output rows of the reconstruction
+        const uint32_t rows = (uint32_t)C * (uint32_t)(n < kRowGroupF ? n : kRowGroupF);
+        o += al16(16u * nstr * (rows > 2u ? rows : 2u));
+    } else if (kind == kBwd)
         o += al16(16u * nstr);
     else
         o += al16(32u * nstr);

@@ -182,3 +182,49 @@ def test_package_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(_lib, "_lib", None)
     with pytest.raises(RuntimeError, match="not built"):
         _lib.load(str(tmp_path / "missing.so"))
+
+
+def test_unpadded_mode_geometry():
+    """Algorithm 1 border mode: same grid, no padding, tau 0 = per-cell majority."""
+    st, h, L = create([dp.FrameParams(45, 70, 3, b=16, sb=4, pad_mode=dp.PAD_NONE)])
+    assert st == 0
+    fi = info(h, L)
+    assert (fi.grid_rows, fi.grid_cols) == (3, 5)
+    assert fi.fg_min_count == 0
+    L.dp_pix_plan_destroy(h)
+    st, h, L = create([dp.FrameParams(45, 70, 3, b=16, sb=4, pad_mode=dp.PAD_NONE, tau=3)])
+    assert st == 0 and info(h, L).fg_min_count == 3
+    L.dp_pix_plan_destroy(h)
+
+
+def test_plans_for_extreme_and_mixed_batches():
+    """Host layout of batches that stress the tile and plan-unit arithmetic:
+    very wide and very tall frames, b = 1 and b = 256, every (layout,
+    channels) pair in one batch (the most launch groups), explicit tile
+    widths from 1 to far past the grid.  Plan creation succeeds, the
+    workspace covers the tables, and the frames' cells are laid out back to
+    back."""
+    frames = [dp.FrameParams(3, 1 << 20, 1, b=1, sb=1), dp.FrameParams(1 << 16, 7, 4, b=256, sb=16),
+              dp.FrameParams(600, 900, 2, b=3, sb=1, tile_cells=1), dp.FrameParams(17, 4001, 3, b=12, sb=4,
+                                                                                  tile_cells=100000)]
+    for C in (1, 2, 3, 4):
+        frames.append(dp.FrameParams(40, 50, C, dp.U8_HWC, b=8, sb=4))
+        frames.append(dp.FrameParams(40, 50, C, dp.F32_CHW, b=8, sb=4))
+        frames.append(dp.FrameParams(300, 520, C, dp.U8_HWC, b=16, sb=4))   # small tiles: 128-lane group
+    st, h, L = create(frames)
+    assert st == 0, L.dp_pix_last_error()
+    sz = _lib.Sizes()
+    assert L.dp_pix_plan_sizes(h, ctypes.byref(sz)) == 0
+    cells = 0
+    tiles = 0
+    for f, fp in enumerate(frames):
+        fi = info(h, L, f)
+        assert fi.cell_offset == cells
+        cells += fi.grid_rows * fi.grid_cols
+        assert 1 <= fi.tile_cells <= fi.grid_cols
+        assert fi.tiles_per_band == -(-fi.grid_cols // fi.tile_cells)
+        tiles += fi.grid_rows * fi.tiles_per_band
+    assert sz.flag_bytes == cells and sz.n_tiles == tiles
+    # the workspace holds at least the frame records, two scheduling maps and per-tile counters
+    assert sz.workspace_bytes >= 144 * len(frames) + 8 * tiles + cells + 8 * tiles
+    L.dp_pix_plan_destroy(h)
