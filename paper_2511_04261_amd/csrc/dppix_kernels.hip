@@ -1298,45 +1298,68 @@ __device__ void backward_reduce_tile(const TileArgs& a, const FrameRec& F, const
     const uint64_t fg_base = a.frame_base[2 * tc.f + 1];
     const int nn = n * n, kn = Kt * n;
     lds_barrier();
-    for (int ch = 0; ch < C; ++ch) {
-        const float* pl = go + plane * ch;
-        for (int fr = 0; fr < n; ++fr) {
-            const int row0 = r * b + fr * s;
+    // as in the fp32 forward: (channel, subgrid row, strip) items over groups
+    // of kRowGroupF subgrid rows, real rows only, in order, then one lane per
+    // (channel, subcell column)
+    const int kn4 = 4 * nstr;
+    for (int fr0 = 0; fr0 < n; fr0 += kRowGroupF) {
+        const int ng = min(kRowGroupF, n - fr0);
+        for (int it = tid; it < C * ng * nstr; it += NT) {
+            const int st = it % nstr;
+            const int rest = it / nstr;
+            const int g = rest % ng, ch = rest / ng;
+            const float* pl = go + plane * ch;
+            const int row0 = r * b + (fr0 + g) * s;
             const int rows = max(0, min(s, H - row0));   // real rows only
-            for (int st = tid; st < nstr; st += NT) {
-                const int64_t p0 = X0 + 4 * st;
-                v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
-                if (aligned && p0 + 4 <= lim) {
-                    for (int k = 0; k < rows; ++k) {
-                        acc += *reinterpret_cast<const v4f*>(pl + (int64_t)(row0 + k) * pitch + p0);
-                    }
-                } else {
-                    for (int k = 0; k < rows; ++k) {
-                        const float* rk = pl + (int64_t)(row0 + k) * pitch;
-                        acc.x += (p0 + 0 < lim) ? rk[p0 + 0] : 0.f;
-                        acc.y += (p0 + 1 < lim) ? rk[p0 + 1] : 0.f;
-                        acc.z += (p0 + 2 < lim) ? rk[p0 + 2] : 0.f;
-                        acc.w += (p0 + 3 < lim) ? rk[p0 + 3] : 0.f;
-                    }
+            const int64_t p0 = X0 + 4 * st;
+            v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
+            if (aligned && p0 + 4 <= lim) {
+                const float* col = pl + (int64_t)row0 * pitch + p0;
+                int k = 0;
+                for (; k + 4 <= rows; k += 4) {
+                    v4f w[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        w[i] = ld16f_nt(col + (int64_t)(k + i) * pitch);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        acc += w[i];
                 }
-                reinterpret_cast<v4f*>(colsum)[st] = acc;
+                for (; k < rows; ++k)
+                    acc += ld16f_nt(col + (int64_t)k * pitch);
+            } else {
+                for (int k = 0; k < rows; ++k) {
+                    const float* rk = pl + (int64_t)(row0 + k) * pitch;
+                    acc.x += (p0 + 0 < lim) ? rk[p0 + 0] : 0.f;
+                    acc.y += (p0 + 1 < lim) ? rk[p0 + 1] : 0.f;
+                    acc.z += (p0 + 2 < lim) ? rk[p0 + 2] : 0.f;
+                    acc.w += (p0 + 3 < lim) ? rk[p0 + 3] : 0.f;
+                }
             }
-            lds_barrier();
-            for (int fc = tid; fc < kn; fc += NT) {
+            reinterpret_cast<v4f*>(colsum)[(ch * ng + g) * nstr + st] = acc;
+        }
+        lds_barrier();
+        for (int j = tid; j < C * kn; j += NT) {
+            const int ch = j / kn, fc = j - ch * kn;
+            const int kc = fc / n, jj = fc - kc * n;
+            const int ci = fc * C + ch;
+            double part = fr0 == 0 ? 0.0 : cspart[ci];
+            for (int g = 0; g < ng; ++g) {
+                const float* cs = colsum + (ch * ng + g) * kn4 + fc * s;
                 double G = 0.0;
                 for (int x = 0; x < s; ++x)
-                    G += (double)colsum[fc * s + x];
-                const int kc = fc / n, jj = fc - kc * n;
-                const int ci = fc * C + ch;
-                cspart[ci] = (fr == 0 ? 0.0 : cspart[ci]) + G;
+                    G += (double)cs[x];
+                part += G;
                 if (cflag[kc]) {
+                    const int fr = fr0 + g;
                     const uint64_t at = fg_base + ((uint64_t)cidx[kc] * nn + fr * n + jj) * C + ch;
-                    const double area = stat_area(F, row0, x0c * b + fc * s, s);
+                    const double area = stat_area(F, r * b + fr * s, x0c * b + fc * s, s);
                     a.g_fg[at] = (a.clip_fg[at] && area > 0.0) ? (float)(G / area) : 0.f;
                 }
             }
-            lds_barrier();
+            cspart[ci] = part;
         }
+        lds_barrier();
     }
     for (int j = tid; j < Kt * C; j += NT) {
         const int kc = j / C, ch = j - kc * C;

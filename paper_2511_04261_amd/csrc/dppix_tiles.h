@@ -49,8 +49,8 @@ __host__ __device__ inline LdsPlan lds_plan(int kind, int K, int b, int n, int C
     // u8 forward: 16-bit column sums of up to kRowGroup subgrid rows (reused
     // as two expanded output rows); f32 forward: float column sums of every
     // channel for up to kRowGroupF subgrid rows (reused likewise); f32
-    // reconstruction: two expanded output rows; adjoint: one row of float
-    // column sums
+    // reconstruction: two expanded output rows; adjoint: float column sums
+    // like the f32 forward
     if (kind == kFwdU8)
         o += al16(32u * nstr * (uint32_t)(n < kRowGroup ? n : kRowGroup));
     else if (kind == kFwdF32) {
@@ -58,8 +58,11 @@ __host__ __device__ inline LdsPlan lds_plan(int kind, int K, int b, int n, int C
         // the two expanded output rows of the reconstruction
         const uint32_t rows = (uint32_t)C * (uint32_t)(n < kRowGroupF ? n : kRowGroupF);
         o += al16(16u * nstr * (rows > 2u ? rows : 2u));
-    } else if (kind == kBwd)
-        o += al16(16u * nstr);
+    } else if (kind == kBwd) {
+        // float4 column sums per (channel, subgrid row of a group)
+        const uint32_t rows = (uint32_t)C * (uint32_t)(n < kRowGroupF ? n : kRowGroupF);
+        o += al16(16u * nstr * rows);
+    }
     else
         o += al16(32u * nstr);
     p.cspart = o;
