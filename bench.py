@@ -35,11 +35,21 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
+def _code_only(text: str) -> str:
+    """C/C++ source without comments and blank lines (the code the compiler sees)."""
+    import re
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(ln.rstrip() for ln in text.splitlines() if ln.strip())
+
+
+def kernel_source_hash(root: str = ROOT) -> str:
+    """Hash of the device code (kernels and the headers they include), so that
+    a counter summary is only trusted for the kernels it was taken from."""
     h = hashlib.sha256()
     for name in ("dppix_kernels.hip", "dppix_internal.h", "dppix_tiles.h"):
-        with open(os.path.join(ROOT, "paper_2511_04261_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(root, "paper_2511_04261_amd", "csrc", name), encoding="utf-8") as f:
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 

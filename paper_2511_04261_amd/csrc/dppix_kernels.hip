@@ -4,20 +4,25 @@
 // the mask) once and writes the reconstruction once; the statistics are a few
 // percent of that.  Nothing is a dense contraction, so there is no MFMA work.
 // Every tile kernel follows one pattern:
-//   1. each lane owns a 16-byte strip of the tile's padded rows and sums it
-//      down the rows of one subgrid row in registers (two 16-bit lanes per
-//      32-bit register for bytes: 255 * 256 rows still fits);
-//   2. the column sums go to LDS, where one lane per (subcell, channel) adds
-//      its s_b columns — exact integer sums of every s_b x s_b subcell;
+//   1. a work item is one 16-byte strip of the tile's padded rows over one
+//      (or a few) subgrid rows; it issues all of its row loads, then sums
+//      them in registers (two 16-bit lanes per 32-bit register for bytes:
+//      255 * 256 rows still fits);
+//   2. the column sums go to LDS, where one lane per (subcell column,
+//      channel) adds its s_b columns — exact integer sums of every s_b x s_b
+//      subcell;
 //   3. a coarse cell's sum is the exact total of its n x n subcell sums
 //      (Eq. 16-17: b = n * s_b), so simple and complex cells cost the same;
-//   4. one lane per released statistic draws Philox4x32-10 words, turns them
-//      into Laplace noise in fp64, clips and rounds once to fp32;
+//   4. each released statistic draws one Philox4x32-10 block, turns it into
+//      Laplace noise in fp64, clips and rounds once to fp32 (the releases
+//      of complex subcells are dealt evenly over the lanes);
 //   5. with a fused output, the rounded values are expanded into one padded
-//      row in LDS and each lane stores its strip on the s_b output rows.
+//      row in LDS and the strips are stored on the s_b output rows.
 // Mirror padding (Algorithm 2 step 4, Algorithm 3 step 3) is never
 // materialised: padded rows fold to a source row per row, and padded columns
-// fold per byte in the few strips that cross the right edge.
+// fold per byte in the few strips that cross the right edge (which become
+// one-row items so their byte loads overlap).  The unpadded mode (Algorithm
+// 1) skips those rows and columns and divides by real pixel counts.
 #include "dppix_internal.h"
 #include "dppix_tiles.h"
 
