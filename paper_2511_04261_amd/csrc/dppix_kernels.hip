@@ -451,12 +451,32 @@ __device__ void plan_count(const TileArgs& a, const FrameRec& F, const uint8_t* 
                 for (int i = 0; i < kPlanBatch; ++i)
                     acc_bytes(nz_strip(w[i]), e, o);
             }
-            for (; k < k1; ++k)
-                acc_bytes(nz_strip(ld16_nt(col + (int64_t)k * W)), e, o);
+            if (k < k1) {
+                // the last partial batch (b not a multiple of the batch)
+                v4u w[kPlanBatch];
+#pragma unroll
+                for (int i = 0; i < kPlanBatch; ++i)
+                    w[i] = k + i < k1 ? ld16_nt(col + (int64_t)(k + i) * W) : v4u{0u, 0u, 0u, 0u};
+#pragma unroll
+                for (int i = 0; i < kPlanBatch; ++i)
+                    acc_bytes(nz_strip(w[i]), e, o);
+            }
         } else {
-            for (int k = k0; k < k1; ++k)
-                if (row0 + k < H || pad != kPadNone)
-                    acc_bytes(nz_strip(ld16_nt(mask + (int64_t)fold(row0 + k, H, pad) * W + p0)), e, o);
+            // bottom border: mirrored rows (absent without padding), still
+            // issued a batch at a time so that their latencies overlap
+            for (int k = k0; k < k1; k += kPlanBatch) {
+                v4u w[kPlanBatch];
+#pragma unroll
+                for (int i = 0; i < kPlanBatch; ++i) {
+                    const int r = row0 + k + i;
+                    w[i] = (k + i < k1 && (r < H || pad != kPadNone))
+                               ? ld16_nt(mask + (int64_t)fold(r, H, pad) * W + p0)
+                               : v4u{0u, 0u, 0u, 0u};
+                }
+#pragma unroll
+                for (int i = 0; i < kPlanBatch; ++i)
+                    acc_bytes(nz_strip(w[i]), e, o);
+            }
         }
         spread_strip(e, o, cellcnt + j * KCs, KC, b, 16 * st);
     }
