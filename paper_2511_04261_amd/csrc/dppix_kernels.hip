@@ -79,9 +79,10 @@ __device__ __forceinline__ double laplace_sample(const FrameRec& F, uint32_t id,
     const uint4 w = philox10(make_uint4(id, (uint32_t)ch | ((uint32_t)level << 8), F.fi0, F.fi1), F.key0, F.key1);
     const uint64_t bits = ((uint64_t)w.y << 32) | (uint64_t)w.x;
     const double u = (double)(((bits >> 12) << 1) | 1ull) * 0x1p-53;
-    if (u < 0.5)
-        return sigma * log(2.0 * u);
-    return -sigma * log(2.0 * (1.0 - u));
+    // one log per lane: the two tails differ only in its argument and sign
+    const bool lower = u < 0.5;
+    const double l = log(lower ? 2.0 * u : 2.0 * (1.0 - u));
+    return lower ? sigma * l : -sigma * l;
 }
 
 // Release one statistic: mean = sum / area, plus noise (Eq. 11 scale given by

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import oracle
-from tests.helpers import compare_frame, oracle_params, chw_to_hwc
+from tests.helpers import compare_frame, oracle_params, chw_to_hwc, run_gpu
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -228,3 +228,42 @@ def test_edge_mask_label_matches_oracle(dev, H, W, C, b, sb, T, pad):
     assert np.array_equal(masks[0].cpu().numpy(), want_mask)
     want = oracle.forward(img, want_mask, oracle_params(fp))
     compare_frame(plan.store_host()[0], want, out.cpu().numpy(), "edge-labelled")
+
+
+
+@pytest.mark.parametrize("case", ["1100 tiny frames", "300 frames, 38400 tiles"])
+def test_scan_many_frames_store_offsets(dev, case):
+    """The scan of the complex counts over batches with more frames than one
+    workgroup's lanes (the frame-level pass loops) and with many tiles: store
+    offsets are the running sums of every frame's counts in batch order, and
+    sampled frames (first, last and random ones) equal the oracle."""
+    say("case: scan", case)
+    r = np.random.Generator(np.random.PCG64(len(case)))
+    frames, imgs, masks = [], [], []
+    if case.startswith("1100"):
+        for i in range(1100):
+            H, W, C = int(r.integers(1, 41)), int(r.integers(1, 71)), int(r.choice([1, 3]))
+            b = int(r.choice([4, 8]))
+            sb = int(r.choice([s for s in (1, 2, 4, 8) if b % s == 0]))
+            frames.append(dp.FrameParams(H, W, C, dp.U8_HWC, b=b, sb=sb, m=4, eps_bg=1.0, eps_fg=0.5, tau=1,
+                                         pad_mode=int(r.integers(0, 3)), seed=9, frame_index=i))
+            imgs.append(r.integers(0, 256, (H, W, C), dtype=np.uint8))
+            masks.append((r.random((H, W)) < 0.3).astype(np.uint8))
+    else:
+        for i in range(300):
+            frames.append(dp.FrameParams(256, 64, 1, dp.U8_HWC, b=2, sb=1, m=2, eps_bg=1.0, eps_fg=0.5, tau=2,
+                                         seed=10, frame_index=i))
+            imgs.append(r.integers(0, 256, (256, 64, 1), dtype=np.uint8))
+            masks.append((r.random((256, 64)) < 0.4).astype(np.uint8))
+    res = run_gpu(frames, imgs, masks, dev, reconstruct=False)
+    ob = of = 0
+    for fp, fi, st in zip(frames, res["info"], res["store"]):
+        nb, nf = st["counts"]
+        assert nb + nf == fi.grid_rows * fi.grid_cols and nf == int(st["flags"].sum())
+        assert st["offsets"] == (ob, of)
+        ob += nb * fp.channels
+        of += nf * fi.n * fi.n * fp.channels
+    picks = {0, len(frames) - 1} | {int(k) for k in r.choice(len(frames), size=8, replace=False)}
+    for i in sorted(picks):
+        want = oracle.forward(imgs[i], masks[i], oracle_params(frames[i]))
+        compare_frame(res["store"][i], want, res["fused"][i], "frame %d" % i)
