@@ -58,6 +58,7 @@ struct dppix_plan {
     std::vector<int64_t> sched_base;
     int64_t n_tiles = 0;
     int64_t n_units = 0;
+    bool prefix_scan = false;           // the plan's scan needs no hand-off between workgroups
     int64_t total_cells = 0;
     int64_t total_fine = 0;
     int64_t total_pixels = 0;
@@ -304,6 +305,9 @@ dppix_status_t dp_pix_plan_create(const dppix_frame_desc_t* descs, int32_t n_fra
         delete p;
         return fail(DPPIX_ENOTSUP, "more than 2^31 tiles");
     }
+    p->prefix_scan = tile <= kPrefixScanTiles;
+    for (const FrameRec& F : p->frames)
+        p->prefix_scan = p->prefix_scan && F.C == p->frames[0].C && F.n == p->frames[0].n && F.K < 65536;
     // Scheduling order: frames with the heaviest tiles first (longest tiles
     // start early, the tail is made of light ones); ties keep batch order.
     std::vector<int32_t> order(n_frames);
@@ -560,7 +564,8 @@ dppix_status_t dp_pix_plan(dppix_plan_t p, const uint8_t* const* masks, const dp
     TileArgs a = base_args(p);
     a.masks = masks;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    hipError_t e = launch_plan(a, p->n_units, plain_threads(p), p->lds[kPlan], store ? store->counts : nullptr, s);
+    hipError_t e = launch_plan(a, p->n_units, plain_threads(p), p->lds[kPlan], p->prefix_scan,
+                               store ? store->counts : nullptr, s);
     if (e != hipSuccess)
         return dev_fail(e, "plan launch");
     return DPPIX_OK;

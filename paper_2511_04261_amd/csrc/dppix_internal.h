@@ -92,8 +92,12 @@ struct TileArgs {
 };
 
 // Host-side launchers (defined in dppix_kernels.hip).
-hipError_t launch_plan(const TileArgs& a, int64_t n_units, int threads, size_t lds, uint64_t* counts_out,
-                       hipStream_t s);
+// prefix_scan: every frame has the same C and n and the batch has at most
+// kPrefixScanTiles tiles (each workgroup of the scan then re-reads the counts
+// of all earlier frames instead of waiting for the others).
+constexpr int64_t kPrefixScanTiles = 16384;
+hipError_t launch_plan(const TileArgs& a, int64_t n_units, int threads, size_t lds, bool prefix_scan,
+                       uint64_t* counts_out, hipStream_t s);
 hipError_t launch_forward(const TileArgs& a, int layout, int C, int threads, size_t lds, int grid, hipStream_t s);
 hipError_t launch_reconstruct(const TileArgs& a, int layout, int C, int threads, size_t lds, int grid,
                               hipStream_t s);

@@ -578,6 +578,62 @@ __global__ __launch_bounds__(256) void k_scan(TileArgs a, uint64_t* frame_base, 
         atomicExch(&a.ticket[kScanWord], 0u);
 }
 
+// The scan without a hand-off between workgroups, for batches whose frames
+// share C and n (a frame's store size is then a fixed weight times its
+// counts) and whose tile counts are few: frames are concatenated, so the
+// complex cells of every earlier frame are one prefix of the tile array,
+// which workgroup f adds up itself before scanning its own tiles.
+__global__ __launch_bounds__(256) void k_scan_prefix(TileArgs a, uint64_t* frame_base, uint64_t* counts)
+{
+    __shared__ uint32_t wave_tot[9];
+    const int f = blockIdx.x, tid = threadIdx.x, NT = blockDim.x;
+    const FrameRec F = a.frames[f];
+    const int64_t t0 = F.tile_base;
+    const int64_t nt = (int64_t)F.GR * F.TX;
+    // tile counts of the earlier frames: 16 bytes a load, all in flight
+    const int64_t n4 = t0 >> 2;
+    const v4u* c4 = reinterpret_cast<const v4u*>(a.tile_cnt);
+    uint32_t part = tid < (int)(t0 & 3) ? a.tile_cnt[4 * n4 + tid] : 0u;
+    for (int64_t base = 0; base < n4; base += 8 * (int64_t)NT) {
+        v4u w[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int64_t i = base + (int64_t)k * NT + tid;
+            w[k] = i < n4 ? c4[i] : v4u{0u, 0u, 0u, 0u};
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            part += (w[k].x + w[k].y) + (w[k].z + w[k].w);
+    }
+    uint32_t before;
+    block_exclusive_scan<uint32_t>(part, wave_tot, before);
+    uint32_t carry = 0;
+    for (int64_t base = 0; base < nt; base += NT) {
+        const int64_t i = base + tid;
+        const uint32_t v = i < nt ? a.tile_cnt[t0 + i] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_exclusive_scan<uint32_t>(v, wave_tot, tot);
+        if (i < nt)
+            a.tile_fg[t0 + i] = carry + ex;
+        carry += tot;
+    }
+    if (tid == 0) {
+        const uint64_t nf = carry, nb = (uint64_t)F.GR * (uint64_t)F.GC - nf;
+        const uint64_t bb = (uint64_t)F.C * ((uint64_t)F.cell_base - before);
+        const uint64_t fb = (uint64_t)F.n * (uint64_t)F.n * (uint64_t)F.C * (uint64_t)before;
+        frame_base[2 * f + 0] = bb;
+        frame_base[2 * f + 1] = fb;
+        if (counts) {
+            counts[4 * f + 0] = nb;
+            counts[4 * f + 1] = nf;
+            counts[4 * f + 2] = bb;
+            counts[4 * f + 3] = fb;
+        }
+    }
+    if (f == 0 && tid < kScanWord)
+        a.ticket[tid] = 0;
+}
+
 // Subgrid rows per phase-1 item: with short subgrid rows an item takes
 // several, so that every lane has about eight row loads in flight.
 __device__ __forceinline__ int rows_per_item(int s) { return s == 2 ? 4 : ((s == 3 || s == 4) ? 2 : 1); }
@@ -1726,8 +1782,8 @@ hipError_t allow_lds(K kernel, size_t lds)
                                (int)lds);
 }
 
-hipError_t launch_plan(const TileArgs& a, int64_t n_units, int threads, size_t lds, uint64_t* counts_out,
-                       hipStream_t s)
+hipError_t launch_plan(const TileArgs& a, int64_t n_units, int threads, size_t lds, bool prefix_scan,
+                       uint64_t* counts_out, hipStream_t s)
 {
     if (n_units == 0)
         return hipSuccess;
@@ -1738,8 +1794,12 @@ hipError_t launch_plan(const TileArgs& a, int64_t n_units, int threads, size_t l
     e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(k_scan, dim3((unsigned)a.n_frames), dim3(256), 0, s, a, const_cast<uint64_t*>(a.frame_base),
-                       counts_out);
+    if (prefix_scan)
+        hipLaunchKernelGGL(k_scan_prefix, dim3((unsigned)a.n_frames), dim3(256), 0, s, a,
+                           const_cast<uint64_t*>(a.frame_base), counts_out);
+    else
+        hipLaunchKernelGGL(k_scan, dim3((unsigned)a.n_frames), dim3(256), 0, s, a,
+                           const_cast<uint64_t*>(a.frame_base), counts_out);
     return hipGetLastError();
 }
 

@@ -231,20 +231,26 @@ def test_edge_mask_label_matches_oracle(dev, H, W, C, b, sb, T, pad):
 
 
 
-@pytest.mark.parametrize("case", ["1100 tiny frames", "300 frames, 38400 tiles"])
+@pytest.mark.parametrize("case", ["1100 tiny frames, mixed C and n", "1100 tiny frames, one C and n",
+                                  "300 frames, 38400 tiles"])
 def test_scan_many_frames_store_offsets(dev, case):
-    """The scan of the complex counts over batches with more frames than one
-    workgroup's lanes (the frame-level pass loops) and with many tiles: store
-    offsets are the running sums of every frame's counts in batch order, and
-    sampled frames (first, last and random ones) equal the oracle."""
+    """Both scans of the complex counts: the per-frame workgroups with a
+    frame-level pass (mixed C or n, or more than 16384 tiles; here with more
+    frames than one workgroup's lanes, so that pass loops) and the one where
+    each workgroup adds up the counts of all earlier frames itself (one C and
+    n, few tiles).  Store offsets are the running sums of every frame's counts
+    in batch order, and sampled frames (first, last and random ones) equal the
+    oracle."""
     say("case: scan", case)
     r = np.random.Generator(np.random.PCG64(len(case)))
     frames, imgs, masks = [], [], []
     if case.startswith("1100"):
+        mixed = "mixed" in case
         for i in range(1100):
-            H, W, C = int(r.integers(1, 41)), int(r.integers(1, 71)), int(r.choice([1, 3]))
+            H, W = int(r.integers(1, 41)), int(r.integers(1, 71))
+            C = int(r.choice([1, 3])) if mixed else 3
             b = int(r.choice([4, 8]))
-            sb = int(r.choice([s for s in (1, 2, 4, 8) if b % s == 0]))
+            sb = int(r.choice([s for s in (1, 2, 4, 8) if b % s == 0])) if mixed else b // 2
             frames.append(dp.FrameParams(H, W, C, dp.U8_HWC, b=b, sb=sb, m=4, eps_bg=1.0, eps_fg=0.5, tau=1,
                                          pad_mode=int(r.integers(0, 3)), seed=9, frame_index=i))
             imgs.append(r.integers(0, 256, (H, W, C), dtype=np.uint8))
