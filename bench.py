@@ -454,7 +454,8 @@ def main():
                      "kernel": "k_forward_u8<3>", "alg_bytes_per_launch": ab["forward"],
                      "avg_launch_ms": round(res["fwd_ms"], 4),
                      "timing": "HIP events around back-to-back launches on the library stream"},
-        "plan_kernel": {"kernel": "k_plan", "avg_launch_ms": round(res["plan_ms"], 4),
+        "plan_kernel": {"kernel": "k_plan + k_scan_prefix (one dp_pix_plan call)",
+                        "avg_launch_ms": round(res["plan_ms"], 4),
                         "alg_bytes_per_launch": ab["mask"],
                         "gbs": round(ab["mask"] / (res["plan_ms"] * 1e-3) / 1e9, 1)},
         "step_gbs_algorithmic": round(step_gbs, 1),
