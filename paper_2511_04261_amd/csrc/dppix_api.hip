@@ -58,6 +58,7 @@ struct dppix_plan {
     std::vector<int64_t> sched_base;
     int64_t n_tiles = 0;
     int64_t n_units = 0;
+    int64_t n_border = 0;               // tiles with pixels that mirrored padding folds onto
     bool prefix_scan = false;           // the plan's scan needs no hand-off between workgroups
     int64_t total_cells = 0;
     int64_t total_fine = 0;
@@ -360,6 +361,29 @@ dppix_status_t dp_pix_plan_create(const dppix_frame_desc_t* descs, int32_t n_fra
     w.frames = o;      o = align256(o + sizeof(FrameRec) * n_frames);
     w.tile_map = o;    o = align256(o + sizeof(int32_t) * 2 * (size_t)p->n_tiles);
     w.unit_map = o;    o = align256(o + sizeof(int32_t) * 2 * (size_t)p->n_units);
+    // Tiles of the adjoint's mirror pass: those holding a real pixel that a
+    // padded row or column folds onto (the same test the kernel applies).
+    std::vector<int32_t> border;
+    for (int32_t f = 0; f < n_frames; ++f) {
+        const FrameRec& F = p->frames[f];
+        if (F.pad == DPPIX_PAD_NONE)
+            continue;
+        const int PR = F.GR * F.b - F.H, PC = F.GC * F.b - F.W;
+        const int lo_r = PR > 0 ? (PR <= F.H - 1 ? F.H - 1 - PR : 0) : F.H;
+        const int lo_c = PC > 0 ? (PC <= F.W - 1 ? F.W - 1 - PC : 0) : F.W;
+        for (int32_t r = 0; r < F.GR; ++r)
+            for (int32_t ct = 0; ct < F.TX; ++ct) {
+                const int x0c = ct * F.K, Kt = std::min(F.K, F.GC - x0c);
+                const int y0 = r * F.b, y1 = std::min(y0 + F.b, F.H);
+                const int xa = x0c * F.b, xb = std::min((x0c + Kt) * F.b, F.W);
+                if (y0 >= F.H || xa >= F.W || (y1 <= lo_r && xb <= lo_c))
+                    continue;
+                border.push_back(f);
+                border.push_back(r * F.TX + ct);
+            }
+    }
+    p->n_border = (int64_t)border.size() / 2;
+    w.border_map = o;  o = align256(o + sizeof(int32_t) * border.size());
     w.flags = o;       o = align256(o + (size_t)p->total_cells);
     w.tile_cnt = o;    o = align256(o + sizeof(uint32_t) * (size_t)p->n_tiles);
     w.tile_fg = o;     o = align256(o + sizeof(uint32_t) * (size_t)p->n_tiles);
@@ -378,6 +402,8 @@ dppix_status_t dp_pix_plan_create(const dppix_frame_desc_t* descs, int32_t n_fra
             map[2 * i] = order[k];
             map[2 * i + 1] = (int32_t)(i - p->sched_base[k]);
         }
+    if (!border.empty())
+        std::memcpy(p->host_tables.data() + w.border_map, border.data(), sizeof(int32_t) * border.size());
     int32_t* umap = reinterpret_cast<int32_t*>(p->host_tables.data() + w.unit_map);
     for (int32_t f = 0, u = 0; f < n_frames; ++f)
         for (int32_t i = 0; i < p->frames[f].cunits; ++i, ++u) {
@@ -664,10 +690,16 @@ dppix_status_t dp_pix_backward(dppix_plan_t p, const dppix_store_t* store, const
     });
     if (e != hipSuccess)
         return dev_fail(e, "backward launch");
-    // 3. mirror terms of the pixels near padded borders
-    e = launch_backward_mirror(a, plain_threads(p), grid_for(p, 1, 1, plain_threads(p), p->n_tiles, 0), s);
-    if (e != hipSuccess)
-        return dev_fail(e, "backward launch");
+    // 3. mirror terms of the pixels near padded borders: only the border
+    // tiles, and no launch at all when no frame is padded
+    if (p->n_border > 0) {
+        TileArgs m = a;
+        m.tile_map = reinterpret_cast<const int32_t*>(p->bound + p->ws.border_map);
+        m.n_tiles = p->n_border;
+        e = launch_backward_mirror(m, plain_threads(p), grid_for(p, 1, 1, plain_threads(p), p->n_border, 0), s);
+        if (e != hipSuccess)
+            return dev_fail(e, "backward launch");
+    }
     return DPPIX_OK;
 }
 

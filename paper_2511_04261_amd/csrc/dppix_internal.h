@@ -40,6 +40,7 @@ struct WsLayout {
     size_t frames;        // FrameRec[n_frames]
     size_t tile_map;      // int32[n_tiles][2]: (frame, tile within frame) per scheduling index
     size_t unit_map;      // int32[n_units][2]: (frame, plan unit within frame), frame-major
+    size_t border_map;    // int32[n_border][2]: (frame, tile) of the tiles the adjoint's mirror pass visits
     size_t flags;         // uint8[total_cells] (classification)
     size_t tile_cnt;      // uint32[n_tiles]: complex cells per tile
     size_t tile_fg;       // uint32[n_tiles]: complex cells of the frame before the tile
