@@ -674,23 +674,14 @@ dppix_status_t dp_pix_backward(dppix_plan_t p, const dppix_store_t* store, const
     a.g_fg = reinterpret_cast<float*>(sc + align256(4 * p->bg_cap));
     a.cell_index = reinterpret_cast<uint32_t*>(sc + align256(4 * p->bg_cap) + align256(4 * p->fg_cap));
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    // 1. gradient of every statistic (store layout): pass * sum of grad_out over its real pixels / area
+    // 1. gradient of every statistic (store layout): pass * sum of grad_out
+    // over its real pixels / area, broadcast in the same tile to the real
+    // pixels of the statistic (grad_in)
     hipError_t e = launch_backward_reduce(a, plain_threads(p), p->lds[kBwd],
                                           grid_for(p, 1, 1, plain_threads(p), p->n_tiles, p->lds[kBwd]), s);
     if (e != hipSuccess)
         return dev_fail(e, "backward launch");
-    // 2. each real pixel takes its own statistic's gradient: a reconstruction of the gradient store
-    TileArgs r = a;
-    r.bg = a.g_bg;
-    r.fg = a.g_fg;
-    r.outs = reinterpret_cast<void* const*>(grad_in);
-    r.cell_index = nullptr;
-    e = for_groups(p, r, true, [&](const TileArgs& ga, const LaunchGroup& g, size_t lds, int grid) {
-        return launch_reconstruct(ga, g.layout, g.C, group_threads(p, g), lds, grid, s);
-    });
-    if (e != hipSuccess)
-        return dev_fail(e, "backward launch");
-    // 3. mirror terms of the pixels near padded borders: only the border
+    // 2. mirror terms of the pixels near padded borders: only the border
     // tiles, and no launch at all when no frame is padded
     if (p->n_border > 0) {
         TileArgs m = a;

@@ -962,6 +962,52 @@ __device__ void forward_tile_u8(const TileArgs& a, const FrameRec& F, const Tile
 // Forward, fp32 CHW.  Column sums in fp32 over at most s_b rows, subcell and
 // cell sums in fp64.
 // ==========================================================================
+// Broadcast of a tile's statistics to its real pixels, fp32 CHW: per
+// (channel, subgrid row) one padded row is expanded in LDS (two alternating
+// buffers of 4 * nstr floats at `rowbuf`, one barrier per row) and each lane
+// stores the s_b rows of one 4-float strip.  vgs / vgc hold the values of the
+// simple cells and of the complex subcells (as the fp32 forward lays them out).
+__device__ void broadcast_tile_f32(const FrameRec& F, int r, int64_t X0, int64_t lim, int Kt, int nstr,
+                                   float* rowbuf, const uint8_t* cflag, const float* vgs, const float* vgc,
+                                   float* out)
+{
+    const int tid = threadIdx.x, NT = blockDim.x;
+    const int b = F.b, s = F.s, n = F.n, H = F.H, C = F.C;
+    const int kn = Kt * n;
+    const int64_t pitch = F.pitch, plane = pitch * H;
+    const bool out_aligned = ((reinterpret_cast<uintptr_t>(out) | (uintptr_t)(pitch * 4) | (uintptr_t)(X0 * 4)) & 15) == 0;
+    for (int ch = 0; ch < C; ++ch) {
+        float* pl = out + plane * ch;
+        for (int fr = 0; fr < n; ++fr) {
+            float* exf = rowbuf + ((ch * n + fr) & 1) * (4 * nstr);   // two alternating row buffers
+            for (int fc = tid; fc < kn; fc += NT) {
+                const int kc = fc / n;
+                const float v = cflag[kc] ? vgc[(fr * kn + fc) * C + ch] : vgs[kc * C + ch];
+                for (int x = 0; x < s; ++x)
+                    exf[fc * s + x] = v;
+            }
+            lds_barrier();
+            const int row0 = r * b + fr * s;
+            const int rows = min(s, H - row0);
+            for (int st = tid; st < nstr; st += NT) {
+                const int64_t p0 = X0 + 4 * st;
+                if (p0 >= lim)
+                    continue;
+                const v4f v = reinterpret_cast<const v4f*>(exf)[st];
+                if (out_aligned && p0 + 4 <= lim) {
+                    for (int k = 0; k < rows; ++k)
+                        st16f_nt(pl + (int64_t)(row0 + k) * pitch + p0, v);
+                } else {
+                    const float vv[4] = {v.x, v.y, v.z, v.w};
+                    for (int k = 0; k < rows; ++k)
+                        for (int q = 0; q < 4 && p0 + q < lim; ++q)
+                            pl[(int64_t)(row0 + k) * pitch + p0 + q] = vv[q];
+                }
+            }
+        }
+    }
+}
+
 __device__ void forward_tile_f32(const TileArgs& a, const FrameRec& F, const TileCoord& tc, uint8_t* lds)
 {
     const int tid = threadIdx.x, NT = blockDim.x;
@@ -1089,37 +1135,7 @@ __device__ void forward_tile_f32(const TileArgs& a, const FrameRec& F, const Til
     if (out == nullptr)
         return;
     lds_barrier();
-    const bool out_aligned = ((reinterpret_cast<uintptr_t>(out) | (uintptr_t)(pitch * 4) | (uintptr_t)(X0 * 4)) & 15) == 0;
-    for (int ch = 0; ch < C; ++ch) {
-        float* pl = out + plane * ch;
-        for (int fr = 0; fr < n; ++fr) {
-            float* exf = colsum + ((ch * n + fr) & 1) * (4 * nstr);   // two alternating row buffers
-            for (int fc = tid; fc < kn; fc += NT) {
-                const int kc = fc / n;
-                const float v = cflag[kc] ? vgc[(fr * kn + fc) * C + ch] : vgs[kc * C + ch];
-                for (int x = 0; x < s; ++x)
-                    exf[fc * s + x] = v;
-            }
-            lds_barrier();
-            const int row0 = r * b + fr * s;
-            const int rows = min(s, H - row0);
-            for (int st = tid; st < nstr; st += NT) {
-                const int64_t p0 = X0 + 4 * st;
-                if (p0 >= lim)
-                    continue;
-                const v4f v = reinterpret_cast<const v4f*>(exf)[st];
-                if (out_aligned && p0 + 4 <= lim) {
-                    for (int k = 0; k < rows; ++k)
-                        st16f_nt(pl + (int64_t)(row0 + k) * pitch + p0, v);
-                } else {
-                    const float vv[4] = {v.x, v.y, v.z, v.w};
-                    for (int k = 0; k < rows; ++k)
-                        for (int q = 0; q < 4 && p0 + q < lim; ++q)
-                            pl[(int64_t)(row0 + k) * pitch + p0 + q] = vv[q];
-                }
-            }
-        }
-    }
+    broadcast_tile_f32(F, r, X0, lim, Kt, nstr, colsum, cflag, vgs, vgc, out);
 }
 
 // Persistent workgroups take tiles from an atomic ticket; the last one out
@@ -1375,6 +1391,9 @@ __device__ void backward_reduce_tile(const TileArgs& a, const FrameRec& F, const
     double* cspart = reinterpret_cast<double*>(lds + L.cspart);
     uint32_t* cidx = reinterpret_cast<uint32_t*>(lds + L.cidx);
     uint8_t* cflag = lds + L.cflag;
+    float* vgs = reinterpret_cast<float*>(lds + L.vgs);
+    float* vgc = reinterpret_cast<float*>(lds + L.vgc);
+    float* gin = a.grad_in ? a.grad_in[tc.f] : nullptr;
     tile_cells(a, F, tc.t, r, x0c, Kt, cidx, cflag, false);
     const uint64_t bg_base = a.frame_base[2 * tc.f + 0];
     const uint64_t fg_base = a.frame_base[2 * tc.f + 1];
@@ -1436,7 +1455,9 @@ __device__ void backward_reduce_tile(const TileArgs& a, const FrameRec& F, const
                     const int fr = fr0 + g;
                     const uint64_t at = fg_base + ((uint64_t)cidx[kc] * nn + fr * n + jj) * C + ch;
                     const double area = stat_area(F, r * b + fr * s, x0c * b + fc * s, s);
-                    a.g_fg[at] = (a.clip_fg[at] && area > 0.0) ? (float)(G / area) : 0.f;
+                    const float gv = (a.clip_fg[at] && area > 0.0) ? (float)(G / area) : 0.f;
+                    a.g_fg[at] = gv;
+                    vgc[(fr * kn + fc) * C + ch] = gv;
                 }
             }
             cspart[ci] = part;
@@ -1451,8 +1472,16 @@ __device__ void backward_reduce_tile(const TileArgs& a, const FrameRec& F, const
         for (int jj = 0; jj < n; ++jj)
             G += cspart[(kc * n + jj) * C + ch];
         const uint64_t at = bg_base + (uint64_t)cidx[kc] * C + ch;
-        a.g_bg[at] = a.clip_bg[at] ? (float)(G / stat_area(F, r * b, (x0c + kc) * b, b)) : 0.f;
+        const float gv = a.clip_bg[at] ? (float)(G / stat_area(F, r * b, (x0c + kc) * b, b)) : 0.f;
+        a.g_bg[at] = gv;
+        vgs[kc * C + ch] = gv;
     }
+    if (gin == nullptr)
+        return;
+    // every real pixel takes its own statistic's gradient (the mirror terms
+    // of pixels near padded borders are added by a later pass)
+    lds_barrier();
+    broadcast_tile_f32(F, r, X0, lim, Kt, nstr, colsum, cflag, vgs, vgc, gin);
 }
 
 __global__ __launch_bounds__(kMaxThreads) void k_backward_reduce(TileArgs a)

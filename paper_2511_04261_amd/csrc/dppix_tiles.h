@@ -24,8 +24,8 @@ struct LdsPlan {
     uint32_t cspart;  // per (subcell column, channel) running sum over subcell rows
     uint32_t cidx;    // per cell: index within its class (frame-local)
     uint32_t cflag;   // per cell: 1 = complex
-    uint32_t vgs;     // per (cell, channel): value of a simple cell
-    uint32_t vgc;     // per (subcell row, subcell column, channel): value of a complex subcell
+    uint32_t vgs;     // per (cell, channel): value of a simple cell (adjoint: its gradient)
+    uint32_t vgc;     // per (subcell row, subcell column, channel): value of a complex subcell (adjoint: gradient)
     uint32_t cxl;     // u8 forward: the tile's complex cells in order (uint16 each)
     uint32_t bytes;
 };
@@ -59,9 +59,10 @@ __host__ __device__ inline LdsPlan lds_plan(int kind, int K, int b, int n, int C
         const uint32_t rows = (uint32_t)C * (uint32_t)(n < kRowGroupF ? n : kRowGroupF);
         o += al16(16u * nstr * (rows > 2u ? rows : 2u));
     } else if (kind == kBwd) {
-        // float4 column sums per (channel, subgrid row of a group)
+        // float4 column sums per (channel, subgrid row of a group), at least
+        // the two expanded rows of the gradient broadcast
         const uint32_t rows = (uint32_t)C * (uint32_t)(n < kRowGroupF ? n : kRowGroupF);
-        o += al16(16u * nstr * rows);
+        o += al16(16u * nstr * (rows > 2u ? rows : 2u));
     }
     else
         o += al16(32u * nstr);
@@ -77,12 +78,12 @@ __host__ __device__ inline LdsPlan lds_plan(int kind, int K, int b, int n, int C
     p.vgs = o;
     if (kind == kFwdU8 || kind == kRecU8)
         o += al16((uint32_t)(K * C));
-    else if (kind == kFwdF32 || kind == kRecF32)
+    else if (kind == kFwdF32 || kind == kRecF32 || kind == kBwd)
         o += al16(4u * (uint32_t)(K * C));
     p.vgc = o;
     if (kind == kFwdU8 || kind == kRecU8)
         o += al16((uint32_t)(K * n * n * C));
-    else if (kind == kFwdF32 || kind == kRecF32)
+    else if (kind == kFwdF32 || kind == kRecF32 || kind == kBwd)
         o += al16(4u * (uint32_t)(K * n * n * C));
     p.cxl = o;
     if (kind == kFwdU8)
