@@ -1368,9 +1368,11 @@ __global__ __launch_bounds__(kMaxThreads) void k_reconstruct_f32(TileArgs a)
 }
 
 // ==========================================================================
-// Adjoint (fp32 CHW).  Pass 1 per tile: G_k = sum of grad_out over the real
-// pixels of statistic k, g_k = pass_k * G_k / area_k.  Pass 2 per pixel: sum
-// g over every padded position that folds onto the pixel.
+// Adjoint (fp32 CHW).  Per tile: G_k = sum of grad_out over the real pixels
+// of statistic k, g_k = pass_k * G_k / area_k (kept in the gradient store for
+// the mirror terms), and every real pixel of the tile takes its own g_k.
+// Then, only where padding folds onto real pixels: add the g of every padded
+// position that folds onto the pixel.
 // ==========================================================================
 __device__ void backward_reduce_tile(const TileArgs& a, const FrameRec& F, const TileCoord& tc, uint8_t* lds)
 {
@@ -1504,7 +1506,7 @@ __device__ __forceinline__ float g_at(const TileArgs& a, const FrameRec& F, int 
 // Mirror terms of the adjoint: a real pixel near the bottom or right border is
 // also the source of the padded positions that fold onto it, and collects
 // their statistics' gradients too.  Its own statistic's gradient is already in
-// grad_in (the gradient statistics broadcast like a reconstruction), so only
+// grad_in (broadcast by the reduction's tile), so only
 // the pixels that have mirror preimages are visited, and only the mirror
 // terms are added.  Nothing to do in the unpadded mode.
 __device__ void backward_mirror_tile(const TileArgs& a, const FrameRec& F, const TileCoord& tc)
