@@ -479,7 +479,17 @@ __device__ void plan_count(const TileArgs& a, const FrameRec& F, const uint8_t* 
                     acc_bytes(nz_strip(w[i]), e, o);
             }
         }
-        spread_strip(e, o, cellcnt + j * KCs, KC, b, 16 * st);
+        if ((b & 15) == 0) {
+            // b a multiple of 16: the strip lies in one cell, one counter
+            // update (a 16-bit half sums at most 8 columns of 16 rows)
+            const uint32_t t = (e[0] + e[1] + e[2] + e[3]) + (o[0] + o[1] + o[2] + o[3]);
+            const uint32_t cnt = (t & 0xFFFFu) + (t >> 16);
+            const int cell = (16 * st) / b;
+            if (cnt != 0u && cell < KC)
+                atomicAdd(cellcnt + j * KCs + cell, cnt);
+        } else {
+            spread_strip(e, o, cellcnt + j * KCs, KC, b, 16 * st);
+        }
     }
     for (int item = tid; item < nb * b * nslow; item += NT) {
         const int st = nfast + item % nslow;
