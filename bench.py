@@ -127,12 +127,27 @@ def time_steps(step_fn, warmup, steps):
     return time.perf_counter() - t0
 
 
+def warm_up(call, ms=30.0):
+    """Untimed launches until about `ms` of GPU time has passed: after the
+    host has kept the GPU idle (building inputs), its clocks take some 10 ms
+    of load to settle, and work timed before that reads several per cent
+    slow."""
+    import torch
+    t0 = time.perf_counter()
+    while True:
+        for _ in range(4):
+            call()
+        torch.cuda.synchronize()
+        if (time.perf_counter() - t0) * 1e3 >= ms:
+            return
+
+
 def time_launches(call, n, stream):
     """Average duration of one launch: n back-to-back launches of the same
-    call between two HIP events on the stream the kernels run on."""
+    call between two HIP events on the stream the kernels run on, after a
+    warm-up."""
     import torch
-    call()
-    torch.cuda.synchronize()
+    warm_up(call)
     a = torch.cuda.Event(enable_timing=True)
     b = torch.cuda.Event(enable_timing=True)
     a.record(stream)
@@ -389,8 +404,10 @@ def cpu_baseline_parallel(n_frames, budget_s=10.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    # 200 untimed steps (about 40 ms of GPU work) bring the clocks to their
+    # steady state before the timed steps start
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--frames", type=int, default=64)
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-extra", action="store_true", help="only the headline workload")
@@ -463,7 +480,7 @@ def main():
     }
     if not args.skip_extra:
         log("bench: per-frame launches")
-        pf = run_per_frame(frames_s, dev, 1, max(3, args.steps // 4))
+        pf = run_per_frame(frames_s, dev, 10, max(3, min(args.steps, 50)))
         pf_gbs = pf["bytes"] / (pf["step_ms"] * 1e-3) / 1e9
         out["per_frame"] = {"value": round(pf["pixels"] / (pf["step_ms"] * 1e-3) / 1e6, 1), "unit": "megapixels/s",
                             "ms_per_step": round(pf["step_ms"], 3), "frac_hbm": round(pf_gbs / HBM_PEAK_GBS, 4)}
@@ -471,7 +488,7 @@ def main():
         torch.cuda.empty_cache()
         log("bench: uneven mixed-resolution batch (256 frames)")
         ub = synth.uneven_batch(256)
-        ur = run_batched(ub, dev, 2, max(5, args.steps // 2), graph=True, threads=args.threads)
+        ur = run_batched(ub, dev, 15, max(5, min(args.steps, 50)), graph=True, threads=args.threads)
         u_gbs = ur["bytes"]["step"] / (ur["step_ms"] * 1e-3) / 1e9
         uf_gbs = ur["bytes"]["forward"] / (ur["fwd_ms"] * 1e-3) / 1e9
         out["uneven_batch"] = {"value": round(ur["pixels"] / (ur["step_ms"] * 1e-3) / 1e6, 1),
