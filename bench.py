@@ -75,10 +75,11 @@ def read_traffic(bytes_per_launch_alg: float):
     return fetch + write
 
 
-def build_batch(frames_s, dev, persistent=0, threads=0, host_render=False):
+def build_batch(frames_s, dev, persistent=0, threads=0, host_render=False, frames=None):
     import torch
     import paper_2511_04261_amd as dp
-    frames = [dp.FrameParams.from_spec(s) for s in frames_s]
+    if frames is None:
+        frames = [dp.FrameParams.from_spec(s) for s in frames_s]
     plan = dp.Plan(frames, device=dev, threads=threads, persistent=persistent)
     if host_render:
         # byte-identical frames rendered on the host and copied over (no
@@ -158,9 +159,9 @@ def time_launches(call, n, stream):
     return a.elapsed_time(b) / n
 
 
-def run_batched(frames_s, dev, warmup, steps, graph=False, threads=0, persistent=0):
+def run_batched(frames_s, dev, warmup, steps, graph=False, threads=0, persistent=0, frames=None):
     import torch
-    plan, imgs, masks, outs = build_batch(frames_s, dev, persistent=persistent, threads=threads)
+    plan, imgs, masks, outs = build_batch(frames_s, dev, persistent=persistent, threads=threads, frames=frames)
     stream = torch.cuda.current_stream()
     plan_call, fwd_call = plan.bound_calls(masks, imgs, outs, stream)
     g = plan.graph(masks, imgs, outs, stream) if graph else None
@@ -179,6 +180,29 @@ def run_batched(frames_s, dev, warmup, steps, graph=False, threads=0, persistent
     ab = alg_bytes(plan)
     return dict(plan=plan, seconds=dt, step_ms=1e3 * dt / steps, fwd_ms=fwd_ms, plan_ms=plan_ms, bytes=ab,
                 pixels=sum(fp.height * fp.width for fp in plan.frames))
+
+
+def autotune_batch(frames_s, dev):
+    """Tile shapes and workgroup size for the batch from the project's
+    autotuner, timing whole candidate configurations of this batch (one
+    workgroup per tile; tile rows of about 1-4 KB or the library's choice;
+    0 / 128 / 256 lanes)."""
+    import torch
+    import paper_2511_04261_amd as dp
+    from paper_2511_04261_amd.autotune import Autotuner
+    t0 = time.perf_counter()
+    imgs = [s.image_torch(dev) for s in frames_s]
+    masks = [s.mask_torch(dev) for s in frames_s]
+    tuner = Autotuner(dev, cache_path=None, reps=5, threads=(0, 128, 256), launch_modes=(0,))
+    tuned, info = tuner.tune_whole_batch([dp.FrameParams.from_spec(s) for s in frames_s], imgs, masks)
+    del imgs, masks
+    torch.cuda.empty_cache()
+    launch = dict(threads=info["threads"], persistent=info["persistent"])
+    return tuned, launch, dict(seconds=round(time.perf_counter() - t0, 1), tile_bytes=info["tile_bytes"],
+                               threads=info["threads"], candidates=len(info["tried"]),
+                               ms_best=round(info["ms"], 4),
+                               ms_library_default=round(min(r["ms"] for r in info["tried"] if r["tile_bytes"] == 0
+                                                            and r["threads"] == 0), 4))
 
 
 def run_per_frame(frames_s, dev, warmup, steps):
@@ -486,18 +510,27 @@ def main():
                             "ms_per_step": round(pf["step_ms"], 3), "frac_hbm": round(pf_gbs / HBM_PEAK_GBS, 4)}
         del res
         torch.cuda.empty_cache()
-        log("bench: uneven mixed-resolution batch (256 frames)")
+        log("bench: uneven mixed-resolution batch (256 frames): autotuning its tile shapes")
         ub = synth.uneven_batch(256)
-        ur = run_batched(ub, dev, 15, max(5, min(args.steps, 50)), graph=True, threads=args.threads)
-        u_gbs = ur["bytes"]["step"] / (ur["step_ms"] * 1e-3) / 1e9
-        uf_gbs = ur["bytes"]["forward"] / (ur["fwd_ms"] * 1e-3) / 1e9
-        out["uneven_batch"] = {"value": round(ur["pixels"] / (ur["step_ms"] * 1e-3) / 1e6, 1),
-                               "unit": "megapixels/s", "ms_per_step": round(ur["step_ms"], 3),
-                               "frames": 256, "gigapixels": round(ur["pixels"] / 1e9, 3),
-                               "step_frac_hbm": round(u_gbs / HBM_PEAK_GBS, 4),
-                               "forward_frac_hbm": round(uf_gbs / HBM_PEAK_GBS, 4)}
-        del ur, ub
+        tuned, launch, tinfo = autotune_batch(ub, dev)
         torch.cuda.empty_cache()
+        log("bench: uneven batch, autotuned tiles (%.1f s of tuning) and default tiles" % tinfo["seconds"])
+        u_steps = max(5, min(args.steps, 50))
+        for key, kw in (("uneven_batch", dict(frames=tuned, **launch)),
+                        ("uneven_batch_default_tiles", dict(threads=args.threads))):
+            ur = run_batched(ub, dev, 15, u_steps, graph=True, **kw)
+            u_gbs = ur["bytes"]["step"] / (ur["step_ms"] * 1e-3) / 1e9
+            uf_gbs = ur["bytes"]["forward"] / (ur["fwd_ms"] * 1e-3) / 1e9
+            out[key] = {"value": round(ur["pixels"] / (ur["step_ms"] * 1e-3) / 1e6, 1),
+                        "unit": "megapixels/s", "ms_per_step": round(ur["step_ms"], 3),
+                        "frames": 256, "gigapixels": round(ur["pixels"] / 1e9, 3),
+                        "step_frac_hbm": round(u_gbs / HBM_PEAK_GBS, 4),
+                        "forward_frac_hbm": round(uf_gbs / HBM_PEAK_GBS, 4)}
+            if key == "uneven_batch":
+                out[key]["autotune"] = tinfo
+            del ur
+            torch.cuda.empty_cache()
+        del ub
     if not args.skip_extra:
         log("bench: single 256x256 frame latency")
         out["single_frame"] = run_single_frame(dev)

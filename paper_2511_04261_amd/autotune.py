@@ -6,13 +6,15 @@ fastest.  For each geometry class (layout, H, W, C, b, s_b) it times
 plan + forward on a synthetic batch of that class large enough to fill the GPU,
 for a few tile widths and workgroup sizes and both launch modes, with HIP
 events around steps enqueued back to back, and keeps the fastest.  Winners are cached in a JSON file keyed
-by the device name and the class.
+by the device name and the class.  `tune_whole_batch` instead times whole
+candidate configurations of one given batch.
 """
 from __future__ import annotations
 
 import json
 import os
 import statistics
+import time
 from dataclasses import replace
 from typing import Dict, List, Optional, Sequence, Tuple
 
@@ -68,7 +70,7 @@ def _class_batch(fp: FrameParams, device, min_pixels: float):
 
 
 def time_config(frames: Sequence[FrameParams], imgs, masks, device, threads: int, persistent: int,
-                reps: int = 5, fused: bool = True) -> float:
+                reps: int = 5, fused: bool = True, warm_s: float = 0.015) -> float:
     """GPU ms of one plan + forward for one launch configuration: the median
     of three windows of `reps` steps enqueued back to back through the C ABI
     (no host work between steps inside a window)."""
@@ -86,6 +88,14 @@ def time_config(frames: Sequence[FrameParams], imgs, masks, device, threads: int
     op = None if outs is None else ctypes.c_void_p(plan.pointer_table(outs).data_ptr())
     stream = torch.cuda.current_stream()
     sh = ctypes.c_void_p(stream.cuda_stream)
+    # untimed steps first: after host work the GPU's clocks need some 10 ms
+    # of load to settle, and a configuration timed before that reads slow
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < warm_s:
+        for _ in range(reps):
+            _lib.check(lib.dp_pix_plan(h, mp, st, sh))
+            _lib.check(lib.dp_pix_forward(h, ip, st, None, None, op, sh))
+        torch.cuda.synchronize()
     times = []
     for _ in range(3):
         a = torch.cuda.Event(enable_timing=True)
@@ -103,12 +113,14 @@ def time_config(frames: Sequence[FrameParams], imgs, masks, device, threads: int
 
 class Autotuner:
     def __init__(self, device=None, cache_path: Optional[str] = DEFAULT_CACHE, min_pixels: float = 64e6,
-                 reps: int = 5):
+                 reps: int = 5, threads: Sequence[int] = THREADS, launch_modes: Sequence[int] = LAUNCH_MODES):
         import torch
         self.device = torch.device(device if device is not None else "cuda:0")
         self.cache_path = cache_path
         self.min_pixels = min_pixels
         self.reps = reps
+        self.threads = tuple(threads)
+        self.launch_modes = tuple(launch_modes)
         self.cache: Dict[str, dict] = {}
         if cache_path and os.path.exists(cache_path):
             with open(cache_path) as f:
@@ -124,15 +136,16 @@ class Autotuner:
         os.replace(tmp, self.cache_path)
 
     def tune_class(self, fp: FrameParams) -> dict:
-        key = _device_name(self.device) + "|" + class_key(fp)
+        key = "%s|%s|thr%s|modes%s" % (_device_name(self.device), class_key(fp),
+                                       ",".join(map(str, self.threads)), ",".join(map(str, self.launch_modes)))
         if key in self.cache:
             return self.cache[key]
         n, imgs, masks = _class_batch(fp, self.device, self.min_pixels)
         results: List[Tuple[float, int, int, int]] = []
         for tc in tile_candidates(fp):
             frames = [replace(fp, tile_cells=tc, frame_index=i) for i in range(n)]
-            for th in THREADS:
-                for pers in LAUNCH_MODES:
+            for th in self.threads:
+                for pers in self.launch_modes:
                     ms = time_config(frames, imgs, masks, self.device, th, pers, self.reps)
                     results.append((ms, tc, th, pers))
         results.sort()
@@ -143,6 +156,34 @@ class Autotuner:
         self.cache[key] = best
         self._save()
         return best
+
+    def tune_whole_batch(self, frames: Sequence[FrameParams], imgs, masks,
+                         tile_bytes: Sequence[int] = (0, 1024, 1536, 3072, 4096)) -> Tuple[List[FrameParams], dict]:
+        """Tile shapes for one batch as it will run: every frame's tile row is
+        about `tile_bytes` long (0: the library's choice), for each candidate
+        and workgroup size the whole batch is timed (plan + forward on its own
+        images and masks), and the fastest wins.  Per-class tuning on
+        separate small batches does not see how classes share the GPU in a
+        mixed batch; this does, at the cost of one timing per candidate."""
+        results = []
+        for tb in tile_bytes:
+            if tb == 0:
+                cand = [replace(fp, tile_cells=0) for fp in frames]
+            else:
+                cand = []
+                for fp in frames:
+                    unit = fp.b * fp.channels if fp.layout == U8_HWC else 4 * fp.b
+                    gc = -(-fp.width // fp.b)
+                    cand.append(replace(fp, tile_cells=int(min(gc, max(1, tb // unit)))))
+            for th in self.threads:
+                for pers in self.launch_modes:
+                    ms = time_config(cand, imgs, masks, self.device, th, pers, self.reps)
+                    results.append((ms, tb, th, pers, cand))
+        results.sort(key=lambda r: r[0])
+        ms, tb, th, pers, cand = results[0]
+        info = dict(ms=ms, tile_bytes=tb, threads=th, persistent=pers,
+                    tried=[dict(ms=round(r[0], 4), tile_bytes=r[1], threads=r[2], persistent=r[3]) for r in results])
+        return list(cand), info
 
     def tune_batch(self, frames: Sequence[FrameParams]) -> Tuple[List[FrameParams], dict]:
         """Per-class tile widths for every frame, and one launch shape for the

@@ -88,6 +88,33 @@ def test_autotuned_shapes_are_bitwise_identical(dev, tmp_path):
         assert torch.equal(x, y)
 
 
+def test_whole_batch_autotune_is_bitwise_identical(dev):
+    """tune_whole_batch times candidate tile widths and workgroup sizes on the
+    batch itself; whatever it picks gives the same store and output bit for
+    bit as the library's defaults."""
+    say("case: whole-batch autotune")
+    from paper_2511_04261_amd.autotune import Autotuner
+    specs = synth.region_batch(2, height=300, width=500) + synth.region_batch(2, height=200, width=700, b=16, sb=4)
+    frames = [dp.FrameParams.from_spec(s) for s in specs]
+    imgs = [s.image_torch(dev) for s in specs]
+    masks = [s.mask_torch(dev) for s in specs]
+    tuner = Autotuner(dev, cache_path=None, reps=2, threads=(0, 128), launch_modes=(0, 1))
+    tuned, info = tuner.tune_whole_batch(frames, imgs, masks, tile_bytes=(0, 1024, 4096))
+    assert len(info["tried"]) == 3 * 2 * 2 and abs(info["ms"] - min(t["ms"] for t in info["tried"])) < 1e-4
+    a = dp.Plan(frames, device=dev)
+    b = dp.Plan(tuned, device=dev, threads=info["threads"], persistent=info["persistent"])
+    oa = [torch.empty_like(t) for t in imgs]
+    ob = [torch.empty_like(t) for t in imgs]
+    for p, o in ((a, oa), (b, ob)):
+        p.plan(masks)
+        p.forward(imgs, out=o)
+    torch.cuda.synchronize()
+    for x, y in zip(a.store_host(), b.store_host()):
+        assert _store_equal(x, y)
+    for x, y in zip(oa, ob):
+        assert torch.equal(x, y)
+
+
 def test_uneven_batch_full_size_sampled(dev):
     """256 frames of 768x576 .. 6000x4000, per-frame grids and budgets, one
     graph-replayed launch in the benchmark's configuration (one workgroup per
