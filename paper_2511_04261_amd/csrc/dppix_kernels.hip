@@ -727,6 +727,52 @@ __device__ __forceinline__ void strip_rows_1(const uint8_t* base, uint32_t off, 
     store_colsums16(dst, e, o);
 }
 
+// One padded row of a band's rounded values, expanded in LDS for the row
+// stores: subcell column fc (cell fc / n) covers s_b pixels of C bytes from
+// byte fc * s_b * C.  When that span is whole dwords, the pixel's C-byte
+// pattern is written a dword at a time (for C = 3 it repeats every three
+// dwords): a quarter of the LDS writes of one byte per (pixel, channel), and
+// no two lanes write into the same dword.
+template <int C>
+__device__ __forceinline__ void expand_row_u8(uint8_t* exb, int kn, int n, int s, int fr, const uint8_t* cflag,
+                                              const uint8_t* vgs, const uint8_t* vgc)
+{
+    const int tid = threadIdx.x, NT = blockDim.x;
+    if (((s * C) & 3) == 0) {
+        const int words = (s * C) >> 2;
+        for (int fc = tid; fc < kn; fc += NT) {
+            const int kc = fc / n;
+            const uint8_t* v = cflag[kc] ? vgc + (fr * kn + fc) * C : vgs + kc * C;
+            uint32_t pix = 0;   // the pixel's C bytes, first channel lowest
+#pragma unroll
+            for (int ch = 0; ch < C; ++ch)
+                pix |= (uint32_t)v[ch] << (8 * ch);
+            uint32_t* d = reinterpret_cast<uint32_t*>(exb + fc * s * C);
+            if (C == 3) {
+                const uint32_t d0 = pix | (pix << 24), d1 = (pix >> 8) | (pix << 16), d2 = (pix >> 16) | (pix << 8);
+                for (int k = 0; k < words; k += 3) {
+                    d[k] = d0;
+                    d[k + 1] = d1;
+                    d[k + 2] = d2;
+                }
+            } else {
+                const uint32_t w = C == 1 ? pix * 0x01010101u : (C == 2 ? pix | (pix << 16) : pix);
+                for (int k = 0; k < words; ++k)
+                    d[k] = w;
+            }
+        }
+        return;
+    }
+    for (int j = tid; j < kn * C; j += NT) {
+        const int fc = j / C, ch = j - fc * C;
+        const int kc = fc / n;
+        const uint8_t v = cflag[kc] ? vgc[(fr * kn + fc) * C + ch] : vgs[kc * C + ch];
+        uint8_t* e = exb + fc * s * C + ch;
+        for (int x = 0; x < s; ++x)
+            e[x * C] = v;
+    }
+}
+
 // ==========================================================================
 // Forward, uint8 HWC (Algorithm 3 steps 7-19, fused steps 11, 18-21).
 // ==========================================================================
@@ -924,14 +970,7 @@ __device__ void forward_tile_u8(const TileArgs& a, const FrameRec& F, const Tile
     uint8_t* band_out = out + (int64_t)r * b * pitch + X0;
     for (int fr = 0; fr < n; ++fr) {
         uint8_t* exb = ex + (fr & 1) * (16 * nstr);
-        for (int j = tid; j < items; j += NT) {
-            const int fc = j / C, ch = j - fc * C;
-            const int kc = fc / n;
-            const uint8_t v = cflag[kc] ? vgc[(fr * Kt * n + fc) * C + ch] : vgs[kc * C + ch];
-            uint8_t* e = exb + fc * s * C + ch;
-            for (int x = 0; x < s; ++x)
-                e[x * C] = v;
-        }
+        expand_row_u8<C>(exb, Kt * n, n, s, fr, cflag, vgs, vgc);
         lds_barrier();
         const int row0 = r * b + fr * s;
         const int rows = min(s, H - row0);
@@ -1227,7 +1266,7 @@ __device__ void reconstruct_tile_u8(const TileArgs& a, const FrameRec& F, const 
     tile_cells(a, F, tc.t, r, x0c, Kt, cidx, cflag, false);
     const uint64_t bg_base = a.frame_base[2 * tc.f + 0];
     const uint64_t fg_base = a.frame_base[2 * tc.f + 1];
-    const int nn = n * n, kn = Kt * n, items = Kt * n * C;
+    const int nn = n * n, kn = Kt * n;
     lds_barrier();
     for (int j = tid; j < Kt * C; j += NT) {
         const int kc = j / C, ch = j - kc * C;
@@ -1249,14 +1288,7 @@ __device__ void reconstruct_tile_u8(const TileArgs& a, const FrameRec& F, const 
     uint8_t* band_out = out + (int64_t)r * b * pitch + X0;
     for (int fr = 0; fr < n; ++fr) {
         uint8_t* exb = ex + (fr & 1) * (16 * nstr);   // two alternating row buffers
-        for (int j = tid; j < items; j += NT) {
-            const int fc = j / C, ch = j - fc * C;
-            const int kc = fc / n;
-            const uint8_t v = cflag[kc] ? vgc[(fr * kn + fc) * C + ch] : vgs[kc * C + ch];
-            uint8_t* e = exb + fc * s * C + ch;
-            for (int x = 0; x < s; ++x)
-                e[x * C] = v;
-        }
+        expand_row_u8<C>(exb, kn, n, s, fr, cflag, vgs, vgc);
         lds_barrier();
         const int row0 = r * b + fr * s;
         const int rows = min(s, H - row0);
