@@ -810,6 +810,70 @@ __device__ __forceinline__ void expand_row_u8(uint8_t* exb, int kn, int n, int s
     }
 }
 
+// Phase 2a of the u8 forward for even s_b: one lane per subcell column
+// adds, for every subgrid row of the group, the subcell's s_b * C packed
+// 16-bit column sums (contiguous in LDS: s_b pixels of C channels) read two
+// at a time as dwords, into one sum per channel, and keeps the running sums
+// over subgrid rows in cspart[fc * C + ch].  (Per-(column, channel) lanes
+// would read each 16-bit sum on its own, C lanes into the same dwords.)
+// dbg: optional exact subcell sums, row-major over the fine grid from
+// dbg_base (first subgrid row of the group, first subcell column of the
+// tile), dbg_row fine cells per row.
+template <int C>
+__device__ __forceinline__ void subcell_sums_pairs(const uint16_t* col16, int rowbuf, int kn, int s, int ng, int fr0,
+                                                   uint32_t* cspart, uint32_t* dbg, int64_t dbg_base, int64_t dbg_row)
+{
+    const int tid = threadIdx.x, NT = blockDim.x;
+    const int dw = (s * C) >> 1;   // dwords per (subgrid row, subcell column)
+    for (int fc = tid; fc < kn; fc += NT) {
+        uint32_t tot[C];
+#pragma unroll
+        for (int ch = 0; ch < C; ++ch)
+            tot[ch] = fr0 == 0 ? 0u : cspart[fc * C + ch];
+        for (int g = 0; g < ng; ++g) {
+            const uint32_t* cp = reinterpret_cast<const uint32_t*>(col16 + g * rowbuf + fc * s * C);
+            uint32_t S[C];
+#pragma unroll
+            for (int ch = 0; ch < C; ++ch)
+                S[ch] = 0u;
+            if (C == 3) {
+                // two pixels per three dwords: (c0 c1) (c2 c0) (c1 c2)
+                for (int k = 0; k < dw; k += 3) {
+                    const uint32_t w0 = cp[k], w1 = cp[k + 1], w2 = cp[k + 2];
+                    S[0] += (w0 & 0xFFFFu) + (w1 >> 16);
+                    S[1 % C] += (w0 >> 16) + (w2 & 0xFFFFu);
+                    S[2 % C] += (w1 & 0xFFFFu) + (w2 >> 16);
+                }
+            } else if (C == 1) {
+                for (int k = 0; k < dw; ++k)
+                    S[0] += (cp[k] & 0xFFFFu) + (cp[k] >> 16);
+            } else if (C == 2) {
+                for (int k = 0; k < dw; ++k) {
+                    S[0] += cp[k] & 0xFFFFu;
+                    S[1 % C] += cp[k] >> 16;
+                }
+            } else {
+                // C = 4: one pixel per two dwords, (c0 c1) (c2 c3)
+                for (int k = 0; k < dw; k += 2) {
+                    S[0] += cp[k] & 0xFFFFu;
+                    S[1 % C] += cp[k] >> 16;
+                    S[2 % C] += cp[k + 1] & 0xFFFFu;
+                    S[3 % C] += cp[k + 1] >> 16;
+                }
+            }
+#pragma unroll
+            for (int ch = 0; ch < C; ++ch) {
+                tot[ch] += S[ch];
+                if (dbg)
+                    dbg[(dbg_base + (int64_t)g * dbg_row + fc) * C + ch] = S[ch];
+            }
+        }
+#pragma unroll
+        for (int ch = 0; ch < C; ++ch)
+            cspart[fc * C + ch] = tot[ch];
+    }
+}
+
 // ==========================================================================
 // Forward, uint8 HWC (Algorithm 3 steps 7-19, fused steps 11, 18-21).
 // ==========================================================================
@@ -929,20 +993,26 @@ __device__ void forward_tile_u8(const TileArgs& a, const FrameRec& F, const Tile
         // the row loads above are still in flight
         lds_barrier();
         // running sums of every (subcell column, channel) for the coarse cells
-        for (int j = tid; j < items; j += NT) {
-            const int fc = j / C, ch = j - fc * C;
-            uint32_t total = fr0 == 0 ? 0u : cspart[j];
-            for (int g = 0; g < ng; ++g) {
-                const uint16_t* cp = col16 + g * rowbuf + fc * s * C + ch;
-                uint32_t S = 0;
-                for (int x = 0; x < s; ++x)
-                    S += cp[x * C];
-                total += S;
-                if (a.dbg_fine)
-                    a.dbg_fine[(F.fine_base + (int64_t)(r * n + fr0 + g) * ((int64_t)F.GC * n) + (int64_t)x0c * n +
-                                fc) * C + ch] = S;
+        if ((s & 1) == 0) {
+            subcell_sums_pairs<C>(col16, rowbuf, Kt * n, s, ng, fr0, cspart, a.dbg_fine,
+                                  F.fine_base + (int64_t)(r * n + fr0) * ((int64_t)F.GC * n) + (int64_t)x0c * n,
+                                  (int64_t)F.GC * n);
+        } else {
+            for (int j = tid; j < items; j += NT) {
+                const int fc = j / C, ch = j - fc * C;
+                uint32_t total = fr0 == 0 ? 0u : cspart[j];
+                for (int g = 0; g < ng; ++g) {
+                    const uint16_t* cp = col16 + g * rowbuf + fc * s * C + ch;
+                    uint32_t S = 0;
+                    for (int x = 0; x < s; ++x)
+                        S += cp[x * C];
+                    total += S;
+                    if (a.dbg_fine)
+                        a.dbg_fine[(F.fine_base + (int64_t)(r * n + fr0 + g) * ((int64_t)F.GC * n) +
+                                    (int64_t)x0c * n + fc) * C + ch] = S;
+                }
+                cspart[j] = total;
             }
-            cspart[j] = total;
         }
         // releases of the complex cells' subcells, spread evenly over the
         // lanes (only complex cells draw noise, so a lane-per-subcell loop
