@@ -43,7 +43,7 @@ typedef enum {
     DPPIX_EINVAL = 1,  /* invalid argument; nothing was enqueued            */
     DPPIX_ENOMEM = 2,  /* host allocation failed or workspace too small      */
     DPPIX_EDEVICE = 3, /* HIP runtime / launch error                         */
-    DPPIX_ENOTSUP = 4  /* valid but outside what this build supports         */
+    DPPIX_ENOTSUP = 4  /* valid but not supported by this library          */
 } dppix_status_t;
 
 typedef enum {
