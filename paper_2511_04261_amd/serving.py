@@ -7,8 +7,10 @@ host-to-device copy at once on a copy stream, and launches every admitted,
 copied frame as one batch (one plan, one forward launch) as soon as fewer
 than ``max_inflight`` batches are on the GPU — so frames that arrive while a
 batch runs are copied during it and join the next one.  Each frame keeps its
-own Philox counter (its stream's sequence number), so its result is the same
-alone or in any mix.
+own Philox counter (its stream and its sequence number in it), so its result
+is the same alone or in any mix; streams differ in the counter's high bits,
+so no two frames of any streams share noise (``StreamCounters``, which also
+saves and restores the counters so that resumed streams continue them).
 
 The scheduler is host logic over a small backend interface; ``GpuBackend``
 drives libdppix, and the tests drive the same scheduler with a CPU backend.
@@ -351,10 +353,63 @@ def camera_streams(duration_s: float = 60.0, rate_hz: float = 30.0, seed: int = 
     return out
 
 
+class StreamCounters:
+    """Philox frame counters of camera streams.  Frame k of stream s is
+    drawn with counter words 2-3 = (s << 40) | k under one key (the seed), so
+    no two frames of any streams share a counter: two frames released with
+    the same noise would give away the exact difference of their true cell
+    means.  The state (seed and each stream's next k) can be saved and
+    restored, so a resumed stream continues its counter instead of reusing
+    one."""
+
+    STREAM_SHIFT = 40
+
+    def __init__(self, seed: int, next_index: Optional[Dict[int, int]] = None):
+        self.seed = int(seed)
+        self.next_index: Dict[int, int] = {int(k): int(v) for k, v in (next_index or {}).items()}
+
+    def frame_index(self, stream: int, k: int) -> int:
+        if not (0 <= stream < (1 << (64 - self.STREAM_SHIFT)) and 0 <= k < (1 << self.STREAM_SHIFT)):
+            raise ValueError("stream %d / frame %d outside the counter range" % (stream, k))
+        return (int(stream) << self.STREAM_SHIFT) | int(k)
+
+    def take(self, stream: int) -> int:
+        """The next frame of `stream`: its counter, advancing the stream."""
+        k = self.next_index.get(int(stream), 0)
+        self.next_index[int(stream)] = k + 1
+        return self.frame_index(stream, k)
+
+    def state(self) -> dict:
+        return {"seed": self.seed, "next": {str(s): n for s, n in sorted(self.next_index.items())}}
+
+    @classmethod
+    def from_state(cls, state: dict) -> "StreamCounters":
+        return cls(state["seed"], {int(s): int(n) for s, n in state["next"].items()})
+
+    def save(self, path: str):
+        import json
+        import os
+        tmp = path + ".tmp%d" % os.getpid()
+        with open(tmp, "w") as f:
+            json.dump(self.state(), f)
+        os.replace(tmp, path)
+
+    @classmethod
+    def load(cls, path: str) -> "StreamCounters":
+        import json
+        with open(path) as f:
+            return cls.from_state(json.load(f))
+
+
 def serve_streams(streams, scheduler: Scheduler, params: dict, duration_s: Optional[float] = None,
-                  seed: int = 4, keep_results: bool = False, clock=time.perf_counter):
+                  seed: int = 4, keep_results: bool = False, clock=time.perf_counter,
+                  counters: Optional[StreamCounters] = None):
     """Replay the streams' arrivals in real time through the scheduler.
-    params: b, sb, m, eps_bg, eps_fg, tau.  Returns the finished requests."""
+    params: b, sb, m, eps_bg, eps_fg, tau.  Each frame's Philox counter comes
+    from `counters` (a fresh StreamCounters(seed) by default), which the
+    caller can save to resume the streams later.  Returns the finished
+    requests."""
+    counters = counters if counters is not None else StreamCounters(seed)
     events = []
     for s in streams:
         for k, t in enumerate(s.arrivals):
@@ -369,8 +424,8 @@ def serve_streams(streams, scheduler: Scheduler, params: dict, duration_s: Optio
         while i < len(events) and events[i][0] <= now:
             t, sid, k = events[i]
             s = by_id[sid]
-            r = Request(rid, sid, k, s.height, s.width, 3, params["b"], params["sb"], params["m"],
-                        params["eps_bg"], params["eps_fg"], params["tau"], seed,
+            r = Request(rid, sid, counters.take(sid), s.height, s.width, 3, params["b"], params["sb"], params["m"],
+                        params["eps_bg"], params["eps_fg"], params["tau"], counters.seed,
                         image=s.pool_images[k % len(s.pool_images)], mask=s.pool_masks[k % len(s.pool_masks)],
                         arrival=t0 + t)
             scheduler.offer(r)

@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 from paper_2511_04261_amd import synth
-from paper_2511_04261_amd.serving import MemoryLedger, Request, Scheduler, latency_stats
+from paper_2511_04261_amd.serving import MemoryLedger, Request, Scheduler, StreamCounters, latency_stats
 
 
 class FakeClock:
@@ -68,13 +68,13 @@ class CpuBackend:
 def make_requests(n, streams=3, H=24, W=40, seed=0):
     rng = np.random.Generator(np.random.PCG64(seed))
     reqs = []
-    per = [0] * streams
+    counters = StreamCounters(9)
     for i in range(n):
         s = i % streams
         img = synth.gradient_image(rng, H, W, 3)
         mk = synth.rect_mask(rng, H, W, n_rects=2, rect_frac=0.05, cover=(0.05, 0.3))
-        reqs.append(Request(i, s, per[s], H, W, 3, 8, 4, 4, 1.0, 0.5, 1, 9, image=img, mask=mk, arrival=0.0))
-        per[s] += 1
+        reqs.append(Request(i, s, counters.take(s), H, W, 3, 8, 4, 4, 1.0, 0.5, 1, counters.seed, image=img, mask=mk,
+                            arrival=0.0))
     return reqs
 
 
@@ -169,3 +169,39 @@ def test_latency_stats():
         rs.append(r)
     st = latency_stats(rs)
     assert st["n"] == 100 and abs(st["p50_ms"] - 50.5) < 1e-9 and abs(st["p99_ms"] - 99.01) < 1e-9
+
+
+def test_stream_counters_unique_and_resumable(tmp_path):
+    """Every (stream, frame) gets its own Philox counter; a saved and
+    restored counter state continues each stream where it stopped."""
+    a = StreamCounters(7)
+    seen = [a.take(s) for _ in range(50) for s in (0, 1, 5)]
+    path = str(tmp_path / "counters.json")
+    a.save(path)
+    b = StreamCounters.load(path)
+    assert b.state() == a.state() and b.seed == 7
+    more = [b.take(s) for _ in range(50) for s in (0, 1, 5, 6)]
+    whole = StreamCounters(7)
+    ref = [whole.take(s) for _ in range(50) for s in (0, 1, 5)] + [whole.take(s) for _ in range(50) for s in (0, 1, 5, 6)]
+    assert seen + more == ref
+    assert len(set(seen + more)) == len(seen) + len(more)
+    assert a.frame_index(0, 3) == 3 and a.frame_index(2, 3) == (2 << 40) | 3
+    with pytest.raises(ValueError):
+        a.frame_index(0, 1 << 40)
+    with pytest.raises(ValueError):
+        a.frame_index(1 << 24, 0)
+
+
+def test_identical_frames_of_two_streams_get_independent_noise():
+    """The same image sent as frame 0 of two streams: each release has its
+    own noise (equal noise would give away the difference of true means)."""
+    rng = np.random.Generator(np.random.PCG64(3))
+    img = synth.gradient_image(rng, 32, 48, 3)
+    counters = StreamCounters(11)
+    outs = []
+    for stream in (0, 1):
+        p = oracle.Params(32, 48, 3, b=8, sb=8, m=4, eps_simple=1.0, eps_complex=1.0, seed=counters.seed,
+                          frame_index=counters.take(stream))
+        outs.append(oracle.forward(img, None, p)["bg"])
+    assert outs[0].shape == outs[1].shape
+    assert (outs[0] == outs[1]).mean() < 0.01
