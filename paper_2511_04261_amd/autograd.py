@@ -44,7 +44,13 @@ class DPPixFn(torch.autograd.Function):
 
 
 class DPPixLayer(torch.nn.Module):
-    """Module wrapper: one plan per batch geometry, masks given per call."""
+    """Module wrapper: one plan per batch geometry, masks given per call.
+
+    Image i of every call draws its noise with counter first_frame_index + i
+    under `seed`: the noise is frozen, as training through the layer needs.
+    Outputs meant as privacy releases must not reuse a counter for different
+    images (equal noise gives away the exact difference of their true cell
+    means): give each released batch its own first_frame_index or seed."""
 
     def __init__(self, b: int = 16, sb: Optional[int] = None, m: int = 8, eps_bg: float = 1.0,
                  eps_fg: Optional[float] = None, tau: int = 1, seed: int = 0, first_frame_index: int = 0):
