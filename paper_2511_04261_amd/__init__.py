@@ -380,7 +380,10 @@ def debug_philox(blocks):
 def pixelize(image, mask=None, b: int = 16, sb: Optional[int] = None, m: int = 16, eps_bg: float = 0.5,
              eps_fg: Optional[float] = None, tau: int = 0, seed: int = 0, frame_index: int = 0,
              pad_mode: int = PAD_SYMMETRIC):
-    """One frame, end to end: returns (reconstruction, per-frame store dict on the host)."""
+    """One frame, end to end: returns (reconstruction, per-frame store dict on the host).
+    (seed, frame_index) is the frame's Philox counter: every released frame
+    needs its own, or frames released with equal noise give away the exact
+    difference of their true cell means."""
     torch = _torch()
     if image.dtype == torch.uint8:
         img = image if image.dim() == 3 else image.unsqueeze(-1)
