@@ -19,6 +19,7 @@ from __future__ import annotations
 
 import collections
 import ctypes
+import gc
 import math
 import time
 from dataclasses import dataclass, field
@@ -403,13 +404,34 @@ class StreamCounters:
 
 def serve_streams(streams, scheduler: Scheduler, params: dict, duration_s: Optional[float] = None,
                   seed: int = 4, keep_results: bool = False, clock=time.perf_counter,
-                  counters: Optional[StreamCounters] = None):
+                  counters: Optional[StreamCounters] = None, freeze_gc: bool = True):
     """Replay the streams' arrivals in real time through the scheduler.
     params: b, sb, m, eps_bg, eps_fg, tau.  Each frame's Philox counter comes
     from `counters` (a fresh StreamCounters(seed) by default), which the
     caller can save to resume the streams later.  Returns the finished
-    requests."""
+    requests.
+
+    freeze_gc: a full (generation 2) collection walks every tracked object of
+    the process — several hundred thousand once torch is imported — and
+    stalls the loop for tens of milliseconds, which every frame queued behind
+    it sees as latency.  The loop therefore moves the objects that exist when
+    it starts to the collector's permanent generation (gc.freeze) and
+    releases them when it ends; objects made by the loop are collected as
+    usual.  A caller that has frozen objects itself keeps control: the loop
+    then leaves the collector as it finds it."""
     counters = counters if counters is not None else StreamCounters(seed)
+    own_freeze = freeze_gc and gc.get_freeze_count() == 0
+    if own_freeze:
+        gc.collect()
+        gc.freeze()
+    try:
+        return _serve_loop(streams, scheduler, params, duration_s, keep_results, clock, counters)
+    finally:
+        if own_freeze:
+            gc.unfreeze()
+
+
+def _serve_loop(streams, scheduler, params, duration_s, keep_results, clock, counters):
     events = []
     for s in streams:
         for k, t in enumerate(s.arrivals):

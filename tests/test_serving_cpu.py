@@ -205,3 +205,53 @@ def test_identical_frames_of_two_streams_get_independent_noise():
         outs.append(oracle.forward(img, None, p)["bg"])
     assert outs[0].shape == outs[1].shape
     assert (outs[0] == outs[1]).mean() < 0.01
+
+
+def _tiny_streams(rng, n_streams=2, frames=3, H=24, W=40):
+    from paper_2511_04261_amd.serving import StreamSpec
+    out = []
+    for s in range(n_streams):
+        imgs = [synth.gradient_image(rng, H, W, 3) for _ in range(2)]
+        masks = [synth.rect_mask(rng, H, W, n_rects=2, rect_frac=0.05, cover=(0.05, 0.3)) for _ in range(2)]
+        out.append(StreamSpec(s, H, W, np.arange(frames) * 2e-3, imgs, masks))
+    return out
+
+
+def test_serve_streams_freezes_the_collector_only_for_its_loop():
+    import gc
+
+    from paper_2511_04261_amd.serving import serve_streams
+    rng = np.random.Generator(np.random.PCG64(5))
+    streams = _tiny_streams(rng)
+    params = dict(b=8, sb=4, m=4, eps_bg=1.0, eps_fg=0.5, tau=1)
+    seen = []
+
+    class Probe(CpuBackend):
+        def launch(self, batch):
+            seen.append(gc.get_freeze_count())
+            return super().launch(batch)
+
+    assert gc.get_freeze_count() == 0
+    done = serve_streams(streams, Scheduler(Probe(), MemoryLedger(1 << 20), clock=FakeClock()), params,
+                         keep_results=True, clock=FakeClock())
+    assert gc.get_freeze_count() == 0 and seen and min(seen) > 0
+    assert len(done) == 6 and all(r.error is None for r in done)
+    for r in done:
+        s = streams[r.stream]
+        k = r.frame_index & ((1 << StreamCounters.STREAM_SHIFT) - 1)
+        want = oracle.forward(s.pool_images[k % 2], s.pool_masks[k % 2], CpuBackend.params(r))
+        np.testing.assert_array_equal(r.result["bg"], want["bg"])
+    # a caller that froze objects itself keeps them frozen
+    gc.freeze()
+    try:
+        before = gc.get_freeze_count()
+        serve_streams(_tiny_streams(rng), Scheduler(CpuBackend(), MemoryLedger(1 << 20), clock=FakeClock()), params,
+                      clock=FakeClock())
+        assert gc.get_freeze_count() == before
+    finally:
+        gc.unfreeze()
+    # and the switch turns it off
+    seen.clear()
+    serve_streams(_tiny_streams(rng), Scheduler(Probe(), MemoryLedger(1 << 20), clock=FakeClock()), params,
+                  clock=FakeClock(), freeze_gc=False)
+    assert seen and max(seen) == 0
