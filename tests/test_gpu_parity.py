@@ -290,6 +290,57 @@ def test_backward_mixed_padding_batch(dev):
         plan.close()
 
 
+def _pitched(dev, H, W, C, pitch, fill):
+    """A (H, W, C) uint8 view with rows `pitch` bytes apart into a fresh
+    device buffer of H * pitch bytes, every byte set to `fill`."""
+    buf = torch.full((H * pitch,), fill, dtype=torch.uint8, device=dev)
+    return buf, buf.as_strided((H, W, C), (pitch, C, 1))
+
+
+def test_rows_past_32bit_band_offsets(dev):
+    """Rows so far apart that b + 1 of them span more than 2^31 bytes, and the
+    frame more than 2^32: the kernels then address every row with a 64-bit
+    offset instead of a 32-bit one from the band's first byte.  A 70-row
+    frame with 65 MB between rows (three 4.6 GB buffers), batched with a
+    frame of ordinary pitch, against the oracle on the packed pixels; the
+    fused and the standalone reconstruction leave the bytes between rows
+    untouched."""
+    b, sb = 32, 8
+    P = (-(-(2 ** 31) // (b + 1)) + 15) // 16 * 16
+    H, W, C = 70, 70, 3
+    assert (b + 1) * P >= 2 ** 31 and (H - 1) * P >= 2 ** 32
+    say("case: row pitch", P, "bytes,", H, "x", W, "x", C)
+    r = rng(77)
+    imgs = [r.integers(0, 256, (H, W, C)).astype(np.uint8), r.integers(0, 256, (33, 65, 3)).astype(np.uint8)]
+    masks = [(r.random(x.shape[:2]) < 0.3).astype(np.uint8) for x in imgs]
+    fps = [dp.FrameParams(H, W, C, dp.U8_HWC, b=b, sb=sb, m=4, eps_bg=1.5, eps_fg=0.4, tau=1, seed=11,
+                          frame_index=5, pitch=P),
+           dp.FrameParams(33, 65, 3, dp.U8_HWC, b=b, sb=sb, m=4, eps_bg=1.5, eps_fg=0.4, tau=1, seed=11,
+                          frame_index=6)]
+    ibuf, iv = _pitched(dev, H, W, C, P, 0)
+    iv.copy_(torch.from_numpy(imgs[0]).to(dev))
+    fbuf, fv = _pitched(dev, H, W, C, P, 0xA5)
+    rbuf, rv = _pitched(dev, H, W, C, P, 0xA5)
+    t2 = torch.from_numpy(imgs[1]).to(dev)
+    f2, r2 = torch.empty_like(t2), torch.empty_like(t2)
+    plan = dp.Plan(fps, device=dev)
+    plan.plan([torch.from_numpy(m).to(dev) for m in masks])
+    plan.forward([iv, t2], out=[fv, f2])
+    plan.reconstruct([rv, r2])
+    torch.cuda.synchronize()
+    store = plan.store_host()
+    for i, (fp, fused, recon) in enumerate(zip(fps, [fv, f2], [rv, r2])):
+        want = oracle.forward(imgs[i], masks[i], oracle_params(fp))
+        compare_frame(store[i], want, fused.cpu().numpy(), "fused %d" % i)
+        compare_frame(store[i], want, recon.cpu().numpy(), "recon %d" % i)
+    for buf in (fbuf, rbuf):
+        gap = buf.view(H, P)[:, W * C:]
+        assert int(gap.min()) == 0xA5 and int(gap.max()) == 0xA5
+    plan.close()
+    del ibuf, fbuf, rbuf, iv, fv, rv
+    torch.cuda.empty_cache()
+
+
 def test_laplace_draws_match_oracle_on_many_cells(dev):
     """A constant 1080p RGB frame, b = 2, no mask, a budget that never clips
     (sigma = 1.275, |eta| <= 46): every released value is 128 plus its
