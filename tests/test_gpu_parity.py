@@ -341,6 +341,28 @@ def test_rows_past_32bit_band_offsets(dev):
     torch.cuda.empty_cache()
 
 
+def test_maximum_frame_sides(dev):
+    """Frames at the largest side the library takes (2^24 pixels), one wide
+    and one tall, batched: 8.4 M cells each, 4.2 M bands of one tile in the
+    tall frame (the scan past the single-pass limit), a partial last band or
+    cell, unaligned rows in the tall one; the whole store and both
+    reconstructions against the oracle."""
+    say("case: maximum sides 5 x 2^24 and 2^24 x 5, b = 4, s_b = 2")
+    r = rng(88)
+    shapes = [(5, 1 << 24), (1 << 24, 5)]
+    imgs = [r.integers(0, 256, (H, W, 1)).astype(np.uint8) for H, W in shapes]
+    masks = [(r.random(sh) < 0.3).astype(np.uint8) for sh in shapes]
+    fps = [dp.FrameParams(H, W, 1, dp.U8_HWC, b=4, sb=2, m=4, eps_bg=1.5, eps_fg=0.4, tau=0, seed=11,
+                          frame_index=20 + k) for k, (H, W) in enumerate(shapes)]
+    res = run_gpu(fps, imgs, masks, dev)
+    for k, fp in enumerate(fps):
+        want = oracle.forward(imgs[k], masks[k], oracle_params(fp))
+        assert 0 < want["counts"][1] < want["counts"][0]
+        compare_frame(res["store"][k], want, res["fused"][k], "fused %d" % k)
+        compare_frame(res["store"][k], want, res["recon"][k], "recon %d" % k)
+    res["plan"].close()
+
+
 def test_laplace_draws_match_oracle_on_many_cells(dev):
     """A constant 1080p RGB frame, b = 2, no mask, a budget that never clips
     (sigma = 1.275, |eta| <= 46): every released value is 128 plus its
