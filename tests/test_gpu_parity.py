@@ -137,6 +137,30 @@ def test_noise_off_identity_and_exact_mean(dev):
     assert np.array_equal(res["fused"][0], want["recon_u8"])
 
 
+def test_one_region_without_noise(dev):
+    """eps = inf for one region only (its statistics are the exact means, the
+    other region's draws unchanged), both ways round in one batch."""
+    say("case: one region without noise")
+    r = rng(4)
+    img = r.integers(0, 256, (45, 70, 3)).astype(np.uint8)
+    mask = np.zeros((45, 70), np.uint8)
+    mask[:, :30] = r.random((45, 30)) < 0.6
+    fps = [dp.FrameParams(45, 70, 3, dp.U8_HWC, b=8, sb=4, m=4, eps_bg=math.inf, eps_fg=0.4, seed=3, frame_index=9),
+           dp.FrameParams(45, 70, 3, dp.U8_HWC, b=8, sb=4, m=4, eps_bg=1.5, eps_fg=math.inf, seed=3, frame_index=9)]
+    res = run_gpu(fps, [img, img], [mask, mask], dev)
+    for k, fp in enumerate(fps):
+        want = oracle.forward(img, mask, oracle_params(fp))
+        assert want["counts"][0] > 0 and want["counts"][1] > 0
+        compare_frame(res["store"][k], want, res["fused"][k], "fused %d" % k)
+        compare_frame(res["store"][k], want, res["recon"][k], "recon %d" % k)
+        exact = "bg" if k == 0 else "fg"
+        assert np.array_equal(res["store"][k][exact], want[exact]), exact
+    # the noisy region of each frame is the same draw as with noise everywhere
+    both = dp.FrameParams(45, 70, 3, dp.U8_HWC, b=8, sb=4, m=4, eps_bg=1.5, eps_fg=0.4, seed=3, frame_index=9)
+    full = run_gpu([both], [img], [mask], dev)["store"][0]
+    assert np.array_equal(res["store"][0]["fg"], full["fg"]) and np.array_equal(res["store"][1]["bg"], full["bg"])
+
+
 def test_uneven_batch_matches_frames_alone(dev):
     """Mixed resolutions, grids and budgets in one launch == each frame alone
     (bitwise), and each frame matches the oracle."""
