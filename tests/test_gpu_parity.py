@@ -326,9 +326,9 @@ def test_rows_past_32bit_band_offsets(dev):
     frame more than 2^32: the kernels then address every row with a 64-bit
     offset instead of a 32-bit one from the band's first byte.  A 70-row
     frame with 65 MB between rows (three 4.6 GB buffers), batched with a
-    frame of ordinary pitch, against the oracle on the packed pixels; the
-    fused and the standalone reconstruction leave the bytes between rows
-    untouched."""
+    frame of ordinary pitch, against the oracle on the packed pixels (store,
+    both reconstructions, Sobel labels, MSE / SSIM); the fused and the
+    standalone reconstruction leave the bytes between rows untouched."""
     b, sb = 32, 8
     P = (-(-(2 ** 31) // (b + 1)) + 15) // 16 * 16
     H, W, C = 70, 70, 3
@@ -357,6 +357,13 @@ def test_rows_past_32bit_band_offsets(dev):
         want = oracle.forward(imgs[i], masks[i], oracle_params(fp))
         compare_frame(store[i], want, fused.cpu().numpy(), "fused %d" % i)
         compare_frame(store[i], want, recon.cpu().numpy(), "recon %d" % i)
+    # the Sobel labels and the utility metrics read the same far-apart rows
+    labels = plan.edge_masks([iv, t2], 40)
+    got = plan.metrics([iv, t2], [fv, f2]).cpu().numpy()
+    for i, fused in enumerate([fv, f2]):
+        assert np.array_equal(labels[i].cpu().numpy(), oracle.edge_mask(imgs[i], 40, fps[i].pad_mode)), i
+        mse, ssim = oracle.metrics(imgs[i], fused.cpu().numpy())
+        assert got[i, 0] == pytest.approx(mse, rel=1e-15, abs=0) and abs(got[i, 1] - ssim) <= 1e-9, i
     for buf in (fbuf, rbuf):
         gap = buf.view(H, P)[:, W * C:]
         assert int(gap.min()) == 0xA5 and int(gap.max()) == 0xA5
