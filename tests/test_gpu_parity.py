@@ -279,6 +279,58 @@ def test_backward_matches_oracle_gradient(dev, C, H, W, b, sb, pad):
     assert np.abs(got - want).max() <= 1e-5 * max(1.0, np.abs(want).max())
 
 
+def test_fp32_pitched_rows(dev):
+    """fp32 CHW planes whose rows are longer than the frame (a 16-byte-aligned
+    pitch and an unaligned one) through forward, reconstruction and adjoint
+    in one batch, against the oracle; the floats past each row's end keep
+    their sentinel."""
+    say("case: fp32 pitched rows")
+    r = rng(31)
+    shapes = [(3, 61, 57, 64, 16, 8), (1, 13, 29, 31, 8, 4)]    # C, H, W, pitch, b, s_b
+    fps, xs, ms, gs = [], [], [], []
+    for k, (C, H, W, P, b, sb) in enumerate(shapes):
+        fps.append(dp.FrameParams(H, W, C, dp.F32_CHW, b=b, sb=sb, m=8, eps_bg=1.0, eps_fg=0.5, tau=1, seed=5,
+                                  frame_index=k, pitch=P))
+        xs.append(synth.uniform_f32(r, (C, H, W)))
+        ms.append(synth.rect_mask(r, H, W, n_rects=2, rect_frac=0.1, cover=(0.05, 0.5)))
+        gs.append(r.standard_normal((C, H, W)).astype(np.float32))
+
+    def pitched(k, fill, src=None):
+        C, H, W, P = shapes[k][:4]
+        buf = torch.full((C * H * P,), fill, dtype=torch.float32, device=dev)
+        v = buf.as_strided((C, H, W), (H * P, P, 1))
+        if src is not None:
+            v.copy_(torch.from_numpy(src).to(dev))
+        return buf, v
+
+    tx = [pitched(k, 0.0, xs[k])[1] for k in range(2)]
+    tg = [pitched(k, 0.0, gs[k])[1] for k in range(2)]
+    outs = [pitched(k, -7.0) for k in range(2)]
+    recs = [pitched(k, -7.0) for k in range(2)]
+    gis = [pitched(k, -7.0) for k in range(2)]
+    plan = dp.Plan(fps, device=dev)
+    clip = plan.clip_buffers()
+    plan.plan([torch.from_numpy(m).to(dev) for m in ms])
+    plan.forward(tx, out=[v for _, v in outs], clip=clip)
+    plan.reconstruct([v for _, v in recs])
+    plan.backward(tg, [v for _, v in gis], clip)
+    torch.cuda.synchronize()
+    store = plan.store_host()
+    for k, fp in enumerate(fps):
+        want = oracle.forward(chw_to_hwc(xs[k]), ms[k], oracle_params(fp))
+        compare_frame(store[k], want, chw_to_hwc(outs[k][1].cpu().numpy()), "fused f32 %d" % k)
+        compare_frame(store[k], want, chw_to_hwc(recs[k][1].cpu().numpy()), "recon f32 %d" % k)
+        gw = oracle.backward(chw_to_hwc(xs[k]).astype(np.float64), ms[k], chw_to_hwc(gs[k]).astype(np.float64),
+                             oracle_params(fp))
+        got = chw_to_hwc(gis[k][1].cpu().numpy())
+        assert np.abs(got - gw).max() <= 1e-5 * max(1.0, np.abs(gw).max()), k
+        C, H, W, P = shapes[k][:4]
+        for buf, _ in (outs[k], recs[k], gis[k]):
+            tail = buf.view(C * H, P)[:, W:]
+            assert bool((tail == -7.0).all()), k
+    plan.close()
+
+
 def test_backward_mixed_padding_batch(dev):
     """One adjoint launch over frames with and without padding, both padding
     modes, persistent and one-workgroup-per-tile launches: the mirror pass
