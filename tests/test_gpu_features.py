@@ -300,3 +300,40 @@ def test_scan_many_frames_store_offsets(dev, case):
     for i in sorted(picks):
         want = oracle.forward(imgs[i], masks[i], oracle_params(frames[i]))
         compare_frame(res["store"][i], want, res["fused"][i], "frame %d" % i)
+
+
+def test_two_plans_on_two_streams_overlap(dev):
+    """Two plans issued alternately on two streams, so that their launches
+    can overlap on the device: each plan's workspace (tickets, counters,
+    tables) is its own, and every round's stores and reconstructions equal
+    those of each plan run alone."""
+    say("case: two plans, two streams")
+    runs = []
+    for specs in (synth.region_batch(6, height=270, width=480, seed=3), synth.uneven_batch(12, seed=8)):
+        plan = dp.Plan([dp.FrameParams.from_spec(s) for s in specs], device=dev)
+        imgs = [s.image_torch(dev) for s in specs]
+        masks = [s.mask_torch(dev) for s in specs]
+        runs.append((plan, imgs, masks, [torch.empty_like(t) for t in imgs]))
+    alone = []
+    for plan, imgs, masks, outs in runs:
+        plan.plan(masks)
+        plan.forward(imgs, out=outs)
+        torch.cuda.synchronize()
+        alone.append((plan.store_host(), [o.cpu().numpy() for o in outs]))
+    streams = [torch.cuda.Stream(dev), torch.cuda.Stream(dev)]
+    for rnd in range(4):
+        for _, _, _, outs in runs:
+            for o in outs:
+                o.zero_()
+        torch.cuda.synchronize()
+        for (plan, imgs, masks, outs), st in zip(runs, streams):
+            plan.plan(masks, stream=st)
+        for (plan, imgs, masks, outs), st in zip(runs, streams):
+            plan.forward(imgs, out=outs, stream=st)
+        torch.cuda.synchronize()
+        for (plan, _, _, outs), (store, recon) in zip(runs, alone):
+            got = plan.store_host()
+            assert all(_store_equal(a, b) for a, b in zip(got, store)), rnd
+            assert all(np.array_equal(o.cpu().numpy(), w) for o, w in zip(outs, recon)), rnd
+    for plan, *_ in runs:
+        plan.close()
