@@ -185,6 +185,61 @@ def test_uneven_batch_matches_frames_alone(dev):
         compare_frame(batch["store"][i], want, batch["fused"][i], "frame %d" % i)
 
 
+def _random_frames(r, n):
+    """n frames of random valid geometry: sizes 1-180, b from 1 to 64 with a
+    random divisor as s_b, 1-4 channels, both layouts, every pad mode, the
+    majority rule or a random threshold, masks of random density or none."""
+    bs = [1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 12, 14, 16, 20, 24, 30, 32, 40, 48, 64]
+    frames, imgs, masks = [], [], []
+    for i in range(n):
+        H, W = (int(x) for x in r.integers(1, 181, 2))
+        C = int(r.integers(1, 5))
+        b = int(r.choice(bs))
+        sb = int(r.choice([d for d in range(1, b + 1) if b % d == 0]))
+        layout = dp.F32_CHW if r.random() < 0.3 else dp.U8_HWC
+        tau = 0 if r.random() < 0.4 else int(r.integers(1, b * b + 1))
+        frames.append(dp.FrameParams(H, W, C, layout, b=b, sb=sb, m=int(r.integers(1, 33)),
+                                     eps_bg=float(r.uniform(0.2, 3.0)), eps_fg=float(r.uniform(0.05, 1.0)), tau=tau,
+                                     pad_mode=int(r.integers(0, 3)), seed=int(r.integers(0, 2 ** 63)),
+                                     frame_index=int(r.integers(0, 2 ** 40))))
+        if layout == dp.U8_HWC:
+            imgs.append(r.integers(0, 256, (H, W, C)).astype(np.uint8))
+        else:
+            imgs.append(synth.uniform_f32(r, (C, H, W)))
+        masks.append(None if r.random() < 0.15 else
+                     (r.random((H, W)) < r.uniform(0.0, 1.0)).astype(np.uint8) * r.integers(1, 256, (H, W)).astype(np.uint8))
+    return frames, imgs, masks
+
+
+@pytest.mark.parametrize("seed", [2026, 7, 99])
+def test_random_geometries_one_batch(dev, seed):
+    """40 frames of random valid geometry, grid, budget, layout, pad mode and
+    threshold in one batch: every frame against the oracle, and the resident
+    ticketed launch bitwise equal to one workgroup per tile."""
+    say("case: random geometries, seed", seed)
+    r = rng(seed)
+    frames, imgs, masks = _random_frames(r, 40)
+    for i, fp in enumerate(frames):
+        say("  frame", i, fp.height, fp.width, fp.channels, "layout", fp.layout, "b", fp.b, "sb", fp.sb, "pad",
+            fp.pad_mode, "tau", fp.tau)
+    say("case: random geometries, one workgroup per tile")
+    res = run_gpu(frames, imgs, masks, dev)
+    say("case: random geometries, resident grid")
+    per = run_gpu(frames, imgs, masks, dev, persistent=True)
+    for i, fp in enumerate(frames):
+        f32 = fp.layout == dp.F32_CHW
+        x = chw_to_hwc(imgs[i]) if f32 else imgs[i]
+        want = oracle.forward(x, masks[i], oracle_params(fp))
+        for tag, got in (("fused", res["fused"][i]), ("recon", res["recon"][i])):
+            compare_frame(res["store"][i], want, chw_to_hwc(got) if f32 else got, "frame %d %s" % (i, tag))
+        assert _store_equal(res["store"][i], per["store"][i]), i
+        assert np.array_equal(res["fused"][i], per["fused"][i]) and np.array_equal(res["recon"][i], per["recon"][i])
+
+
+def _store_equal(a, b):
+    return all(np.array_equal(a[k], b[k]) for k in ("flags", "bg", "fg")) and tuple(a["counts"]) == tuple(b["counts"])
+
+
 @pytest.mark.parametrize("threads,persistent,tile", [(64, 0, 1), (128, 1, 3), (256, 0, 0), (512, 1, 7), (192, 1, 0),
                                                      (256, 3, 0), (128, 2, 5)])
 def test_launch_shapes_are_bitwise_identical(dev, threads, persistent, tile):
