@@ -185,7 +185,7 @@ def test_uneven_batch_matches_frames_alone(dev):
         compare_frame(batch["store"][i], want, batch["fused"][i], "frame %d" % i)
 
 
-def _random_frames(r, n):
+def _random_frames(r, n, f32_frac=0.3):
     """n frames of random valid geometry: sizes 1-180, b from 1 to 64 with a
     random divisor as s_b, 1-4 channels, both layouts, every pad mode, the
     majority rule or a random threshold, masks of random density or none."""
@@ -196,7 +196,7 @@ def _random_frames(r, n):
         C = int(r.integers(1, 5))
         b = int(r.choice(bs))
         sb = int(r.choice([d for d in range(1, b + 1) if b % d == 0]))
-        layout = dp.F32_CHW if r.random() < 0.3 else dp.U8_HWC
+        layout = dp.F32_CHW if r.random() < f32_frac else dp.U8_HWC
         tau = 0 if r.random() < 0.4 else int(r.integers(1, b * b + 1))
         frames.append(dp.FrameParams(H, W, C, layout, b=b, sb=sb, m=int(r.integers(1, 33)),
                                      eps_bg=float(r.uniform(0.2, 3.0)), eps_fg=float(r.uniform(0.05, 1.0)), tau=tau,
@@ -234,6 +234,31 @@ def test_random_geometries_one_batch(dev, seed):
             compare_frame(res["store"][i], want, chw_to_hwc(got) if f32 else got, "frame %d %s" % (i, tag))
         assert _store_equal(res["store"][i], per["store"][i]), i
         assert np.array_equal(res["fused"][i], per["fused"][i]) and np.array_equal(res["recon"][i], per["recon"][i])
+
+
+def test_random_geometries_adjoint(dev):
+    """The adjoint over 30 fp32 frames of random geometry in one batch, each
+    frame's gradient against the oracle's."""
+    say("case: random geometries, adjoint")
+    r = rng(515)
+    frames, xs, masks = _random_frames(r, 30, f32_frac=1.0)
+    gs = [r.standard_normal(x.shape).astype(np.float32) for x in xs]
+    plan = dp.Plan(frames, device=dev)
+    tx = [torch.from_numpy(x).to(dev) for x in xs]
+    tm = [None if m is None else torch.from_numpy(m).to(dev) for m in masks]
+    ys = [torch.empty_like(t) for t in tx]
+    gi = [torch.empty_like(t) for t in tx]
+    clip = plan.clip_buffers()
+    plan.plan(tm if any(m is not None for m in tm) else None)
+    plan.forward(tx, out=ys, clip=clip)
+    plan.backward([torch.from_numpy(g).to(dev) for g in gs], gi, clip)
+    torch.cuda.synchronize()
+    for i, fp in enumerate(frames):
+        want = oracle.backward(chw_to_hwc(xs[i]).astype(np.float64), masks[i], chw_to_hwc(gs[i]).astype(np.float64),
+                               oracle_params(fp))
+        got = chw_to_hwc(gi[i].cpu().numpy())
+        assert np.abs(got - want).max() <= 1e-5 * max(1.0, np.abs(want).max()), (i, fp)
+    plan.close()
 
 
 def _store_equal(a, b):
