@@ -83,8 +83,11 @@ class Scheduler:
     """Admission by memory, continuous batching, completion polling."""
 
     def __init__(self, backend, ledger: MemoryLedger, max_batch: int = 64, max_inflight: int = 2,
-                 max_queue: int = 4096, clock=time.perf_counter):
+                 max_queue: int = 4096, clock=time.perf_counter, on_done=None):
+        """on_done(request), if given, runs for every finished request right
+        after its result is set (e.g. to hand the result on and drop it)."""
         self.backend = backend
+        self.on_done = on_done
         self.ledger = ledger
         self.max_batch = max_batch
         self.max_inflight = max_inflight
@@ -134,6 +137,8 @@ class Scheduler:
                 self.ledger.release(r.nbytes)
                 self.backend.release(r)
                 self.finished.append(r)
+                if self.on_done is not None:
+                    self.on_done(r)
                 moved += 1
         # admissions in arrival order; a request that does not fit blocks the
         # ones behind it (no overtaking, so per-stream order holds)
@@ -421,17 +426,27 @@ def serve_streams(streams, scheduler: Scheduler, params: dict, duration_s: Optio
     then leaves the collector as it finds it."""
     counters = counters if counters is not None else StreamCounters(seed)
     own_freeze = freeze_gc and gc.get_freeze_count() == 0
+    # without keep_results a result is dropped as soon as its frame finishes,
+    # so a long replay holds no stores on the host
+    hook = scheduler.on_done
+    if not keep_results:
+        def drop(r, prev=hook):
+            if prev is not None:
+                prev(r)
+            r.result = None
+        scheduler.on_done = drop
     if own_freeze:
         gc.collect()
         gc.freeze()
     try:
-        return _serve_loop(streams, scheduler, params, duration_s, keep_results, clock, counters)
+        return _serve_loop(streams, scheduler, params, duration_s, clock, counters)
     finally:
+        scheduler.on_done = hook
         if own_freeze:
             gc.unfreeze()
 
 
-def _serve_loop(streams, scheduler, params, duration_s, keep_results, clock, counters):
+def _serve_loop(streams, scheduler, params, duration_s, clock, counters):
     events = []
     for s in streams:
         for k, t in enumerate(s.arrivals):
@@ -456,8 +471,4 @@ def _serve_loop(streams, scheduler, params, duration_s, keep_results, clock, cou
         if scheduler.pump() == 0:
             nxt = events[i][0] - (clock() - t0) if i < len(events) else 0.0
             time.sleep(min(max(nxt, 0.0), 2e-4))
-    done = scheduler.finished
-    if not keep_results:
-        for r in done:
-            r.result = None
-    return done
+    return scheduler.finished

@@ -255,3 +255,19 @@ def test_serve_streams_freezes_the_collector_only_for_its_loop():
     serve_streams(_tiny_streams(rng), Scheduler(Probe(), MemoryLedger(1 << 20), clock=FakeClock()), params,
                   clock=FakeClock(), freeze_gc=False)
     assert seen and max(seen) == 0
+
+
+def test_on_done_hook_sees_results_and_replay_drops_them():
+    from paper_2511_04261_amd.serving import serve_streams
+    rng = np.random.Generator(np.random.PCG64(6))
+    params = dict(b=8, sb=4, m=4, eps_bg=1.0, eps_fg=0.5, tau=1)
+    seen = []
+    sch = Scheduler(CpuBackend(), MemoryLedger(1 << 20), clock=FakeClock(),
+                    on_done=lambda r: seen.append((r.rid, r.result is not None)))
+    done = serve_streams(_tiny_streams(rng), sch, params, clock=FakeClock())
+    assert len(seen) == len(done) == 6 and all(has for _, has in seen)
+    assert all(r.result is None and r.done is not None for r in done)
+    assert sch.on_done is not None and sch.on_done.__name__ == "<lambda>"   # the caller's hook is restored
+    kept = serve_streams(_tiny_streams(rng), Scheduler(CpuBackend(), MemoryLedger(1 << 20), clock=FakeClock()), params,
+                         keep_results=True, clock=FakeClock())
+    assert all(r.result is not None for r in kept)
