@@ -28,6 +28,10 @@
 
 #include <math.h>
 
+#include <map>
+#include <mutex>
+#include <utility>
+
 // Register budget of the u8 forward kernel, as resident waves per SIMD: 4
 // leaves 128 VGPRs (no spills with all of a subgrid row's loads in flight).
 #ifndef DPPIX_FWD_WAVES_PER_EU
@@ -1952,14 +1956,30 @@ __global__ void k_philox(const uint32_t* in, uint32_t* out, int64_t n)
 // ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
-// Workgroups asking for more than 64 KiB of LDS must opt in per kernel.
+// Workgroups asking for more than 64 KiB of LDS must opt in per kernel.  The
+// limit belongs to the kernel, not to a plan, so it is only ever raised (per
+// device, under a lock): a smaller request from one host thread must not
+// lower it between another thread's opt-in and its launch.
 template <typename K>
 hipError_t allow_lds(K kernel, size_t lds)
 {
     if (lds <= 65536)
         return hipSuccess;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)lds);
+    static std::mutex mu;
+    static std::map<std::pair<int, const void*>, size_t> granted;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    const void* fn = reinterpret_cast<const void*>(kernel);
+    std::lock_guard<std::mutex> lock(mu);
+    size_t& g = granted[{dev, fn}];
+    if (lds <= g)
+        return hipSuccess;
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e == hipSuccess)
+        g = lds;
+    return e;
 }
 
 hipError_t launch_plan(const TileArgs& a, int64_t n_units, int threads, size_t lds, bool prefix_scan,
