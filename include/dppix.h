@@ -16,14 +16,23 @@
  *    arrays (images, masks, outputs) are passed as DEVICE arrays of n_frames
  *    device pointers, so a captured graph can be replayed on new frames by
  *    refilling the same buffers.  The library never allocates device memory:
- *    its working memory is the caller's workspace (dp_pix_plan_bind).
- *  - Calls are asynchronous on the given HIP stream and never synchronise.
+ *    its working memory is the caller's plan workspace (dp_pix_plan_bind),
+ *    the per-call state of each store (dppix_store_t.state) and the scratch
+ *    arguments of dp_pix_backward / dp_pix_metrics.
+ *  - Calls are asynchronous on the given HIP stream and never synchronise
+ *    (dp_pix_plan_bind, a set-up call, returns once its upload is done).
  *  - Errors: argument errors are found on the host before anything is
  *    enqueued; the call returns DPPIX_EINVAL (or DPPIX_ENOTSUP for valid but
  *    unsupported parameters) and writes nothing.  Launch failures return
  *    DPPIX_EDEVICE.  dp_pix_last_error() gives a per-thread detail string.
- *  - A plan is immutable after dp_pix_plan_create except for the workspace it
- *    is bound to; calls that share a plan must not overlap on the device.
+ *  - A plan is immutable once bound: its workspace holds only the frame and
+ *    tile tables that dp_pix_plan_bind uploads.  Everything a call sequence
+ *    derives from its masks (flags, counts, tile prefixes, ticket words)
+ *    lives in that sequence's store, so one plan serves any number of
+ *    streams and host threads at once, each with its own store and images.
+ *    Calls that share a STORE are ordered by the caller (one stream, or
+ *    events); dp_pix_plan_set_launch must not run concurrently with other
+ *    calls on the plan.
  *  - One code path: a single frame is a batch of one.
  */
 #ifndef DPPIX_H
@@ -114,14 +123,33 @@ typedef struct dppix_plan* dppix_plan_t;
  *           floats each (mu'_{G_s}, clipped)
  *   counts  per frame 4 x uint64: n_bg cells, n_fg cells, offset of the
  *           frame's first float in bg, offset of its first float in fg
+ *           (8-byte aligned)
+ *   state   store_state_bytes of device memory, 256-byte aligned: the store's
+ *           index (complex cells per work tile and before each tile, derived
+ *           from the flags) and the ticket words of its call sequence.
+ *           dp_pix_plan writes it (dp_pix_store_index rebuilds it from the
+ *           flags of a store written elsewhere); its initial contents do
+ *           not matter.
+ *   noise   optional INPUT of dp_pix_forward / dp_pix_debug_sums: device
+ *           array of n_frames x 2 uint64, (seed, frame_index) of each
+ *           frame's Philox draws, read when the kernels run; NULL uses the
+ *           descriptors' seed and frame_index.  One plan then serves every
+ *           step of a video: a replayed graph draws fresh noise once the
+ *           counters are advanced (dp_pix_noise_advance).  The seed is the
+ *           generator's key and must stay secret: whoever knows it can
+ *           regenerate the noise and subtract it.
  * Capacities (worst case: every cell simple, resp. complex) come from
- * dp_pix_plan_sizes; actual counts stay on the device.
+ * dp_pix_plan_sizes; actual counts stay on the device.  forward, reconstruct
+ * and backward read the cell classes and offsets from the store they are
+ * given and nothing else, so any number of stores of one plan can be in use.
  */
 typedef struct {
     float* bg;
     float* fg;
     uint8_t* flags;
     uint64_t* counts;
+    void* state;
+    const uint64_t* noise;
 } dppix_store_t;
 
 typedef struct {
@@ -135,6 +163,7 @@ typedef struct {
     int64_t n_tiles;         /* work tiles of the batch                         */
     int64_t total_pixels;    /* sum of height*width                             */
     size_t metrics_scratch_bytes; /* device scratch for dp_pix_metrics          */
+    size_t store_state_bytes; /* dppix_store_t.state of each store              */
 } dppix_sizes_t;
 
 typedef struct {
@@ -159,23 +188,38 @@ dppix_status_t dp_pix_plan_create(const dppix_frame_desc_t* descs, int32_t n_fra
 void dp_pix_plan_destroy(dppix_plan_t plan);
 
 dppix_status_t dp_pix_plan_sizes(dppix_plan_t plan, dppix_sizes_t* out);
+
+/* The sizes of dp_pix_plan_sizes for n_frames descriptors, without keeping a
+ * plan: host only, for sizing buffers before anything is allocated.  Returns
+ * the status dp_pix_plan_create would return for these descriptors. */
+dppix_status_t dp_pix_plan_workspace_size(const dppix_frame_desc_t* descs, int32_t n_frames, dppix_sizes_t* out);
 dppix_status_t dp_pix_plan_frame_info(dppix_plan_t plan, int32_t frame, dppix_frame_info_t* out);
 
 /* Bind a device workspace of at least workspace_bytes (256-byte aligned) and
- * upload the plan's frame and tile tables into it (one async host-to-device
- * copy on the stream; the host source lives inside the plan). */
+ * upload the plan's frame and tile tables into it: one host-to-device copy on
+ * the stream, waited for before returning, so the plan may be used from any
+ * stream afterwards.  A plan is bound once (EINVAL on a second bind); not
+ * for use under stream capture. */
 dppix_status_t dp_pix_plan_bind(dppix_plan_t plan, void* workspace, size_t bytes, dppix_stream_t stream);
 
 /* Classify every grid cell and lay out the compact store (Algorithm 3 steps
  * 3-6): count nonzero mask pixels of each mirror-padded b x b cell, flag it
  * complex when the count reaches tau, then scan the flags into store offsets
- * and per-frame counts (written to store->counts and store->flags).
+ * and per-frame counts (written to store->flags, store->counts and
+ * store->state; bg and fg are not touched and may be NULL).
  *   masks   device array of n_frames device pointers to uint8 masks of
  *           height x width bytes, rows width bytes apart; NULL, or a NULL
  *           entry, makes every cell of that frame simple (Algorithm 2).
  * Kernels only: safe under stream capture. */
 dppix_status_t dp_pix_plan(dppix_plan_t plan, const uint8_t* const* masks, const dppix_store_t* store,
                            dppix_stream_t stream);
+
+/* Rebuild a store's counts and state from its flags alone (Table IV: the
+ * flags are the grid layout), for a store whose flags and statistics were
+ * written elsewhere, e.g. decoded from its serialised form: frames are
+ * packed back to back in batch order, as dp_pix_plan lays them out.  Flag
+ * bytes are read as complex when nonzero.  bg and fg are not touched. */
+dppix_status_t dp_pix_store_index(dppix_plan_t plan, const dppix_store_t* store, dppix_stream_t stream);
 
 /* Region mask from the frames themselves (Sec. VI-A: the mask may come from an
  * edge detector such as the Sobel operator): for every real pixel, the 3x3
@@ -214,7 +258,10 @@ dppix_status_t dp_pix_metrics(dppix_plan_t plan, const void* const* images, cons
  *   clip_bg/fg optional (may be NULL): one byte per stored float, 1 when the
  *              noisy mean was inside [0, 255] (its gradient passes)
  *   fused_out  optional device array of n_frames output pointers: also write
- *              the reconstruction (steps 11, 18-21) in the same pass
+ *              the reconstruction (steps 11, 18-21) in the same pass.  An
+ *              output must not overlap its image: with mirror padding a
+ *              tile reads rows and columns that neighbouring tiles of the
+ *              same launch write, so an in-place forward races.
  * ------------------------------------------------------------------------- */
 dppix_status_t dp_pix_forward(dppix_plan_t plan, const void* const* images, const dppix_store_t* store,
                               uint8_t* clip_bg, uint8_t* clip_fg, void* const* fused_out,
@@ -222,7 +269,9 @@ dppix_status_t dp_pix_forward(dppix_plan_t plan, const void* const* images, cons
 
 /* Restoration from the stored metadata (Sec. VI-F): every real pixel takes the
  * value of its cell or subcell; U8_HWC output is rounded half-to-even, F32_CHW
- * output is the stored value.  out: device array of n_frames pointers. */
+ * output is the stored value.  Reads the given store only (flags, counts,
+ * state and statistics): a store keeps its own layout whatever other stores
+ * of the plan were planned since.  out: device array of n_frames pointers. */
 dppix_status_t dp_pix_reconstruct(dppix_plan_t plan, const dppix_store_t* store, void* const* out,
                                   dppix_stream_t stream);
 
@@ -231,7 +280,8 @@ dppix_status_t dp_pix_reconstruct(dppix_plan_t plan, const dppix_store_t* store,
  *   grad_in(p) = sum over padded positions x folding onto p of
  *                pass_k(x) * G_k(x) / area_k(x),
  * where k(x) is the statistic covering x and G_k sums grad_out over the real
- * pixels of k.  clip_bg/clip_fg are the bits written by dp_pix_forward;
+ * pixels of k.  store is the one the matching dp_pix_forward wrote (its cell
+ * classes and offsets); clip_bg/clip_fg are the bits that forward wrote;
  * scratch holds grad_scratch_bytes of device memory. */
 dppix_status_t dp_pix_backward(dppix_plan_t plan, const dppix_store_t* store, const float* const* grad_out,
                                const uint8_t* clip_bg, const uint8_t* clip_fg, float* const* grad_in,
@@ -270,6 +320,13 @@ void dp_pix_graph_destroy(dppix_graph_t graph);
  * uint8 frames only. */
 dppix_status_t dp_pix_debug_sums(dppix_plan_t plan, const void* const* images, const dppix_store_t* store,
                                  uint32_t* coarse, uint32_t* fine, dppix_stream_t stream);
+
+/* Add step to the frame_index of each of n_frames (seed, frame_index) pairs
+ * of a store's noise array (8-byte aligned device memory), on the stream:
+ * the next release of the same frames draws fresh noise (a frame_index must
+ * never repeat under one seed).  A kernel, so it can be captured with the
+ * calls it precedes or follows. */
+dppix_status_t dp_pix_noise_advance(uint64_t* noise, int32_t n_frames, uint64_t step, dppix_stream_t stream);
 
 /* Raw Philox4x32-10 blocks: for i < n, words[4i..4i+3] = Philox(ctr = in[6i..6i+3], key = in[6i+4..6i+5]). */
 dppix_status_t dp_pix_debug_philox(const uint32_t* in, uint32_t* words, int64_t n, dppix_stream_t stream);

@@ -34,7 +34,7 @@ class FrameDesc(ctypes.Structure):
 
 class Store(ctypes.Structure):
     _fields_ = [("bg", ctypes.c_void_p), ("fg", ctypes.c_void_p), ("flags", ctypes.c_void_p),
-                ("counts", ctypes.c_void_p)]
+                ("counts", ctypes.c_void_p), ("state", ctypes.c_void_p), ("noise", ctypes.c_void_p)]
 
 
 class Sizes(ctypes.Structure):
@@ -42,7 +42,8 @@ class Sizes(ctypes.Structure):
                 ("fg_capacity", ctypes.c_size_t), ("flag_bytes", ctypes.c_size_t),
                 ("clip_bytes_bg", ctypes.c_size_t), ("clip_bytes_fg", ctypes.c_size_t),
                 ("grad_scratch_bytes", ctypes.c_size_t), ("n_tiles", ctypes.c_int64),
-                ("total_pixels", ctypes.c_int64), ("metrics_scratch_bytes", ctypes.c_size_t)]
+                ("total_pixels", ctypes.c_int64), ("metrics_scratch_bytes", ctypes.c_size_t),
+                ("store_state_bytes", ctypes.c_size_t)]
 
 
 class FrameInfo(ctypes.Structure):
@@ -61,9 +62,12 @@ SYMBOLS = {
     "dp_pix_plan_create": (_st, [_P(FrameDesc), ctypes.c_int32, _P(_vp)]),
     "dp_pix_plan_destroy": (None, [_vp]),
     "dp_pix_plan_sizes": (_st, [_vp, _P(Sizes)]),
+    "dp_pix_plan_workspace_size": (_st, [_P(FrameDesc), ctypes.c_int32, _P(Sizes)]),
     "dp_pix_plan_frame_info": (_st, [_vp, ctypes.c_int32, _P(FrameInfo)]),
     "dp_pix_plan_bind": (_st, [_vp, _vp, ctypes.c_size_t, _vp]),
     "dp_pix_plan": (_st, [_vp, _vp, _P(Store), _vp]),
+    "dp_pix_store_index": (_st, [_vp, _P(Store), _vp]),
+    "dp_pix_noise_advance": (_st, [_vp, ctypes.c_int32, ctypes.c_uint64, _vp]),
     "dp_pix_edge_mask": (_st, [_vp, _vp, ctypes.c_int32, _vp, _vp]),
     "dp_pix_forward": (_st, [_vp, _vp, _P(Store), _vp, _vp, _vp, _vp]),
     "dp_pix_reconstruct": (_st, [_vp, _P(Store), _vp, _vp]),

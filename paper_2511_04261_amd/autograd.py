@@ -16,7 +16,13 @@ from . import F32_CHW, FrameParams, Plan
 
 
 class DPPixFn(torch.autograd.Function):
-    """y = pixelize(x) for a batch x of shape (B, C, H, W), float32, on the GPU."""
+    """y = pixelize(x) for a batch x of shape (B, C, H, W), float32, on the GPU.
+
+    Every call plans into a store of its own, which its backward reads: the
+    adjoint goes through the cell classes and store offsets of the forward it
+    belongs to, however many other forwards of the same plan (other masks)
+    ran in between — gradient accumulation, two-branch losses, recomputation.
+    """
 
     @staticmethod
     def forward(ctx, x: torch.Tensor, plan: Plan, masks: Optional[Sequence[torch.Tensor]] = None):
@@ -27,9 +33,11 @@ class DPPixFn(torch.autograd.Function):
         y = torch.empty_like(x)
         outs = [y[i] for i in range(x.shape[0])]
         clip = plan.clip_buffers()
-        plan.plan(masks)
-        plan.forward(frames, out=outs, clip=clip)
+        store = plan.new_store()
+        plan.plan(masks, store=store)
+        plan.forward(frames, out=outs, clip=clip, store=store)
         ctx.plan = plan
+        ctx.store = store
         ctx.save_for_backward(clip[0], clip[1])
         return y
 
@@ -39,7 +47,7 @@ class DPPixFn(torch.autograd.Function):
         gy = gy.contiguous()
         gx = torch.empty_like(gy)
         ctx.plan.backward([gy[i] for i in range(gy.shape[0])], [gx[i] for i in range(gx.shape[0])],
-                          (clip_bg, clip_fg))
+                          (clip_bg, clip_fg), store=ctx.store)
         return gx, None, None
 
 

@@ -81,7 +81,7 @@ def time_config(frames: Sequence[FrameParams], imgs, masks, device, threads: int
     outs = [torch.empty_like(t) for t in imgs] if fused else None
     plan.plan(masks)
     plan.forward(imgs, out=outs)      # checks shapes once, builds the pointer tables
-    lib, h, st = plan.lib, plan.handle, ctypes.byref(plan.store)
+    lib, h, st = plan.lib, plan.handle, ctypes.byref(plan.store.c)
     ip = ctypes.c_void_p(plan.pointer_table(imgs).data_ptr())
     mt = plan.pointer_table(masks)
     mp = None if mt is None else ctypes.c_void_p(mt.data_ptr())

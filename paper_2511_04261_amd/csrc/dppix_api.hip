@@ -65,15 +65,16 @@ struct dppix_plan {
     int64_t total_pixels = 0;
     size_t bg_cap = 0, fg_cap = 0;
     WsLayout ws{};
+    StateLayout st{};
     size_t lds[6] = {0, 0, 0, 0, 0, 0};
     std::vector<LaunchGroup> groups;
     bool any_f32 = false, any_u8 = false;
     int threads = 0;                    // 0: per launch group (forward, reconstruct), else fixed
     int persistent = 0;
-    int cus = 0;                        // compute units of the device (queried once)
+    int cus = 0;                        // compute units of the bound device
     uint8_t* bound = nullptr;
     size_t bound_bytes = 0;
-    std::vector<uint8_t> host_tables;   // frames + sched tables as uploaded
+    std::vector<uint8_t> host_tables;   // frame records and scheduling maps, as uploaded
 };
 
 struct dppix_graph {
@@ -384,17 +385,18 @@ dppix_status_t dp_pix_plan_create(const dppix_frame_desc_t* descs, int32_t n_fra
     }
     p->n_border = (int64_t)border.size() / 2;
     w.border_map = o;  o = align256(o + sizeof(int32_t) * border.size());
-    w.flags = o;       o = align256(o + (size_t)p->total_cells);
-    w.tile_cnt = o;    o = align256(o + sizeof(uint32_t) * (size_t)p->n_tiles);
-    w.tile_fg = o;     o = align256(o + sizeof(uint32_t) * (size_t)p->n_tiles);
-    w.frame_tot = o;   o = align256(o + sizeof(uint64_t) * 2 * n_frames);
-    w.frame_base = o;  o = align256(o + sizeof(uint64_t) * 2 * n_frames);
-    w.counters = o;    o = align256(o + sizeof(uint32_t) * kTicketWords);
     w.total = o;
+    // Per-call state carried by each store.
+    StateLayout& sl = p->st;
+    o = 0;
+    sl.tile_cnt = o;   o = align256(o + sizeof(uint32_t) * (size_t)p->n_tiles);
+    sl.tile_fg = o;    o = align256(o + sizeof(uint32_t) * (size_t)p->n_tiles);
+    sl.counters = o;   o = align256(o + sizeof(uint32_t) * kTicketWords);
+    sl.total = o;
 
-    // Host image of the static tables: frame records, and per scheduling index
-    // the frame and the tile within it.
-    p->host_tables.assign(w.flags, 0);
+    // Host image of the tables: frame records, and per scheduling index the
+    // frame and the tile within it.
+    p->host_tables.assign(w.total, 0);
     std::memcpy(p->host_tables.data() + w.frames, p->frames.data(), sizeof(FrameRec) * n_frames);
     int32_t* map = reinterpret_cast<int32_t*>(p->host_tables.data() + w.tile_map);
     for (int32_t k = 0; k < n_frames; ++k)
@@ -421,6 +423,7 @@ dppix_status_t dp_pix_plan_sizes(dppix_plan_t p, dppix_sizes_t* out)
     if (p == nullptr || out == nullptr)
         return fail(DPPIX_EINVAL, "NULL plan or output");
     out->workspace_bytes = p->ws.total;
+    out->store_state_bytes = p->st.total;
     out->bg_capacity = p->bg_cap;
     out->fg_capacity = p->fg_cap;
     out->flag_bytes = (size_t)p->total_cells;
@@ -473,29 +476,52 @@ dppix_status_t dp_pix_plan_bind(dppix_plan_t p, void* ws, size_t bytes, dppix_st
 {
     if (p == nullptr || ws == nullptr)
         return fail(DPPIX_EINVAL, "NULL plan or workspace");
+    if (p->bound != nullptr)
+        return fail(DPPIX_EINVAL, "plan is already bound (its tables are immutable once uploaded)");
     if (bytes < p->ws.total)
         return fail(DPPIX_ENOMEM, "workspace smaller than workspace_bytes");
     if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0)
         return fail(DPPIX_EINVAL, "workspace must be 256-byte aligned");
-    hipError_t e = hipMemcpyAsync(ws, p->host_tables.data(), p->host_tables.size(), hipMemcpyHostToDevice,
-                                  reinterpret_cast<hipStream_t>(stream));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(ws, p->host_tables.data(), p->host_tables.size(), hipMemcpyHostToDevice, s);
     if (e != hipSuccess)
         return dev_fail(e, "uploading plan tables");
-    // tickets start at zero; the scan kernel clears them again on every plan
-    e = hipMemsetAsync(static_cast<uint8_t*>(ws) + p->ws.counters, 0, sizeof(uint32_t) * kTicketWords,
-                       reinterpret_cast<hipStream_t>(stream));
+    // the tables are on the device when bind returns, so calls on any stream
+    // may use the plan from then on
+    e = hipStreamSynchronize(s);
     if (e != hipSuccess)
-        return dev_fail(e, "clearing tickets");
+        return dev_fail(e, "uploading plan tables");
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+        p->cus = n;
+    else
+        p->cus = 256;
     p->bound = static_cast<uint8_t*>(ws);
     p->bound_bytes = bytes;
     return DPPIX_OK;
+}
+
+dppix_status_t dp_pix_plan_workspace_size(const dppix_frame_desc_t* descs, int32_t n_frames, dppix_sizes_t* out)
+{
+    if (out == nullptr)
+        return fail(DPPIX_EINVAL, "out is NULL");
+    dppix_plan_t p = nullptr;
+    dppix_status_t st = dp_pix_plan_create(descs, n_frames, &p);
+    if (st != DPPIX_OK)
+        return st;
+    st = dp_pix_plan_sizes(p, out);
+    dp_pix_plan_destroy(p);
+    return st;
 }
 
 }  // extern "C"
 
 namespace {
 
-TileArgs base_args(dppix_plan_t p)
+// Kernel arguments of one call: the plan's tables, and the per-call state
+// (flags, counts, tile counts and prefixes, tickets) of the call's store.
+TileArgs base_args(dppix_plan_t p, const dppix_store_t* store)
 {
     TileArgs a;
     std::memset(&a, 0, sizeof a);
@@ -505,13 +531,18 @@ TileArgs base_args(dppix_plan_t p)
     a.n_frames = (int32_t)p->frames.size();
     a.n_tiles = p->n_tiles;
     a.unit_map = reinterpret_cast<const int32_t*>(w + p->ws.unit_map);
-    a.ticket = reinterpret_cast<uint32_t*>(w + p->ws.counters);
     a.persistent = p->persistent;
-    a.flags = w + p->ws.flags;
-    a.tile_cnt = reinterpret_cast<uint32_t*>(w + p->ws.tile_cnt);
-    a.tile_fg = reinterpret_cast<uint32_t*>(w + p->ws.tile_fg);
-    a.frame_base = reinterpret_cast<const uint64_t*>(w + p->ws.frame_base);
-    a.frame_tot = reinterpret_cast<uint64_t*>(w + p->ws.frame_tot);
+    if (store != nullptr) {
+        uint8_t* st = static_cast<uint8_t*>(store->state);
+        a.flags = store->flags;
+        a.counts = store->counts;
+        a.bg = store->bg;
+        a.fg = store->fg;
+        a.tile_cnt = reinterpret_cast<uint32_t*>(st + p->st.tile_cnt);
+        a.tile_fg = reinterpret_cast<uint32_t*>(st + p->st.tile_fg);
+        a.ticket = reinterpret_cast<uint32_t*>(st + p->st.counters);
+        a.noise = store->noise;
+    }
     return a;
 }
 
@@ -524,10 +555,20 @@ dppix_status_t need_bound(dppix_plan_t p)
     return DPPIX_OK;
 }
 
+// Every call that takes a store needs its layout (flags, counts) and its
+// per-call state; need_stats: also the statistics arrays.
 dppix_status_t check_store(const dppix_store_t* s, bool need_stats)
 {
     if (s == nullptr)
         return fail(DPPIX_EINVAL, "NULL store");
+    if (s->flags == nullptr || s->counts == nullptr || s->state == nullptr)
+        return fail(DPPIX_EINVAL, "store flags, counts and state are required");
+    if ((reinterpret_cast<uintptr_t>(s->state) & 255) != 0)
+        return fail(DPPIX_EINVAL, "store state must be 256-byte aligned");
+    if ((reinterpret_cast<uintptr_t>(s->counts) & 7) != 0)
+        return fail(DPPIX_EINVAL, "store counts must be 8-byte aligned");
+    if ((reinterpret_cast<uintptr_t>(s->noise) & 7) != 0)
+        return fail(DPPIX_EINVAL, "store noise counters must be 8-byte aligned");
     if (need_stats && (s->bg == nullptr || s->fg == nullptr))
         return fail(DPPIX_EINVAL, "store bg/fg are NULL");
     return DPPIX_OK;
@@ -543,15 +584,7 @@ int grid_for(dppix_plan_t p, int layout, int C, int threads, int64_t tiles, size
 {
     if (!p->persistent)
         return (int)tiles;
-    if (p->cus == 0) {
-        int dev = 0, n = 0;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
-            p->cus = n;
-        else
-            p->cus = 256;
-    }
-    const int cus = p->cus;
+    const int cus = p->cus > 0 ? p->cus : 256;
     int per_cu = p->persistent;
     if (per_cu == 1 && (occupancy_forward(layout, C, threads, lds, &per_cu) != hipSuccess || per_cu < 1))
         per_cu = 1;
@@ -587,13 +620,28 @@ dppix_status_t dp_pix_plan(dppix_plan_t p, const uint8_t* const* masks, const dp
     dppix_status_t st = need_bound(p);
     if (st != DPPIX_OK)
         return st;
-    TileArgs a = base_args(p);
+    if ((st = check_store(store, false)) != DPPIX_OK)
+        return st;
+    TileArgs a = base_args(p, store);
     a.masks = masks;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    hipError_t e = launch_plan(a, p->n_units, plain_threads(p), p->lds[kPlan], p->prefix_scan,
-                               store ? store->counts : nullptr, s);
+    hipError_t e = launch_plan(a, p->n_units, plain_threads(p), p->lds[kPlan], p->prefix_scan, s);
     if (e != hipSuccess)
         return dev_fail(e, "plan launch");
+    return DPPIX_OK;
+}
+
+dppix_status_t dp_pix_store_index(dppix_plan_t p, const dppix_store_t* store, dppix_stream_t stream)
+{
+    dppix_status_t st = need_bound(p);
+    if (st != DPPIX_OK)
+        return st;
+    if ((st = check_store(store, false)) != DPPIX_OK)
+        return st;
+    TileArgs a = base_args(p, store);
+    hipError_t e = launch_store_index(a, p->prefix_scan, reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return dev_fail(e, "store index launch");
     return DPPIX_OK;
 }
 
@@ -609,12 +657,9 @@ dppix_status_t dp_pix_forward(dppix_plan_t p, const void* const* images, const d
         return st;
     if ((clip_bg == nullptr) != (clip_fg == nullptr))
         return fail(DPPIX_EINVAL, "clip_bg and clip_fg must both be given or both be NULL");
-    TileArgs a = base_args(p);
+    TileArgs a = base_args(p, store);
     a.images = images;
     a.outs = fused_out;
-    a.bg = store->bg;
-    a.fg = store->fg;
-    a.store_flags = store->flags;
     a.clip_bg = clip_bg;
     a.clip_fg = clip_fg;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -635,10 +680,8 @@ dppix_status_t dp_pix_reconstruct(dppix_plan_t p, const dppix_store_t* store, vo
         return fail(DPPIX_EINVAL, "out is NULL");
     if ((st = check_store(store, true)) != DPPIX_OK)
         return st;
-    TileArgs a = base_args(p);
+    TileArgs a = base_args(p, store);
     a.outs = out;
-    a.bg = store->bg;
-    a.fg = store->fg;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     hipError_t e = for_groups(p, a, true, [&](const TileArgs& ga, const LaunchGroup& g, size_t lds, int grid) {
         return launch_reconstruct(ga, g.layout, g.C, group_threads(p, g), lds, grid, s);
@@ -659,13 +702,13 @@ dppix_status_t dp_pix_backward(dppix_plan_t p, const dppix_store_t* store, const
         return fail(DPPIX_EINVAL, "backward needs every frame in F32_CHW layout");
     if (grad_out == nullptr || grad_in == nullptr || clip_bg == nullptr || clip_fg == nullptr)
         return fail(DPPIX_EINVAL, "grad_out, grad_in and clip bits are required");
-    if ((st = check_store(store, false)) != DPPIX_OK)
+    if ((st = check_store(store, true)) != DPPIX_OK)
         return st;
     const size_t need = align256(4 * p->bg_cap) + align256(4 * p->fg_cap) + align256(4 * (size_t)p->total_cells);
     if (scratch == nullptr || scratch_bytes < need)
         return fail(DPPIX_ENOMEM, "scratch smaller than grad_scratch_bytes");
     uint8_t* sc = static_cast<uint8_t*>(scratch);
-    TileArgs a = base_args(p);
+    TileArgs a = base_args(p, store);
     a.grad_out = grad_out;
     a.grad_in = grad_in;
     a.clip_bg = const_cast<uint8_t*>(clip_bg);
@@ -706,11 +749,8 @@ dppix_status_t dp_pix_debug_sums(dppix_plan_t p, const void* const* images, cons
         return fail(DPPIX_EINVAL, "images, coarse and fine are required");
     if ((st = check_store(store, true)) != DPPIX_OK)
         return st;
-    TileArgs a = base_args(p);
+    TileArgs a = base_args(p, store);
     a.images = images;
-    a.bg = store->bg;
-    a.fg = store->fg;
-    a.store_flags = store->flags;
     a.dbg_coarse = coarse;
     a.dbg_fine = fine;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -734,7 +774,7 @@ dppix_status_t dp_pix_edge_mask(dppix_plan_t p, const void* const* images, int32
         return fail(DPPIX_EINVAL, "images and masks_out are required");
     if (threshold < 0 || threshold > 4 * 1024)
         return fail(DPPIX_EINVAL, "threshold must be in 0..4096");
-    TileArgs a = base_args(p);
+    TileArgs a = base_args(p, nullptr);
     a.images = images;
     a.masks_out = masks_out;
     a.edge_threshold = threshold;
@@ -762,7 +802,7 @@ dppix_status_t dp_pix_metrics(dppix_plan_t p, const void* const* images, const v
         return fail(DPPIX_EINVAL, "images, recons and out are required");
     if (scratch == nullptr || scratch_bytes < (size_t)(16 * p->n_tiles))
         return fail(DPPIX_ENOMEM, "scratch smaller than metrics_scratch_bytes");
-    TileArgs a = base_args(p);
+    TileArgs a = base_args(p, nullptr);
     a.images = images;
     a.outs = const_cast<void* const*>(recons);
     a.met_partial = static_cast<double*>(scratch);
@@ -778,6 +818,18 @@ dppix_status_t dp_pix_metrics(dppix_plan_t p, const void* const* images, const v
     hipError_t e = launch_metrics_reduce(a, out, s);
     if (e != hipSuccess)
         return dev_fail(e, "metrics reduce launch");
+    return DPPIX_OK;
+}
+
+dppix_status_t dp_pix_noise_advance(uint64_t* noise, int32_t n_frames, uint64_t step, dppix_stream_t stream)
+{
+    if (n_frames < 0 || (n_frames > 0 && noise == nullptr))
+        return fail(DPPIX_EINVAL, "noise must hold n_frames >= 0 counter pairs");
+    if ((reinterpret_cast<uintptr_t>(noise) & 7) != 0)
+        return fail(DPPIX_EINVAL, "noise must be 8-byte aligned");
+    hipError_t e = launch_noise_advance(noise, n_frames, step, reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return dev_fail(e, "noise advance launch");
     return DPPIX_OK;
 }
 

@@ -35,17 +35,23 @@ struct FrameRec {
     uint32_t key0, key1, fi0, fi1;
 };
 
-// Workspace layout (byte offsets from the bound workspace base).
+// Workspace layout of a plan (byte offsets from the bound workspace base):
+// tables written once by dp_pix_plan_bind and only read afterwards, so one
+// bound plan serves any number of concurrent calls.
 struct WsLayout {
     size_t frames;        // FrameRec[n_frames]
     size_t tile_map;      // int32[n_tiles][2]: (frame, tile within frame) per scheduling index
     size_t unit_map;      // int32[n_units][2]: (frame, plan unit within frame), frame-major
     size_t border_map;    // int32[n_border][2]: (frame, tile) of the tiles the adjoint's mirror pass visits
-    size_t flags;         // uint8[total_cells] (classification)
+    size_t total;
+};
+
+// Per-call state that travels with a store (byte offsets from store->state):
+// what dp_pix_plan (or dp_pix_store_index) derives from the flags beside the
+// store's counts, and the ticket words of that call sequence's launches.
+struct StateLayout {
     size_t tile_cnt;      // uint32[n_tiles]: complex cells per tile
     size_t tile_fg;       // uint32[n_tiles]: complex cells of the frame before the tile
-    size_t frame_tot;     // uint64[n_frames][2]: n_bg, n_fg cells
-    size_t frame_base;    // uint64[n_frames][2]: float offsets of the frame in bg, fg
     size_t counters;      // uint32[kTicketWords]: tickets of persistent launches (two per group) and
                           // the scan's finished-frame count
     size_t total;
@@ -64,16 +70,17 @@ struct TileArgs {
     const uint8_t* const* masks;
     const void* const* images;
     void* const* outs;
-    // plan products
-    uint8_t* flags;
-    uint32_t* tile_cnt;
-    uint32_t* tile_fg;
-    const uint64_t* frame_base;
-    uint64_t* frame_tot;
-    // store
+    // products of the plan, held by the caller's store
+    uint8_t* flags;           // store flags, 1 = complex cell
+    uint64_t* counts;         // store counts: per frame n_bg, n_fg, bg offset, fg offset
+    uint32_t* tile_cnt;       // store state: complex cells per tile
+    uint32_t* tile_fg;        // store state: complex cells of the frame before the tile
+    // per-frame Philox (key, counter) of this call: noise[2f] = seed,
+    // noise[2f + 1] = frame_index; NULL: the frame records' own
+    const uint64_t* noise;
+    // store statistics
     float* bg;
     float* fg;
-    uint8_t* store_flags;
     uint8_t* clip_bg;
     uint8_t* clip_fg;
     // diagnostics
@@ -98,13 +105,16 @@ struct TileArgs {
 // of all earlier frames instead of waiting for the others).
 constexpr int64_t kPrefixScanTiles = 16384;
 hipError_t launch_plan(const TileArgs& a, int64_t n_units, int threads, size_t lds, bool prefix_scan,
-                       uint64_t* counts_out, hipStream_t s);
+                       hipStream_t s);
+// Tile counts of complex cells from the store's flags alone, then the scan.
+hipError_t launch_store_index(const TileArgs& a, bool prefix_scan, hipStream_t s);
 hipError_t launch_forward(const TileArgs& a, int layout, int C, int threads, size_t lds, int grid, hipStream_t s);
 hipError_t launch_reconstruct(const TileArgs& a, int layout, int C, int threads, size_t lds, int grid,
                               hipStream_t s);
 hipError_t launch_backward_reduce(const TileArgs& a, int threads, size_t lds, int grid, hipStream_t s);
 hipError_t launch_backward_mirror(const TileArgs& a, int threads, int grid, hipStream_t s);
 hipError_t launch_philox(const uint32_t* in, uint32_t* out, int64_t n, hipStream_t s);
+hipError_t launch_noise_advance(uint64_t* noise, int32_t n, uint64_t step, hipStream_t s);
 hipError_t launch_edge_mask(const TileArgs& a, int C, int threads, hipStream_t s);
 hipError_t launch_metrics(const TileArgs& a, int C, int threads, hipStream_t s);
 hipError_t launch_metrics_reduce(const TileArgs& a, double* out, hipStream_t s);

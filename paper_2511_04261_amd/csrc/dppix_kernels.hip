@@ -259,8 +259,8 @@ __device__ __noinline__ v4u gather_strip_u8(const uint8_t* row, int p0, int tile
 // With cxl, also the list of the tile's complex cells in order (cxl[q] = kc
 // of the q-th complex cell) and their number in *ncx.
 __device__ __forceinline__ void tile_cells(const TileArgs& a, const FrameRec& F, int64_t t, int r, int x0c, int Kt,
-                                           uint32_t* cidx, uint8_t* cflag, bool write_store_flags,
-                                           uint16_t* cxl = nullptr, uint32_t* ncx = nullptr)
+                                           uint32_t* cidx, uint8_t* cflag, uint16_t* cxl = nullptr,
+                                           uint32_t* ncx = nullptr)
 {
     if (threadIdx.x >= 64)
         return;
@@ -281,8 +281,6 @@ __device__ __forceinline__ void tile_cells(const TileArgs& a, const FrameRec& F,
             cidx[kc] = fl ? run_fg + pc : run_bg + (uint32_t)lane - pc;
             if (cxl && fl)
                 cxl[run_fg - fg0 + pc] = (uint16_t)kc;
-            if (write_store_flags && a.store_flags)
-                a.store_flags[F.cell_base + before + kc] = fl;
             if (a.cell_index)
                 a.cell_index[F.cell_base + before + kc] = cidx[kc];
         }
@@ -309,6 +307,15 @@ __device__ __forceinline__ TileCoord tile_of(const TileArgs& a, int64_t sched_id
     tc.f = (int)uniform_u32((uint32_t)a.tile_map[2 * idx]);
     const int64_t local = (int64_t)uniform_u32((uint32_t)a.tile_map[2 * idx + 1]);
     F = a.frames[tc.f];
+    if (a.noise != nullptr) {
+        // this call's noise counters, read at launch time (a replayed graph
+        // draws fresh noise once the caller has advanced them)
+        const uint64_t key = a.noise[2 * tc.f], ctr = a.noise[2 * tc.f + 1];
+        F.key0 = (uint32_t)key;
+        F.key1 = (uint32_t)(key >> 32);
+        F.fi0 = (uint32_t)ctr;
+        F.fi1 = (uint32_t)(ctr >> 32);
+    }
     tc.t = F.tile_base + local;
     tc.r = (int)(local / F.TX);
     tc.ct = (int)(local - (int64_t)tc.r * F.TX);
@@ -350,19 +357,20 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T* wave_tot, T& total)
 }
 
 // Frame-level pass of the scan: store offsets of every frame (frames
-// concatenated in batch order), per-frame counts, ticket reset.  Run by the
-// last workgroup of the plan kernel; the per-frame totals written by others
-// are read with agent-scope atomic loads after an acquire fence.
-__device__ void scan_frames(const TileArgs& a, uint64_t* frame_base, uint64_t* counts, uint64_t* wave_tot)
+// concatenated in batch order) into the store counts, ticket reset.  Run by
+// the last workgroup of k_scan; the per-frame totals the others wrote into
+// counts[4f], counts[4f + 1] are read with agent-scope atomic loads after an
+// acquire fence.
+__device__ void scan_frames(const TileArgs& a, uint64_t* wave_tot)
 {
     uint64_t carry_bg = 0, carry_fg = 0;
     for (int base = 0; base < a.n_frames; base += blockDim.x) {
         const int f = base + threadIdx.x;
-        uint64_t vb = 0, vf = 0, nb = 0, nf = 0;
+        uint64_t vb = 0, vf = 0;
         if (f < a.n_frames) {
             const FrameRec F = a.frames[f];
-            nb = __hip_atomic_load(&a.frame_tot[2 * f], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            nf = __hip_atomic_load(&a.frame_tot[2 * f + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint64_t nb = __hip_atomic_load(&a.counts[4 * f], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint64_t nf = __hip_atomic_load(&a.counts[4 * f + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             vb = nb * (uint64_t)F.C;
             vf = nf * (uint64_t)F.n * (uint64_t)F.n * (uint64_t)F.C;
         }
@@ -370,14 +378,8 @@ __device__ void scan_frames(const TileArgs& a, uint64_t* frame_base, uint64_t* c
         const uint64_t eb = block_exclusive_scan<uint64_t>(vb, wave_tot, tb);
         const uint64_t ef = block_exclusive_scan<uint64_t>(vf, wave_tot, tf);
         if (f < a.n_frames) {
-            frame_base[2 * f + 0] = carry_bg + eb;
-            frame_base[2 * f + 1] = carry_fg + ef;
-            if (counts) {
-                counts[4 * f + 0] = nb;
-                counts[4 * f + 1] = nf;
-                counts[4 * f + 2] = carry_bg + eb;
-                counts[4 * f + 3] = carry_fg + ef;
-            }
+            a.counts[4 * f + 2] = carry_bg + eb;
+            a.counts[4 * f + 3] = carry_fg + ef;
         }
         carry_bg += tb;
         carry_fg += tf;
@@ -567,6 +569,10 @@ __global__ __launch_bounds__(kMaxThreads) void k_plan(TileArgs a)
     uint32_t* tcnt = cellcnt + F.cnb * KCs;
     for (int i = tid; i < F.cnb * (KCs + F.ctx); i += NT)
         cellcnt[i] = 0u;
+    // the store's ticket words start at zero for the scan and later launches
+    // of this call sequence (stream order: no earlier launch still uses them)
+    if (blockIdx.x == 0 && tid < kTicketWords)
+        a.ticket[tid] = 0u;
     lds_barrier();
     const uint8_t* mask = a.masks ? a.masks[f] : nullptr;
     if (mask != nullptr)
@@ -594,7 +600,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_plan(TileArgs a)
 // then runs the frame-level pass.  (A separate launch: electing a last
 // workgroup per plan unit would need an agent-scope fence — an L2 write-back
 // and invalidate — in every unit.)
-__global__ __launch_bounds__(256) void k_scan(TileArgs a, uint64_t* frame_base, uint64_t* counts)
+__global__ __launch_bounds__(256) void k_scan(TileArgs a)
 {
     __shared__ uint32_t wave_tot[9];
     __shared__ uint64_t wave_tot64[9];
@@ -614,8 +620,8 @@ __global__ __launch_bounds__(256) void k_scan(TileArgs a, uint64_t* frame_base, 
     }
     if (threadIdx.x == 0) {
         const uint64_t cells = (uint64_t)F.GR * F.GC;
-        __hip_atomic_store(&a.frame_tot[2 * f + 0], cells - carry, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&a.frame_tot[2 * f + 1], (uint64_t)carry, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&a.counts[4 * f + 0], cells - carry, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&a.counts[4 * f + 1], (uint64_t)carry, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __threadfence();                                    // release the totals
         s_last = atomicAdd(&a.ticket[kScanWord], 1u) == gridDim.x - 1;
     }
@@ -623,7 +629,7 @@ __global__ __launch_bounds__(256) void k_scan(TileArgs a, uint64_t* frame_base, 
     if (!s_last)
         return;
     __threadfence();                                        // acquire the others' totals
-    scan_frames(a, frame_base, counts, wave_tot64);
+    scan_frames(a, wave_tot64);
     __syncthreads();
     if (threadIdx.x == 0)
         atomicExch(&a.ticket[kScanWord], 0u);
@@ -634,7 +640,7 @@ __global__ __launch_bounds__(256) void k_scan(TileArgs a, uint64_t* frame_base, 
 // counts) and whose tile counts are few: frames are concatenated, so the
 // complex cells of every earlier frame are one prefix of the tile array,
 // which workgroup f adds up itself before scanning its own tiles.
-__global__ __launch_bounds__(256) void k_scan_prefix(TileArgs a, uint64_t* frame_base, uint64_t* counts)
+__global__ __launch_bounds__(256) void k_scan_prefix(TileArgs a)
 {
     __shared__ uint32_t wave_tot[9];
     const int f = blockIdx.x, tid = threadIdx.x, NT = blockDim.x;
@@ -672,17 +678,36 @@ __global__ __launch_bounds__(256) void k_scan_prefix(TileArgs a, uint64_t* frame
         const uint64_t nf = carry, nb = (uint64_t)F.GR * (uint64_t)F.GC - nf;
         const uint64_t bb = (uint64_t)F.C * ((uint64_t)F.cell_base - before);
         const uint64_t fb = (uint64_t)F.n * (uint64_t)F.n * (uint64_t)F.C * (uint64_t)before;
-        frame_base[2 * f + 0] = bb;
-        frame_base[2 * f + 1] = fb;
-        if (counts) {
-            counts[4 * f + 0] = nb;
-            counts[4 * f + 1] = nf;
-            counts[4 * f + 2] = bb;
-            counts[4 * f + 3] = fb;
-        }
+        a.counts[4 * f + 0] = nb;
+        a.counts[4 * f + 1] = nf;
+        a.counts[4 * f + 2] = bb;
+        a.counts[4 * f + 3] = fb;
     }
     if (f == 0 && tid < kScanWord)
         a.ticket[tid] = 0;
+}
+
+// Complex cells per tile from the store's flags alone (a store that was
+// written elsewhere, e.g. decoded from its serialised form), one lane per
+// tile; the scan then rebuilds the tile prefixes and the frame counts and
+// offsets.  Workgroup 0 clears the ticket words as k_plan does.
+__global__ __launch_bounds__(256) void k_tile_count(TileArgs a)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (blockIdx.x == 0 && threadIdx.x < kTicketWords)
+        a.ticket[threadIdx.x] = 0u;
+    if (i >= a.n_tiles)
+        return;
+    const int f = a.tile_map[2 * i];
+    const int64_t local = a.tile_map[2 * i + 1];
+    const FrameRec F = a.frames[f];
+    const int r = (int)(local / F.TX), ct = (int)(local - (int64_t)r * F.TX);
+    const int x0c = ct * F.K, Kt = min(F.K, F.GC - x0c);
+    const uint8_t* fl = a.flags + F.cell_base + (int64_t)r * F.GC + x0c;
+    uint32_t cnt = 0;
+    for (int k = 0; k < Kt; ++k)
+        cnt += fl[k] != 0;
+    a.tile_cnt[F.tile_base + local] = cnt;
 }
 
 // Subgrid rows per phase-1 item: with short subgrid rows an item takes
@@ -916,9 +941,9 @@ __device__ void forward_tile_u8(const TileArgs& a, const FrameRec& F, const Tile
     uint16_t* cxl = reinterpret_cast<uint16_t*>(lds + L.cxl);
     __shared__ uint32_t s_ncx;
 
-    tile_cells(a, F, tc.t, r, x0c, Kt, cidx, cflag, true, cxl, &s_ncx);
-    const uint64_t bg_base = a.frame_base[2 * tc.f + 0];
-    const uint64_t fg_base = a.frame_base[2 * tc.f + 1];
+    tile_cells(a, F, tc.t, r, x0c, Kt, cidx, cflag, cxl, &s_ncx);
+    const uint64_t bg_base = a.counts[4 * tc.f + 2];
+    const uint64_t fg_base = a.counts[4 * tc.f + 3];
     const int items = Kt * n * C;
     const int nn = n * n;
     const int rowbuf = 16 * nstr;           // 16-bit column sums of one subgrid row
@@ -1194,9 +1219,9 @@ __device__ void forward_tile_f32(const TileArgs& a, const FrameRec& F, const Til
     float* vgs = reinterpret_cast<float*>(lds + L.vgs);
     float* vgc = reinterpret_cast<float*>(lds + L.vgc);
 
-    tile_cells(a, F, tc.t, r, x0c, Kt, cidx, cflag, true);
-    const uint64_t bg_base = a.frame_base[2 * tc.f + 0];
-    const uint64_t fg_base = a.frame_base[2 * tc.f + 1];
+    tile_cells(a, F, tc.t, r, x0c, Kt, cidx, cflag);
+    const uint64_t bg_base = a.counts[4 * tc.f + 2];
+    const uint64_t fg_base = a.counts[4 * tc.f + 3];
     const int nn = n * n;
     const int kn = Kt * n;
     lds_barrier();
@@ -1374,9 +1399,9 @@ __device__ void reconstruct_tile_u8(const TileArgs& a, const FrameRec& F, const 
     uint8_t* cflag = lds + L.cflag;
     uint8_t* vgs = lds + L.vgs;
     uint8_t* vgc = lds + L.vgc;
-    tile_cells(a, F, tc.t, r, x0c, Kt, cidx, cflag, false);
-    const uint64_t bg_base = a.frame_base[2 * tc.f + 0];
-    const uint64_t fg_base = a.frame_base[2 * tc.f + 1];
+    tile_cells(a, F, tc.t, r, x0c, Kt, cidx, cflag);
+    const uint64_t bg_base = a.counts[4 * tc.f + 2];
+    const uint64_t fg_base = a.counts[4 * tc.f + 3];
     const int nn = n * n, kn = Kt * n;
     lds_barrier();
     for (int j = tid; j < Kt * C; j += NT) {
@@ -1455,9 +1480,9 @@ __device__ void reconstruct_tile_f32(const TileArgs& a, const FrameRec& F, const
     uint8_t* cflag = lds + L.cflag;
     float* vgs = reinterpret_cast<float*>(lds + L.vgs);
     float* vgc = reinterpret_cast<float*>(lds + L.vgc);
-    tile_cells(a, F, tc.t, r, x0c, Kt, cidx, cflag, false);
-    const uint64_t bg_base = a.frame_base[2 * tc.f + 0];
-    const uint64_t fg_base = a.frame_base[2 * tc.f + 1];
+    tile_cells(a, F, tc.t, r, x0c, Kt, cidx, cflag);
+    const uint64_t bg_base = a.counts[4 * tc.f + 2];
+    const uint64_t fg_base = a.counts[4 * tc.f + 3];
     const int nn = n * n, kn = Kt * n;
     lds_barrier();
     for (int j = tid; j < Kt * C; j += NT) {
@@ -1549,9 +1574,9 @@ __device__ void backward_reduce_tile(const TileArgs& a, const FrameRec& F, const
     float* vgs = reinterpret_cast<float*>(lds + L.vgs);
     float* vgc = reinterpret_cast<float*>(lds + L.vgc);
     float* gin = a.grad_in ? a.grad_in[tc.f] : nullptr;
-    tile_cells(a, F, tc.t, r, x0c, Kt, cidx, cflag, false);
-    const uint64_t bg_base = a.frame_base[2 * tc.f + 0];
-    const uint64_t fg_base = a.frame_base[2 * tc.f + 1];
+    tile_cells(a, F, tc.t, r, x0c, Kt, cidx, cflag);
+    const uint64_t bg_base = a.counts[4 * tc.f + 2];
+    const uint64_t fg_base = a.counts[4 * tc.f + 3];
     const int nn = n * n, kn = Kt * n;
     lds_barrier();
     // as in the fp32 forward: (channel, subgrid row, strip) items over groups
@@ -1651,9 +1676,9 @@ __device__ __forceinline__ float g_at(const TileArgs& a, const FrameRec& F, int 
     const int64_t cell = F.cell_base + (int64_t)(y / b) * F.GC + x / b;
     const uint32_t idx = a.cell_index[cell];
     if (!a.flags[cell])
-        return a.g_bg[a.frame_base[2 * f] + (uint64_t)idx * F.C + ch];
+        return a.g_bg[a.counts[4 * f + 2] + (uint64_t)idx * F.C + ch];
     const int i = (y % b) / s, j = (x % b) / s;
-    return a.g_fg[a.frame_base[2 * f + 1] + ((uint64_t)idx * n * n + i * n + j) * F.C + ch];
+    return a.g_fg[a.counts[4 * f + 3] + ((uint64_t)idx * n * n + i * n + j) * F.C + ch];
 }
 
 // Mirror terms of the adjoint: a real pixel near the bottom or right border is
@@ -1935,6 +1960,15 @@ __global__ void k_metrics_reduce(TileArgs a, double* out)
     out[2 * f + 1] = windows > 0 ? t / windows : 0.0;
 }
 
+// Advance every frame's Philox counter (frame_index) by `step`: the next
+// video step of a captured graph draws fresh noise.
+__global__ void k_noise_advance(uint64_t* noise, int32_t n, uint64_t step)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        noise[2 * i + 1] += step;
+}
+
 // ==========================================================================
 // Diagnostics.
 // ==========================================================================
@@ -1982,8 +2016,16 @@ hipError_t allow_lds(K kernel, size_t lds)
     return e;
 }
 
-hipError_t launch_plan(const TileArgs& a, int64_t n_units, int threads, size_t lds, bool prefix_scan,
-                       uint64_t* counts_out, hipStream_t s)
+static hipError_t launch_scan(const TileArgs& a, bool prefix_scan, hipStream_t s)
+{
+    if (prefix_scan)
+        hipLaunchKernelGGL(k_scan_prefix, dim3((unsigned)a.n_frames), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_scan, dim3((unsigned)a.n_frames), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_plan(const TileArgs& a, int64_t n_units, int threads, size_t lds, bool prefix_scan, hipStream_t s)
 {
     if (n_units == 0)
         return hipSuccess;
@@ -1994,13 +2036,18 @@ hipError_t launch_plan(const TileArgs& a, int64_t n_units, int threads, size_t l
     e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    if (prefix_scan)
-        hipLaunchKernelGGL(k_scan_prefix, dim3((unsigned)a.n_frames), dim3(256), 0, s, a,
-                           const_cast<uint64_t*>(a.frame_base), counts_out);
-    else
-        hipLaunchKernelGGL(k_scan, dim3((unsigned)a.n_frames), dim3(256), 0, s, a,
-                           const_cast<uint64_t*>(a.frame_base), counts_out);
-    return hipGetLastError();
+    return launch_scan(a, prefix_scan, s);
+}
+
+hipError_t launch_store_index(const TileArgs& a, bool prefix_scan, hipStream_t s)
+{
+    if (a.n_tiles == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_tile_count, dim3((unsigned)((a.n_tiles + 255) / 256)), dim3(256), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    return launch_scan(a, prefix_scan, s);
 }
 
 template <typename K>
@@ -2077,6 +2124,14 @@ hipError_t launch_metrics(const TileArgs& a, int C, int threads, hipStream_t s)
 hipError_t launch_metrics_reduce(const TileArgs& a, double* out, hipStream_t s)
 {
     hipLaunchKernelGGL(k_metrics_reduce, dim3((unsigned)((a.n_frames + 63) / 64)), dim3(64), 0, s, a, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_noise_advance(uint64_t* noise, int32_t n, uint64_t step, hipStream_t s)
+{
+    if (n == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_noise_advance, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, noise, n, step);
     return hipGetLastError();
 }
 

@@ -51,7 +51,8 @@ int main(void) {
   printf("dppix_frame_info_t size %zu 0\n", sizeof(dppix_frame_info_t));
   F(dppix_frame_desc_t, pitch); F(dppix_frame_desc_t, eps_bg); F(dppix_frame_desc_t, seed);
   F(dppix_frame_desc_t, frame_index); F(dppix_frame_desc_t, tile_cells);
-  F(dppix_sizes_t, n_tiles); F(dppix_sizes_t, total_pixels);
+  F(dppix_sizes_t, n_tiles); F(dppix_sizes_t, total_pixels); F(dppix_sizes_t, store_state_bytes);
+  F(dppix_store_t, counts); F(dppix_store_t, state); F(dppix_store_t, noise);
   F(dppix_frame_info_t, cell_offset); F(dppix_frame_info_t, sigma_fg);
   return 0;
 }
@@ -129,6 +130,10 @@ def test_null_and_empty_arguments():
     assert L.dp_pix_plan(h, None, ctypes.byref(s), None) == _lib.DPPIX_EINVAL
     assert L.dp_pix_forward(h, None, ctypes.byref(s), None, None, None, None) == _lib.DPPIX_EINVAL
     assert L.dp_pix_reconstruct(h, ctypes.byref(s), None, None) == _lib.DPPIX_EINVAL
+    assert L.dp_pix_store_index(h, ctypes.byref(s), None) == _lib.DPPIX_EINVAL
+    assert L.dp_pix_noise_advance(None, 1, 1, None) == _lib.DPPIX_EINVAL
+    assert L.dp_pix_noise_advance(None, -1, 1, None) == _lib.DPPIX_EINVAL
+    assert L.dp_pix_noise_advance(None, 0, 1, None) == 0          # nothing to do, nothing enqueued
     assert L.dp_pix_plan_set_launch(h, 96, 0) == _lib.DPPIX_EINVAL
     assert L.dp_pix_plan_set_launch(h, 1024, 0) == _lib.DPPIX_EINVAL
     assert L.dp_pix_plan_set_launch(h, 128, 1) == 0
@@ -225,6 +230,56 @@ def test_plans_for_extreme_and_mixed_batches():
         assert fi.tiles_per_band == -(-fi.grid_cols // fi.tile_cells)
         tiles += fi.grid_rows * fi.tiles_per_band
     assert sz.flag_bytes == cells and sz.n_tiles == tiles
-    # the workspace holds at least the frame records, two scheduling maps and per-tile counters
-    assert sz.workspace_bytes >= 144 * len(frames) + 8 * tiles + cells + 8 * tiles
+    # the workspace holds the frame records and the tile and plan-unit maps;
+    # each store's state holds two per-tile counters and the ticket words
+    assert sz.workspace_bytes >= 144 * len(frames) + 8 * tiles
+    assert sz.store_state_bytes >= 8 * tiles + 4 * 33
     L.dp_pix_plan_destroy(h)
+
+
+def test_workspace_size_without_a_plan():
+    """dp_pix_plan_workspace_size gives the sizes of dp_pix_plan_sizes for the
+    same descriptors, host only, and the status of dp_pix_plan_create for
+    invalid ones."""
+    L = lib()
+    frames = [dp.FrameParams(1080, 1920, 3, b=32, sb=8, eps_bg=1.0, eps_fg=0.3, tau=1),
+              dp.FrameParams(576, 768, 3, b=16, sb=4), dp.FrameParams(37, 41, 1, dp.F32_CHW, b=8, sb=2)]
+    d = (_lib.FrameDesc * 3)(*[f.desc() for f in frames])
+    a = _lib.Sizes()
+    assert L.dp_pix_plan_workspace_size(d, 3, ctypes.byref(a)) == 0
+    st, h, L = create(frames)
+    assert st == 0
+    b = _lib.Sizes()
+    assert L.dp_pix_plan_sizes(h, ctypes.byref(b)) == 0
+    L.dp_pix_plan_destroy(h)
+    for name, _ in _lib.Sizes._fields_:
+        assert getattr(a, name) == getattr(b, name), name
+    assert a.store_state_bytes > 0 and a.workspace_bytes > 0
+    bad = (_lib.FrameDesc * 1)(dp.FrameParams(10, 10, b=16, sb=5).desc())
+    assert L.dp_pix_plan_workspace_size(bad, 1, ctypes.byref(a)) == _lib.DPPIX_EINVAL
+    assert L.dp_pix_plan_workspace_size(d, 0, ctypes.byref(a)) == _lib.DPPIX_EINVAL
+    assert L.dp_pix_plan_workspace_size(d, 3, None) == _lib.DPPIX_EINVAL
+
+
+def test_host_masks_and_in_place_outputs_are_refused():
+    """The Python face refuses, before any launch, masks that are not CUDA
+    tensors (their host address would reach the plan kernel) and fused
+    outputs that overlap their images."""
+    torch = pytest.importorskip("torch")
+    frames = [dp.FrameParams(8, 12, 3)]
+    cuda0 = torch.device("cuda", 0)
+    with pytest.raises(ValueError, match="CUDA"):
+        dp.check_masks(frames, [torch.zeros((8, 12), dtype=torch.uint8)], cuda0)
+    with pytest.raises(ValueError, match="one mask"):
+        dp.check_masks(frames, [None, None], cuda0)
+    dp.check_masks(frames, [None], cuda0)
+    dp.check_masks(frames, None, cuda0)
+    x = torch.zeros((8, 12, 3), dtype=torch.uint8)
+    with pytest.raises(ValueError, match="overlaps"):
+        dp.check_no_alias([x], [x])
+    with pytest.raises(ValueError, match="overlaps"):
+        big = torch.zeros((16, 12, 3), dtype=torch.uint8)
+        dp.check_no_alias([big[:8]], [big[4:12]])
+    big = torch.zeros((16, 12, 3), dtype=torch.uint8)
+    dp.check_no_alias([big[:8]], [big[8:]])
+    dp.check_no_alias([x], [torch.zeros_like(x)])

@@ -118,8 +118,10 @@ def test_whole_batch_autotune_is_bitwise_identical(dev):
 def test_uneven_batch_full_size_sampled(dev):
     """256 frames of 768x576 .. 6000x4000, per-frame grids and budgets, one
     graph-replayed launch in the benchmark's configuration (one workgroup per
-    tile); one frame of each resolution checked in full against the oracle,
-    all frames for store invariants."""
+    tile); one frame of every (resolution, b, s_b) class present checked in
+    full against the oracle (the classes decide the tile shapes and which
+    launch group, 128 or 256 lanes, a frame runs in), all frames for store
+    invariants."""
     say("case: uneven 256-frame batch")
     specs = synth.uneven_batch(256)
     frames = [dp.FrameParams.from_spec(s) for s in specs]
@@ -141,14 +143,15 @@ def test_uneven_batch_full_size_sampled(dev):
         of += nf * fi.n * fi.n * 3
     seen = set()
     for i, s in enumerate(specs):
-        if (s.height, s.width) in seen:
+        if (s.height, s.width, s.b, s.sb) in seen:
             continue
-        seen.add((s.height, s.width))
+        seen.add((s.height, s.width, s.b, s.sb))
         say("  oracle on frame", i, s.height, s.width, s.b, s.sb)
         img = imgs[i].cpu().numpy()
         want = oracle.forward(img, s.mask, oracle_params(frames[i]))
         compare_frame(store[i], want, outs[i].cpu().numpy(), "frame %d" % i)
         s.drop_host()
+    assert len(seen) == 16      # every class of 4 resolutions x b in {16, 32} x s_b in {4, 8} occurs
     g.close()
 
 
@@ -211,7 +214,9 @@ def test_autograd_full_batch_and_fd(dev):
 
 def test_serving_alone_equals_mix(dev):
     """Frames served from 16 mixed-resolution streams (continuous batching,
-    memory admission) give the same store bit for bit as each frame alone."""
+    memory admission) give the same store bit for bit as each frame alone,
+    and served frames of every resolution equal the oracle's release of the
+    same frame with the same counter."""
     say("case: serving alone vs mix")
     from paper_2511_04261_amd.serving import GpuBackend, MemoryLedger, Scheduler, camera_streams, serve_streams
     streams = camera_streams(duration_s=1.5, pool=3, device=dev)
@@ -231,6 +236,15 @@ def test_serving_alone_equals_mix(dev):
         torch.cuda.synchronize()
         alone = plan.store_host()[0]
         assert _store_equal(q.result, alone), (q.rid, q.stream, q.frame_index)
+    by_res = {}
+    for q in done:
+        by_res.setdefault((q.height, q.width), []).append(q)
+    assert len(by_res) == 3
+    for (H, W), qs in sorted(by_res.items()):
+        for q in (qs[0], qs[len(qs) // 2], qs[-1]):
+            say("  oracle on served frame", q.rid, H, W, q.frame_index)
+            want = oracle.forward(q.image.numpy(), q.mask.numpy(), oracle_params(be.frame_params(q)))
+            compare_frame(q.result, want, None, "served frame %d" % q.rid)
 
 
 @pytest.mark.parametrize("H,W,C,b,sb,T,pad", [(75, 97, 3, 16, 4, 60, 0), (270, 480, 3, 32, 8, 40, 0),

@@ -58,12 +58,28 @@ def test_metrics_match_oracle(dev):
 
 def test_storage_study_small(dev):
     """Encoded store vs PNG of the reconstruction over grid sizes and subgrid
-    factors: the store shrinks with b, grows with n, and decodes exactly."""
+    factors: the store shrinks with b, grows with n; every store the GPU
+    wrote decodes to the oracle's store of the same frame (flags exact, fp32
+    statistics within 1e-3, uint8 statistics within one level of the
+    oracle's rounded ones) with the frame's privacy ledger in its header."""
     say("case: storage study")
     from paper_2511_04261_amd import store_codec as sc
     specs = synth.region_batch(2, height=270, width=480)
-    rows = sc.storage_study(specs, grid_sizes=(4, 16, 64), factors=(1, 4), device=dev)
+    rows = sc.storage_study(specs, grid_sizes=(4, 16, 64), factors=(1, 4), device=dev, keep_blobs=True)
     by = {(r["b"], r["n"]): r for r in rows}
     assert by[(64, 1)]["store_u8"] < by[(16, 1)]["store_u8"] < by[(4, 1)]["store_u8"]
     assert by[(16, 4)]["store_u8"] > by[(16, 1)]["store_u8"]
     assert all(r["store_u8"] < r["png"] for r in rows if r["b"] >= 16)
+    imgs = [s.image_torch(dev).cpu().numpy() for s in specs]
+    for r in rows:
+        for k, (s, fp) in enumerate(zip(specs, r["frames_params"])):
+            say("  decode b=%d n=%d frame %d" % (r["b"], r["n"], k))
+            want = oracle.forward(imgs[k], s.mask, oracle_params(fp))
+            for blob, tol, quant in ((r["blobs_f32"][k], 1e-3, "f32"), (r["blobs_u8"][k], 1.0, "u8")):
+                hdr, st = sc.decode(blob)
+                assert hdr["ledger"] == sc.privacy_ledger(3, fp.m, fp.eps_bg, fp.eps_fg)
+                assert np.array_equal(st["flags"], want["flags"]) and st["counts"] == want["counts"]
+                for key in ("bg", "fg"):
+                    ref = want[key] if quant == "f32" else np.rint(want[key])
+                    if ref.size:
+                        assert np.abs(st[key] - ref).max() <= tol, (r["b"], r["n"], k, quant, key)

@@ -291,8 +291,7 @@ def test_region_batch_1080p_sampled(dev):
     """64 RGB 1920x1080 frames, 8-rectangle masks, b=32/eps=1.0 simple,
     s_b=8/eps=0.3 complex, m=16, in the launch configuration the benchmark
     times (default workgroups, one per tile, plan + forward captured in a
-    graph and replayed); three frames checked in full against the oracle and
-    every frame for invariants."""
+    graph and replayed); every frame checked in full against the oracle."""
     say("case: 64x1080p batch")
     frames_s = synth.region_batch(64)
     frames = [dp.FrameParams.from_spec(s) for s in frames_s]
@@ -305,9 +304,12 @@ def test_region_batch_1080p_sampled(dev):
     g.launch()
     torch.cuda.synchronize()
     store = plan.store_host()
-    for i in (0, 31, 63):
+    for i in range(64):
+        if i % 16 == 0:
+            say("  oracle on frames %d.." % i)
         want = oracle.forward(imgs[i].cpu().numpy(), frames_s[i].mask, oracle_params(frames[i]))
         compare_frame(store[i], want, outs[i].cpu().numpy(), "frame %d" % i)
+        frames_s[i].drop_host()
     g.close()
     res = {"store": store}
     off_b = off_f = 0

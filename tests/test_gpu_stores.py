@@ -1,0 +1,245 @@
+"""GPU tests of stores as the unit of a call sequence: one bound plan serves
+several stores at once (other masks, other images, other streams), every
+call reads the classes and offsets of the store it is given, a store loaded
+from its serialised form is rebuilt from its flags alone, and per-call noise
+counters give every replay of a graph fresh noise.  Everything is checked
+against the oracle on the same seeded inputs."""
+import ctypes
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from tests.helpers import chw_to_hwc, compare_frame, hwc_to_chw, oracle_params
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+dp = pytest.importorskip("paper_2511_04261_amd")
+from paper_2511_04261_amd import _lib, synth  # noqa: E402
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def with_index(fp, frame_index):
+    return dp.FrameParams(fp.height, fp.width, fp.channels, fp.layout, fp.b, fp.sb, fp.m, fp.eps_bg, fp.eps_fg,
+                          fp.tau, fp.pad_mode, fp.seed, frame_index)
+
+
+def test_autograd_two_forwards_then_one_backward(dev):
+    """One layer, two forwards with different masks before a single backward
+    (gradient accumulation, two-branch losses): each input's gradient is the
+    oracle's adjoint through its own forward's classification."""
+    for (H, W) in [(64, 64), (61, 57)]:
+        say("case: two forwards, one backward", H, W)
+        r = rng(100 + H)
+        x1, x2 = synth.uniform_f32(r, (2, 3, H, W)), synth.uniform_f32(r, (2, 3, H, W))
+        m1 = [synth.rect_mask(r, H, W, n_rects=2, rect_frac=0.1, cover=(0.05, 0.5)) for _ in range(2)]
+        m2 = [np.ascontiguousarray(1 - m) for m in m1]          # complement: every class flips
+        w1 = r.standard_normal((2, 3, H, W)).astype(np.float32)
+        w2 = r.standard_normal((2, 3, H, W)).astype(np.float32)
+        layer = dp.DPPixLayer(b=16, sb=8, m=8, eps_bg=1.0, eps_fg=0.5, tau=1, seed=3)
+        t1 = torch.from_numpy(x1).to(dev).requires_grad_(True)
+        t2 = torch.from_numpy(x2).to(dev).requires_grad_(True)
+        y1 = layer(t1, [torch.from_numpy(m).to(dev) for m in m1])
+        y2 = layer(t2, [torch.from_numpy(m).to(dev) for m in m2])
+        loss = (y1 * torch.from_numpy(w1).to(dev)).sum() + (y2 * torch.from_numpy(w2).to(dev)).sum()
+        loss.backward()
+        for x, masks, w, t, y in ((x1, m1, w1, t1, y1), (x2, m2, w2, t2, y2)):
+            for i in range(2):
+                p = oracle_params(dp.FrameParams(H, W, 3, dp.F32_CHW, b=16, sb=8, m=8, eps_bg=1.0, eps_fg=0.5,
+                                                 tau=1, seed=3, frame_index=i))
+                want = oracle.forward(chw_to_hwc(x[i]), masks[i], p)
+                assert np.abs(chw_to_hwc(y[i].detach().cpu().numpy()) - want["recon_f32"]).max() <= 1e-3
+                gw = oracle.backward(chw_to_hwc(x[i]).astype(np.float64), masks[i],
+                                     chw_to_hwc(w[i]).astype(np.float64), p)
+                got = chw_to_hwc(t.grad[i].cpu().numpy())
+                assert np.abs(got - gw).max() <= 1e-5 * max(1.0, np.abs(gw).max())
+
+
+def test_one_plan_shared_by_two_streams(dev):
+    """One bound plan, two stores with their own masks, images and noise
+    counters, plan + forward + reconstruct issued alternately on two streams
+    for several rounds: every result equals the oracle for its own inputs."""
+    say("case: one plan, two streams")
+    specs = synth.region_batch(4, height=270, width=480, seed=21)
+    frames = [dp.FrameParams.from_spec(s) for s in specs]
+    plan = dp.Plan(frames, device=dev)
+    r = rng(22)
+    work = []
+    for k in range(2):
+        imgs = [torch.from_numpy(synth.gradient_image(r, 270, 480, 3)).to(dev) for _ in frames]
+        masks = [torch.from_numpy(synth.rect_mask(r, 270, 480)).to(dev) for _ in frames]
+        noise = plan.noise_counters()
+        noise[:, 1] += 1000 * (k + 1)
+        store = plan.new_store(noise=noise)
+        work.append(dict(imgs=imgs, masks=masks, store=store, outs=[torch.empty_like(t) for t in imgs],
+                         rec=[torch.empty_like(t) for t in imgs], base=1000 * (k + 1)))
+    streams = [torch.cuda.Stream(dev), torch.cuda.Stream(dev)]
+    for rnd in range(3):
+        for w, st in zip(work, streams):
+            plan.plan(w["masks"], stream=st, store=w["store"])
+        for w, st in zip(work, streams):
+            plan.forward(w["imgs"], out=w["outs"], stream=st, store=w["store"])
+        for w, st in zip(work, streams):
+            plan.reconstruct(w["rec"], stream=st, store=w["store"])
+            plan.advance_noise(w["store"].noise, 7, stream=st)
+        torch.cuda.synchronize()
+        for w in work:
+            got = w["store"].host()
+            for i, fp in enumerate(frames):
+                want = oracle.forward(w["imgs"][i].cpu().numpy(), w["masks"][i].cpu().numpy(),
+                                      oracle_params(with_index(fp, fp.frame_index + w["base"] + 7 * rnd)))
+                compare_frame(got[i], want, w["outs"][i].cpu().numpy(), "round %d fused" % rnd)
+                compare_frame(got[i], want, w["rec"][i].cpu().numpy(), "round %d recon" % rnd)
+
+
+@pytest.mark.parametrize("layout", [dp.U8_HWC, dp.F32_CHW])
+def test_reconstruct_reads_its_own_store(dev, layout):
+    """Plan and forward store A, then plan and forward store B on the same
+    plan with other masks; reconstructing A afterwards still gives A's
+    frames (its flags, counts and index), as does B."""
+    say("case: reconstruct store A after plan B", layout)
+    r = rng(30 + layout)
+    shapes = [(75, 97, 3, 16, 4), (130, 47, 3, 32, 8), (61, 57, 1, 20, 5)]
+    frames = [dp.FrameParams(H, W, C, layout, b=b, sb=sb, m=8, eps_bg=1.0, eps_fg=0.4, tau=1, seed=5, frame_index=i)
+              for i, (H, W, C, b, sb) in enumerate(shapes)]
+    plan = dp.Plan(frames, device=dev)
+    sets = []
+    for k in range(2):
+        if layout == dp.U8_HWC:
+            imgs = [r.integers(0, 256, (H, W, C)).astype(np.uint8) for H, W, C, _, _ in shapes]
+        else:
+            imgs = [synth.uniform_f32(r, (C, H, W)) for H, W, C, _, _ in shapes]
+        masks = [(r.random((H, W)) < (0.1 if k == 0 else 0.6)).astype(np.uint8) for H, W, _, _, _ in shapes]
+        ti = [torch.from_numpy(x).to(dev) for x in imgs]
+        tm = [torch.from_numpy(m).to(dev) for m in masks]
+        store = plan.new_store()
+        plan.plan(tm, store=store)
+        plan.forward(ti, store=store)
+        sets.append((imgs, masks, ti, store))
+    for imgs, masks, ti, store in sets:
+        rec = [torch.empty_like(t) for t in ti]
+        plan.reconstruct(rec, store=store)
+        torch.cuda.synchronize()
+        got = store.host()
+        for i, fp in enumerate(frames):
+            img = imgs[i] if layout == dp.U8_HWC else chw_to_hwc(imgs[i])
+            want = oracle.forward(img, masks[i], oracle_params(fp))
+            out = rec[i].cpu().numpy()
+            compare_frame(got[i], want, out if layout == dp.U8_HWC else chw_to_hwc(out), "frame %d" % i)
+
+
+@pytest.mark.parametrize("quant", ["f32", "u8"])
+def test_decoded_store_rebuilt_from_flags(dev, quant):
+    """A store encoded to bytes, decoded on the host and loaded into a fresh
+    store: dp_pix_store_index rebuilds counts and offsets from the flags
+    alone (equal to the planned store's), and the reconstruction from it
+    equals the oracle's reconstruction of the decoded statistics."""
+    say("case: decoded store", quant)
+    from paper_2511_04261_amd import store_codec as sc
+    specs = synth.region_batch(3, height=200, width=333, seed=41) + \
+        synth.region_batch(2, height=77, width=90, b=16, sb=4, seed=42)
+    frames = [dp.FrameParams.from_spec(s) for s in specs]
+    plan = dp.Plan(frames, device=dev)
+    ti = [s.image_torch(dev) for s in specs]
+    tm = [s.mask_torch(dev) for s in specs]
+    plan.plan(tm)
+    plan.forward(ti)
+    torch.cuda.synchronize()
+    planned = plan.store_host()
+    q = sc.Q_F32 if quant == "f32" else sc.Q_U8
+    decoded = []
+    for fp, st in zip(frames, planned):
+        blob = sc.encode(st, fp.height, fp.width, fp.channels, fp.b, fp.sb, fp.m, fp.eps_bg, fp.eps_fg,
+                         frame_index=fp.frame_index, quant=q)
+        decoded.append(sc.decode(blob)[1])
+    fresh = plan.new_store()
+    fresh.load_host(decoded)
+    plan.index_store(fresh)
+    rec = [torch.empty_like(t) for t in ti]
+    plan.reconstruct(rec, store=fresh)
+    torch.cuda.synchronize()
+    got = fresh.host()
+    assert np.array_equal(fresh.counts.cpu().numpy(), plan.counts.cpu().numpy())
+    for i, (fp, s) in enumerate(zip(frames, specs)):
+        assert np.array_equal(got[i]["flags"], planned[i]["flags"])
+        p = oracle_params(fp)
+        _, want_u8 = oracle.reconstruct(decoded[i]["flags"], decoded[i]["bg"], decoded[i]["fg"], p)
+        d = np.abs(rec[i].cpu().numpy().astype(np.int16) - want_u8.astype(np.int16)).max()
+        assert d <= 1, (i, d)
+        # and against the oracle's own release of the frame
+        want = oracle.forward(ti[i].cpu().numpy(), s.mask, p)
+        # fp32 statistics within 1e-3; uint8 ones within one level of the
+        # oracle's rounded statistics
+        tol = 1e-3 if quant == "f32" else 1.0
+        assert np.array_equal(decoded[i]["flags"], want["flags"])
+        for k in ("bg", "fg"):
+            if want[k].size:
+                ref = want[k] if quant == "f32" else np.rint(want[k])
+                assert np.abs(decoded[i][k] - ref).max() <= tol, (i, k)
+
+
+def test_graph_replays_draw_fresh_noise(dev):
+    """A captured plan + forward with device-side noise counters: each replay,
+    after advancing the counters on the device, equals the oracle with the
+    next frame_index; without the advance a replay repeats its noise."""
+    say("case: graph replay with noise counters")
+    specs = synth.region_batch(3, height=150, width=260, seed=51)
+    frames = [dp.FrameParams.from_spec(s) for s in specs]
+    plan = dp.Plan(frames, device=dev)
+    ti = [s.image_torch(dev) for s in specs]
+    tm = [s.mask_torch(dev) for s in specs]
+    outs = [torch.empty_like(t) for t in ti]
+    store = plan.new_store(noise=plan.noise_counters())
+    g = plan.graph(tm, ti, outs, store=store)
+    prev = None
+    for rep in range(3):
+        g.launch()
+        torch.cuda.synchronize()
+        got = store.host()
+        for i, (fp, s) in enumerate(zip(frames, specs)):
+            want = oracle.forward(ti[i].cpu().numpy(), s.mask, oracle_params(with_index(fp, fp.frame_index + rep)))
+            compare_frame(got[i], want, outs[i].cpu().numpy(), "replay %d frame %d" % (rep, i))
+        if prev is not None:
+            assert not np.array_equal(prev[0]["bg"], got[0]["bg"])
+        prev = [dict(d) for d in got]
+        plan.advance_noise(store.noise)
+    g.close()
+
+
+def test_store_arguments_checked_before_launch(dev):
+    """Calls refuse stores without state or counts, or with misaligned state
+    or noise arrays, before anything is enqueued."""
+    say("case: store validation")
+    plan = dp.Plan([dp.FrameParams(32, 32, 1, b=8)], device=dev)
+    L = plan.lib
+    st = plan.store
+    good = st.c
+    for field, value in (("state", None), ("counts", None), ("flags", None), ("state", st.state.data_ptr() + 16),
+                         ("noise", st.state.data_ptr() + 4)):
+        bad = _lib.Store(good.bg, good.fg, good.flags, good.counts, good.state, good.noise)
+        setattr(bad, field, value)
+        assert L.dp_pix_plan(plan.handle, None, ctypes.byref(bad), None) == _lib.DPPIX_EINVAL, field
+        assert len(L.dp_pix_last_error()) > 0
+    assert L.dp_pix_plan_bind(plan.handle, ctypes.c_void_p(plan.workspace.data_ptr()), plan.workspace.numel(),
+                              None) == _lib.DPPIX_EINVAL          # a bound plan's tables never change
+    img = torch.zeros((32, 32, 1), dtype=torch.uint8, device=dev)
+    with pytest.raises(ValueError, match="overlaps"):
+        plan.forward([img], out=[img])
+    with pytest.raises(ValueError, match="CUDA"):
+        plan.plan([torch.zeros((32, 32), dtype=torch.uint8)])

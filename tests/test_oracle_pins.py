@@ -426,6 +426,44 @@ def test_backward_matches_central_fd(M, N, C, b, sb, mode):
         assert fd == pytest.approx(g[idx], abs=1e-7), idx
 
 
+@pytest.mark.parametrize("M,N", [(64, 64), (61, 57)])
+def test_backward_matches_central_fd_autograd_crop(M, N):
+    """The differentiable-layer workload's parameters (s_b = 8 / eps 0.5 for
+    complex cells, b = 16 / eps 1.0 for simple ones, m = 8, rectangle mask)
+    on a 3 x 64 x 64 crop (no padding) and a 3 x 61 x 57 crop (mirror
+    multiplicity on two sides): fp64 central differences with h = 1e-3 at
+    every pixel and channel equal the adjoint.  The map is linear between
+    clip kinks, so the difference is exact up to rounding; statistics within
+    h / area of 0 or 255 would straddle a kink, and none occur here."""
+    import concurrent.futures as cf
+    from paper_2511_04261_amd import synth
+    r = rng(M * 1000 + N)
+    C = 3
+    img = r.uniform(0, 255, (M, N, C))
+    mk = synth.rect_mask(r, M, N, n_rects=3, rect_frac=0.08, cover=(0.1, 0.5))
+    w = r.standard_normal((M, N, C))
+    p = Params(M, N, C, b=16, sb=8, m=8, eps_simple=1.0, eps_complex=0.5, tau=1, seed=5, frame_index=2)
+    o = oracle.forward(img, mk, p)
+    h = 1e-3
+    near = sum(int(((o[k] > 0) & (o[k] < 64 * h)).sum() + ((o[k] < 255) & (o[k] > 255 - 64 * h)).sum())
+               for k in ("bg", "fg"))
+    assert near == 0
+    assert 0 < int(o["flags"].sum()) < o["flags"].size          # both cell kinds present
+    g = oracle.backward(img, mk, w, p)
+
+    def fd(idx):
+        e = np.zeros_like(img)
+        e[idx] = h
+        rp = oracle.forward(img + e, mk, p)["recon_f64"]
+        rm = oracle.forward(img - e, mk, p)["recon_f64"]
+        return idx, float(((rp - rm) * w).sum()) / (2 * h)
+
+    with cf.ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+        for idx, v in ex.map(fd, itertools.product(range(M), range(N), range(C)), chunksize=256):
+            assert v == pytest.approx(g[idx], abs=1e-7), idx
+    assert np.abs(g).max() > 0
+
+
 def test_backward_matches_torch_autograd():
     """torch fp64 autograd of a gather-based definition: indices of the
     mirror-padded grid from numpy's pad, block means by reshape, the oracle's

@@ -21,7 +21,7 @@ def frame(seed=0, H=70, W=101, b=16, sb=4):
 
 def kw(p):
     return dict(height=p.height, width=p.width, channels=p.channels, b=p.b, sb=p.sb, m=p.m, eps_bg=p.eps_simple,
-                eps_fg=p.eps_complex, seed=p.seed, frame_index=p.frame_index)
+                eps_fg=p.eps_complex, frame_index=p.frame_index)
 
 
 @pytest.mark.parametrize("b,sb", [(16, 4), (8, 8), (32, 8), (4, 1)])
@@ -30,7 +30,11 @@ def test_round_trip_f32_exact_and_u8_rebuilds_u8(b, sb):
     hdr, st = sc.decode(sc.encode(o, quant=sc.Q_F32, **kw(p)))
     assert np.array_equal(st["flags"], o["flags"]) and np.array_equal(st["bg"], o["bg"])
     assert np.array_equal(st["fg"], o["fg"]) and st["counts"] == o["counts"]
-    assert hdr["b"] == b and hdr["sb"] == sb and hdr["frame_index"] == 7 and hdr["eps_fg"] == 0.3
+    assert hdr["b"] == b and hdr["sb"] == sb and hdr["frame_index"] == 7
+    led = hdr["ledger"]
+    assert led["eps_fg"] == 0.3 and led["eps_bg"] == 1.0 and led["m"] == 16
+    assert led["eps_frame"] == 1.0 and led["eps_pixel"] == 3.0      # Thm. 1: max over regions; x C whole pixels
+    assert "seed" not in hdr and b"seed" not in sc.encode(o, **kw(p))
     _, st8 = sc.decode(sc.encode(o, quant=sc.Q_U8, **kw(p)))
     _, ru = oracle.reconstruct(st8["flags"], st8["bg"], st8["fg"], p)
     assert np.array_equal(ru, o["recon_u8"])
@@ -56,3 +60,19 @@ def test_corrupt_and_inconsistent_input_refused():
     bad["flags"] = np.zeros_like(o["flags"])
     with pytest.raises(ValueError):
         sc.encode(bad, **kw(p))
+
+
+def test_ledger_and_no_key_in_the_bytes():
+    """The header carries the ledger (budgets, m, max over the regions by
+    parallel composition, C times that for whole-pixel neighbours) and the
+    noise counter, never the generator's key: the encoded bytes are the same
+    for two seeds."""
+    img, mk, p, o = frame(3)
+    blob = sc.encode(o, **kw(p))
+    hdr, _ = sc.decode(blob)
+    assert hdr["ledger"] == sc.privacy_ledger(3, 16, 1.0, 0.3)
+    import inspect
+    assert "seed" not in inspect.signature(sc.encode).parameters
+    led = sc.privacy_ledger(1, 4, 0.5, float("inf"))
+    assert led["eps_frame"] == float("inf") and led["eps_pixel"] == float("inf")
+    assert sc.privacy_ledger(1, 4, 0.5, 0.25)["eps_pixel"] == 0.5
