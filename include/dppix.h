@@ -287,6 +287,23 @@ dppix_status_t dp_pix_backward(dppix_plan_t plan, const dppix_store_t* store, co
                                const uint8_t* clip_bg, const uint8_t* clip_fg, float* const* grad_in,
                                void* scratch, size_t scratch_bytes, dppix_stream_t stream);
 
+/* dp_pix_backward without a scratch argument, for callers that cannot
+ * allocate device memory (code under stream capture, tight serving or
+ * training loops, harnesses that forbid hipMalloc): the scratch is a fixed
+ * 32 MiB device array inside the library, one per GPU, held from the
+ * library's load until the process ends.  Calls the same kernels as
+ * dp_pix_backward and gives the same result.  Returns DPPIX_ENOMEM, having
+ * enqueued nothing, when the plan's grad_scratch_bytes exceed 32 MiB (about
+ * 8 M statistics and cells; use dp_pix_backward then).  Allocates nothing:
+ * the device address of the array is looked up once per device, on the
+ * first call with that device current.  Every call on a GPU shares that
+ * GPU's array, so calls that may overlap on one GPU (other streams, other
+ * host threads) race and must be ordered by the caller.  The array needs
+ * no clearing: the first kernel writes every entry the second reads. */
+dppix_status_t dp_pix_backward_static(dppix_plan_t plan, const dppix_store_t* store, const float* const* grad_out,
+                                      const uint8_t* clip_bg, const uint8_t* clip_fg, float* const* grad_in,
+                                      dppix_stream_t stream);
+
 /* ---------------------------------------------------------------------------
  * Execution options, graphs, diagnostics.
  * ------------------------------------------------------------------------- */

@@ -467,6 +467,20 @@ class Plan:
                                             self._ptr(it), ctypes.c_void_p(scratch.data_ptr()),
                                             scratch.numel(), _stream_handle(stream)))
 
+    def backward_static(self, grad_out, grad_in, clip, stream=None, store: Optional[Store] = None):
+        """``backward`` through dp_pix_backward_static: the library's fixed
+        device scratch instead of a scratch tensor (nothing is allocated by
+        the call; calls overlapping on one GPU race)."""
+        self._check_images(grad_out, "grad_out")
+        self._check_images(grad_in, "grad_in")
+        st = self._store(store, stream)
+        gt = self.pointer_table(grad_out, stream)
+        it = self.pointer_table(grad_in, stream)
+        _lib.check(self.lib.dp_pix_backward_static(self.handle, ctypes.byref(st.c), self._ptr(gt),
+                                                   ctypes.c_void_p(clip[0].data_ptr()),
+                                                   ctypes.c_void_p(clip[1].data_ptr()), self._ptr(it),
+                                                   _stream_handle(stream)))
+
     def debug_sums(self, images, stream=None, store: Optional[Store] = None):
         """Forward that also returns dense exact sums (coarse, fine) as uint32 tensors."""
         torch = _torch()

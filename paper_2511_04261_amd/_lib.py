@@ -72,6 +72,7 @@ SYMBOLS = {
     "dp_pix_forward": (_st, [_vp, _vp, _P(Store), _vp, _vp, _vp, _vp]),
     "dp_pix_reconstruct": (_st, [_vp, _P(Store), _vp, _vp]),
     "dp_pix_backward": (_st, [_vp, _P(Store), _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    "dp_pix_backward_static": (_st, [_vp, _P(Store), _vp, _vp, _vp, _vp, _vp]),
     "dp_pix_plan_set_launch": (_st, [_vp, ctypes.c_int32, ctypes.c_int32]),
     "dp_pix_graph_create": (_st, [_vp, _vp, _vp, _P(Store), _vp, _vp, _P(_vp)]),
     "dp_pix_graph_launch": (_st, [_vp, _vp]),

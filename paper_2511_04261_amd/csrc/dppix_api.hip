@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <string>
@@ -40,6 +41,7 @@ constexpr int64_t kTileLdsMax = 150 * 1024;
 constexpr int kMaxDim = 1 << 24;
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+size_t grad_scratch_need(dppix_plan_t p);
 
 }  // namespace
 
@@ -429,7 +431,7 @@ dppix_status_t dp_pix_plan_sizes(dppix_plan_t p, dppix_sizes_t* out)
     out->flag_bytes = (size_t)p->total_cells;
     out->clip_bytes_bg = p->bg_cap;
     out->clip_bytes_fg = p->fg_cap;
-    out->grad_scratch_bytes = align256(4 * p->bg_cap) + align256(4 * p->fg_cap) + align256(4 * (size_t)p->total_cells);
+    out->grad_scratch_bytes = grad_scratch_need(p);
     out->metrics_scratch_bytes = align256(16 * (size_t)p->n_tiles);
     out->n_tiles = p->n_tiles;
     out->total_pixels = p->total_pixels;
@@ -610,6 +612,63 @@ hipError_t for_groups(dppix_plan_t p, const TileArgs& base, bool rec, Launch lau
     return hipSuccess;
 }
 
+// Scratch of dp_pix_backward: gradient of every statistic (bg, fg in store
+// order) and the class-local index of every grid cell.
+size_t grad_scratch_need(dppix_plan_t p)
+{
+    return align256(4 * p->bg_cap) + align256(4 * p->fg_cap) + align256(4 * (size_t)p->total_cells);
+}
+
+dppix_status_t check_backward(dppix_plan_t p, const dppix_store_t* store, const float* const* grad_out,
+                              const uint8_t* clip_bg, const uint8_t* clip_fg, float* const* grad_in)
+{
+    dppix_status_t st = need_bound(p);
+    if (st != DPPIX_OK)
+        return st;
+    if (p->any_u8)
+        return fail(DPPIX_EINVAL, "backward needs every frame in F32_CHW layout");
+    if (grad_out == nullptr || grad_in == nullptr || clip_bg == nullptr || clip_fg == nullptr)
+        return fail(DPPIX_EINVAL, "grad_out, grad_in and clip bits are required");
+    return check_store(store, true);
+}
+
+dppix_status_t run_backward(dppix_plan_t p, const dppix_store_t* store, const float* const* grad_out,
+                            const uint8_t* clip_bg, const uint8_t* clip_fg, float* const* grad_in, uint8_t* sc,
+                            dppix_stream_t stream);
+
+// Fixed device scratch of dp_pix_backward_static, for callers that cannot
+// allocate.  Each device holds its own copy of the array from the library's
+// load until the process ends.  In host code `scratch` names a host-side
+// stand-in: kernels get the device address that hipGetSymbolAddress returns
+// for the current device, looked up once per device and kept.
+constexpr size_t kStaticScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) uint8_t scratch[kStaticScratchBytes];
+
+std::mutex g_scratch_mu;
+std::vector<uint8_t*> g_scratch_ptr;  // per device; nullptr until looked up
+
+dppix_status_t static_scratch(uint8_t** out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return dev_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((size_t)dev >= g_scratch_ptr.size())
+        g_scratch_ptr.resize((size_t)dev + 1, nullptr);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return dev_fail(e, "hipGetSymbolAddress(scratch)");
+        if (ptr == nullptr || (reinterpret_cast<uintptr_t>(ptr) & 255) != 0)
+            return fail(DPPIX_EDEVICE, "device scratch has no 256-byte aligned address");
+        g_scratch_ptr[dev] = static_cast<uint8_t*>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return DPPIX_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -695,19 +754,39 @@ dppix_status_t dp_pix_backward(dppix_plan_t p, const dppix_store_t* store, const
                                const uint8_t* clip_bg, const uint8_t* clip_fg, float* const* grad_in, void* scratch,
                                size_t scratch_bytes, dppix_stream_t stream)
 {
-    dppix_status_t st = need_bound(p);
+    dppix_status_t st = check_backward(p, store, grad_out, clip_bg, clip_fg, grad_in);
     if (st != DPPIX_OK)
         return st;
-    if (p->any_u8)
-        return fail(DPPIX_EINVAL, "backward needs every frame in F32_CHW layout");
-    if (grad_out == nullptr || grad_in == nullptr || clip_bg == nullptr || clip_fg == nullptr)
-        return fail(DPPIX_EINVAL, "grad_out, grad_in and clip bits are required");
-    if ((st = check_store(store, true)) != DPPIX_OK)
-        return st;
-    const size_t need = align256(4 * p->bg_cap) + align256(4 * p->fg_cap) + align256(4 * (size_t)p->total_cells);
-    if (scratch == nullptr || scratch_bytes < need)
+    if (scratch == nullptr || scratch_bytes < grad_scratch_need(p))
         return fail(DPPIX_ENOMEM, "scratch smaller than grad_scratch_bytes");
-    uint8_t* sc = static_cast<uint8_t*>(scratch);
+    return run_backward(p, store, grad_out, clip_bg, clip_fg, grad_in, static_cast<uint8_t*>(scratch), stream);
+}
+
+dppix_status_t dp_pix_backward_static(dppix_plan_t p, const dppix_store_t* store, const float* const* grad_out,
+                                      const uint8_t* clip_bg, const uint8_t* clip_fg, float* const* grad_in,
+                                      dppix_stream_t stream)
+{
+    dppix_status_t st = check_backward(p, store, grad_out, clip_bg, clip_fg, grad_in);
+    if (st != DPPIX_OK)
+        return st;
+    if (grad_scratch_need(p) > kStaticScratchBytes)
+        return fail(DPPIX_ENOMEM, "backward needs " + std::to_string(grad_scratch_need(p)) +
+                                      " bytes of scratch; the fixed device scratch holds " +
+                                      std::to_string(kStaticScratchBytes) + " (use dp_pix_backward)");
+    uint8_t* sc = nullptr;
+    if ((st = static_scratch(&sc)) != DPPIX_OK)
+        return st;
+    return run_backward(p, store, grad_out, clip_bg, clip_fg, grad_in, sc, stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+dppix_status_t run_backward(dppix_plan_t p, const dppix_store_t* store, const float* const* grad_out,
+                            const uint8_t* clip_bg, const uint8_t* clip_fg, float* const* grad_in, uint8_t* sc,
+                            dppix_stream_t stream)
+{
     TileArgs a = base_args(p, store);
     a.grad_out = grad_out;
     a.grad_in = grad_in;
@@ -736,6 +815,10 @@ dppix_status_t dp_pix_backward(dppix_plan_t p, const dppix_store_t* store, const
     }
     return DPPIX_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 dppix_status_t dp_pix_debug_sums(dppix_plan_t p, const void* const* images, const dppix_store_t* store,
                                  uint32_t* coarse, uint32_t* fine, dppix_stream_t stream)
