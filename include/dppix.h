@@ -164,6 +164,8 @@ typedef struct {
     int64_t total_pixels;    /* sum of height*width                             */
     size_t metrics_scratch_bytes; /* device scratch for dp_pix_metrics          */
     size_t store_state_bytes; /* dppix_store_t.state of each store              */
+    int64_t forward_launches; /* kernel launches of one dp_pix_forward (one per group
+                                 of frames sharing layout, channels and workgroup size) */
 } dppix_sizes_t;
 
 typedef struct {

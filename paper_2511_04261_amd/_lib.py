@@ -43,7 +43,7 @@ class Sizes(ctypes.Structure):
                 ("clip_bytes_bg", ctypes.c_size_t), ("clip_bytes_fg", ctypes.c_size_t),
                 ("grad_scratch_bytes", ctypes.c_size_t), ("n_tiles", ctypes.c_int64),
                 ("total_pixels", ctypes.c_int64), ("metrics_scratch_bytes", ctypes.c_size_t),
-                ("store_state_bytes", ctypes.c_size_t)]
+                ("store_state_bytes", ctypes.c_size_t), ("forward_launches", ctypes.c_int64)]
 
 
 class FrameInfo(ctypes.Structure):

@@ -45,6 +45,18 @@ def tile_candidates(fp: FrameParams) -> List[int]:
     return sorted(out)
 
 
+def with_tile_bytes(frames: Sequence[FrameParams], tile_bytes: int) -> List[FrameParams]:
+    """The frames with tile rows of about `tile_bytes` (0: the library's choice)."""
+    if tile_bytes == 0:
+        return [replace(fp, tile_cells=0) for fp in frames]
+    out = []
+    for fp in frames:
+        unit = fp.b * fp.channels if fp.layout == U8_HWC else 4 * fp.b
+        gc = -(-fp.width // fp.b)
+        out.append(replace(fp, tile_cells=int(min(gc, max(1, tile_bytes // unit)))))
+    return out
+
+
 def _device_name(device) -> str:
     import torch
     return torch.cuda.get_device_name(device).replace(" ", "_")
@@ -158,29 +170,30 @@ class Autotuner:
         return best
 
     def tune_whole_batch(self, frames: Sequence[FrameParams], imgs, masks,
-                         tile_bytes: Sequence[int] = (0, 1024, 1536, 3072, 4096)) -> Tuple[List[FrameParams], dict]:
+                         tile_bytes: Sequence[int] = (0, 1024, 1536, 3072, 4096),
+                         margin: float = 0.01) -> Tuple[List[FrameParams], dict]:
         """Tile shapes for one batch as it will run: every frame's tile row is
         about `tile_bytes` long (0: the library's choice), for each candidate
         and workgroup size the whole batch is timed (plan + forward on its own
         images and masks), and the fastest wins.  Per-class tuning on
         separate small batches does not see how classes share the GPU in a
-        mixed batch; this does, at the cost of one timing per candidate."""
+        mixed batch; this does, at the cost of one timing per candidate.
+        The library's own choice (tile_bytes 0, threads 0) is kept unless a
+        candidate beats it by more than `margin`, so that timing noise does
+        not flip the shapes from run to run."""
         results = []
         for tb in tile_bytes:
-            if tb == 0:
-                cand = [replace(fp, tile_cells=0) for fp in frames]
-            else:
-                cand = []
-                for fp in frames:
-                    unit = fp.b * fp.channels if fp.layout == U8_HWC else 4 * fp.b
-                    gc = -(-fp.width // fp.b)
-                    cand.append(replace(fp, tile_cells=int(min(gc, max(1, tb // unit)))))
+            cand = with_tile_bytes(frames, tb)
             for th in self.threads:
                 for pers in self.launch_modes:
                     ms = time_config(cand, imgs, masks, self.device, th, pers, self.reps)
                     results.append((ms, tb, th, pers, cand))
         results.sort(key=lambda r: r[0])
-        ms, tb, th, pers, cand = results[0]
+        default = [r for r in results if r[1] == 0 and r[2] == 0 and r[3] == 0]
+        best = results[0]
+        if default and best[0] > (1.0 - margin) * default[0][0]:
+            best = default[0]
+        ms, tb, th, pers, cand = best
         info = dict(ms=ms, tile_bytes=tb, threads=th, persistent=pers,
                     tried=[dict(ms=round(r[0], 4), tile_bytes=r[1], threads=r[2], persistent=r[3]) for r in results])
         return list(cand), info

@@ -190,6 +190,32 @@ void choose_tiles(FrameRec& F, int32_t requested)
     F.cunits = (int32_t)(((F.GR + cnb - 1) / cnb) * ((F.TX + F.ctx - 1) / F.ctx));
 }
 
+// XCD-aware tile order within one launch's scheduling range [lo, hi): the
+// dispatcher hands workgroup i of a launch to XCD i mod kXcds, and each XCD
+// has its own L2.  Neighbouring tiles of a band share the cache lines their
+// rows are cut at (rows whose pitch or tile width is not a whole number of
+// lines), so the map gives every XCD runs of kXcdRun consecutive tiles:
+// within each chunk of kXcds * kXcdRun workgroups, workgroup i takes tile
+// (i mod kXcds) * kXcdRun + i / kXcds of the chunk.  A shared line is then
+// fetched once, by one L2, while both tiles are in flight.  The last partial
+// chunk keeps the linear order.
+constexpr int64_t kXcds = 8;
+constexpr int64_t kXcdRun = 8;
+
+void xcd_runs(int32_t* map, int64_t lo, int64_t hi)
+{
+    const int64_t n = hi - lo, chunk = kXcds * kXcdRun;
+    const int64_t full = (n / chunk) * chunk;
+    std::vector<int32_t> tmp(2 * (size_t)full);
+    for (int64_t i = 0; i < full; ++i) {
+        const int64_t c = i / chunk, w = i - c * chunk;
+        const int64_t t = c * chunk + (w % kXcds) * kXcdRun + w / kXcds;
+        tmp[2 * i] = map[2 * (lo + t)];
+        tmp[2 * i + 1] = map[2 * (lo + t) + 1];
+    }
+    std::copy(tmp.begin(), tmp.end(), map + 2 * lo);
+}
+
 // Workgroup size of a frame's forward and reconstruction tiles.  A u8 tile
 // with few phase-1 items (strips x groups of subgrid rows, e.g. b = 16 or
 // narrow frames) keeps more tiles in flight per CU with 128 lanes; larger
@@ -406,6 +432,8 @@ dppix_status_t dp_pix_plan_create(const dppix_frame_desc_t* descs, int32_t n_fra
             map[2 * i] = order[k];
             map[2 * i + 1] = (int32_t)(i - p->sched_base[k]);
         }
+    for (const LaunchGroup& g : p->groups)
+        xcd_runs(map, g.lo, g.hi);
     if (!border.empty())
         std::memcpy(p->host_tables.data() + w.border_map, border.data(), sizeof(int32_t) * border.size());
     int32_t* umap = reinterpret_cast<int32_t*>(p->host_tables.data() + w.unit_map);
@@ -435,6 +463,7 @@ dppix_status_t dp_pix_plan_sizes(dppix_plan_t p, dppix_sizes_t* out)
     out->metrics_scratch_bytes = align256(16 * (size_t)p->n_tiles);
     out->n_tiles = p->n_tiles;
     out->total_pixels = p->total_pixels;
+    out->forward_launches = (int64_t)p->groups.size();
     return DPPIX_OK;
 }
 

@@ -53,6 +53,7 @@ class Request:
     error: Optional[str] = None
     nbytes: int = 0
     state: Any = None            # backend bookkeeping
+    timing: Optional[dict] = None  # backend's split of the in-flight time (ms)
 
     @property
     def latency(self) -> Optional[float]:
@@ -188,11 +189,31 @@ class Scheduler:
 
 
 def latency_stats(reqs: List[Request]) -> Dict[str, float]:
-    lat = np.array([r.latency for r in reqs if r.latency is not None and r.error is None])
+    """Percentiles of arrival -> result latency over the requests that
+    finished, and where that time went: waiting for memory (arrival ->
+    admitted), waiting for a batch slot while the frame's copy runs (admitted
+    -> launched), in flight (launched -> done), and the backend's own split of
+    the in-flight time when it records one (``Request.timing``)."""
+    ok = [r for r in reqs if r.latency is not None and r.error is None]
+    lat = np.array([r.latency for r in ok])
     if lat.size == 0:
         return dict(n=0)
-    return dict(n=int(lat.size), p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3),
-                max_ms=float(lat.max() * 1e3), mean_ms=float(lat.mean() * 1e3))
+    out = dict(n=int(lat.size), p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3),
+               max_ms=float(lat.max() * 1e3), mean_ms=float(lat.mean() * 1e3))
+    parts = {"queue": [r.admitted - r.arrival for r in ok if r.admitted is not None],
+             "wait_launch": [r.launched - r.admitted for r in ok if r.launched is not None and r.admitted is not None],
+             "in_flight": [r.done - r.launched for r in ok if r.launched is not None]}
+    for name, vals in parts.items():
+        if vals:
+            v = np.asarray(vals) * 1e3
+            out["split_%s_mean_ms" % name] = float(v.mean())
+            out["split_%s_p99_ms" % name] = float(np.percentile(v, 99))
+    keys = sorted({k for r in ok if r.timing for k in r.timing})
+    for k in keys:
+        v = np.asarray([r.timing[k] for r in ok if r.timing and k in r.timing])
+        out["split_%s_mean_ms" % k] = float(v.mean())
+        out["split_%s_p99_ms" % k] = float(np.percentile(v, 99))
+    return out
 
 
 # ---------------------------------------------------------------------------
@@ -202,7 +223,17 @@ class GpuBackend:
     """Frames are copied host->device on a copy stream at admission; a batch
     waits for its copies on the compute stream, runs plan + forward (optionally
     with the fused reconstruction), and its store is copied back on the copy
-    stream into pinned host memory."""
+    stream into pinned host memory.
+
+    Plans stay bound on the device and are reused: a batch is ordered by
+    frame geometry, and its plan is looked up by the sequence of geometries
+    (frames of one geometry are interchangeable in a plan).  The frames'
+    Philox counters reach the kernels through the store's noise array (one
+    pinned upload of 16 bytes per frame), so a cached plan serves any frames
+    of its composition.  Each plan keeps a few stores, one per batch in
+    flight."""
+
+    MAX_PLANS = 64
 
     def __init__(self, device=None, reconstruct: bool = False, persistent: int = 0):
         import torch
@@ -215,10 +246,18 @@ class GpuBackend:
         self.copy_stream = torch.cuda.Stream(self.device)
         self.compute_stream = torch.cuda.Stream(self.device)
         self._pool: Dict[tuple, List[Any]] = collections.defaultdict(list)
+        self._plans: "collections.OrderedDict[tuple, dict]" = collections.OrderedDict()
+        self.plans_built = 0
+        self.plan_hits = 0
 
     def frame_params(self, r: Request):
         return self.dp.FrameParams(r.height, r.width, r.channels, self.dp.U8_HWC, r.b, r.sb, r.m, r.eps_bg,
                                    r.eps_fg, r.tau, self.dp.PAD_SYMMETRIC, r.seed, r.frame_index)
+
+    @staticmethod
+    def geometry_key(r: Request) -> tuple:
+        """Everything of a frame that its plan depends on (not its counter)."""
+        return (r.height, r.width, r.channels, r.b, r.sb, r.m, r.eps_bg, r.eps_fg, r.tau)
 
     def validate(self, r: Request) -> Optional[str]:
         lib = self.dp._lib.load()
@@ -259,39 +298,83 @@ class GpuBackend:
             ev.record(self.copy_stream)
         r.state = dict(img=img, mask=mk, ev=ev)
 
+    def _plan_for(self, keys: tuple, reqs: List[Request]) -> dict:
+        """The cached plan of this composition (built and bound on a miss)."""
+        ent = self._plans.get(keys)
+        if ent is not None:
+            self._plans.move_to_end(keys)
+            self.plan_hits += 1
+            return ent
+        plan = self.dp.Plan([self.frame_params(r) for r in reqs], device=self.device, persistent=self.persistent)
+        ent = dict(plan=plan, free=[])
+        self._plans[keys] = ent
+        self.plans_built += 1
+        while len(self._plans) > self.MAX_PLANS:
+            _, old = self._plans.popitem(last=False)
+            old["plan"].close()
+        return ent
+
+    def _store_for(self, ent: dict) -> dict:
+        """A store of the plan that no batch in flight uses, with its device
+        noise array and the pinned host buffer that fills it."""
+        if ent["free"]:
+            return ent["free"].pop()
+        torch = self.torch
+        n = len(ent["plan"].frames)
+        noise = torch.zeros((n, 2), dtype=torch.int64, device=self.device)
+        return dict(store=ent["plan"].new_store(noise=noise), noise=noise,
+                    host_noise=torch.zeros((n, 2), dtype=torch.int64).pin_memory())
+
     def launch(self, batch: List[Request]):
         torch = self.torch
-        frames = [self.frame_params(r) for r in batch]
+        t_host = time.perf_counter()
+        order = sorted(range(len(batch)), key=lambda i: self.geometry_key(batch[i]))
+        reqs = [batch[i] for i in order]
+        keys = tuple(self.geometry_key(r) for r in reqs)
+        ent = self._plan_for(keys, reqs)
+        plan = ent["plan"]
+        st = self._store_for(ent)
+        hn = st["host_noise"].numpy()
+        for i, r in enumerate(reqs):
+            hn[i, 0] = np.int64(np.uint64(r.seed & (2**64 - 1)).view(np.int64))
+            hn[i, 1] = np.int64(np.uint64(r.frame_index & (2**64 - 1)).view(np.int64))
         with torch.cuda.stream(self.compute_stream):
-            for r in batch:
+            for r in reqs:
                 self.compute_stream.wait_event(r.state["ev"])
-            plan = self.dp.Plan(frames, device=self.device, persistent=self.persistent)
-            imgs = [r.state["img"] for r in batch]
-            masks = [r.state["mask"] for r in batch]
+            start = torch.cuda.Event(enable_timing=True)
+            start.record(self.compute_stream)
+            st["noise"].copy_(st["host_noise"], non_blocking=True)
+            imgs = [r.state["img"] for r in reqs]
+            masks = [r.state["mask"] for r in reqs]
             outs = [self._buf(tuple(t.shape), torch.uint8) for t in imgs] if self.reconstruct else None
-            plan.plan(masks if any(m is not None for m in masks) else None)
-            plan.forward(imgs, out=outs)
-            done = torch.cuda.Event()
+            plan.plan(masks if any(m is not None for m in masks) else None, store=st["store"])
+            plan.forward(imgs, out=outs, store=st["store"])
+            done = torch.cuda.Event(enable_timing=True)
             done.record(self.compute_stream)
         # store back to pinned host memory on the copy stream
+        store = st["store"]
         with torch.cuda.stream(self.copy_stream):
             self.copy_stream.wait_event(done)
-            host = dict(counts=plan.counts.to("cpu", non_blocking=True), bg=plan.bg.to("cpu", non_blocking=True),
-                        fg=plan.fg.to("cpu", non_blocking=True), flags=plan.flags.to("cpu", non_blocking=True))
+            host = dict(counts=store.counts.to("cpu", non_blocking=True), bg=store.bg.to("cpu", non_blocking=True),
+                        fg=store.fg.to("cpu", non_blocking=True), flags=store.flags.to("cpu", non_blocking=True))
             if outs is not None:
                 host["recon"] = [o.to("cpu", non_blocking=True) for o in outs]
-            fin = torch.cuda.Event()
+            fin = torch.cuda.Event(enable_timing=True)
             fin.record(self.copy_stream)
-        return dict(plan=plan, host=host, fin=fin, outs=outs, batch=batch)
+        host_ms = (time.perf_counter() - t_host) * 1e3
+        return dict(ent=ent, st=st, host=host, start=start, done=done, fin=fin, outs=outs, order=order,
+                    host_ms=host_ms, batch=batch)
 
     def poll(self, handle) -> bool:
         return handle["fin"].query()
 
     def collect(self, handle) -> List[dict]:
-        plan, host = handle["plan"], handle["host"]
+        plan, host = handle["ent"]["plan"], handle["host"]
         counts = host["counts"].numpy()
         bg, fg, flags = host["bg"].numpy(), host["fg"].numpy(), host["flags"].numpy()
-        res = []
+        timing = dict(host_launch=handle["host_ms"], gpu=handle["start"].elapsed_time(handle["done"]),
+                      d2h=handle["done"].elapsed_time(handle["fin"]))
+        res: List[Optional[dict]] = [None] * len(handle["order"])
         for f, (fp, fi) in enumerate(zip(plan.frames, plan.info)):
             nb, nf, ob, of = (int(x) for x in counts[f])
             C, nn = fp.channels, fi.n * fi.n
@@ -300,11 +383,13 @@ class GpuBackend:
                 fg=fg[of: of + nf * nn * C].reshape(nf, nn, C).copy(), counts=(nb, nf))
             if "recon" in host:
                 d["recon"] = host["recon"][f].numpy()
-            res.append(d)
+            res[handle["order"][f]] = d
+        for r in handle["batch"]:
+            r.timing = dict(timing)
         if handle["outs"] is not None:
             for o in handle["outs"]:
                 self._pool[(tuple(o.shape), self.torch.uint8)].append(o)
-        plan.close()
+        handle["ent"]["free"].append(handle["st"])
         return res
 
     def release(self, r: Request):

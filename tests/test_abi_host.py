@@ -51,7 +51,7 @@ int main(void) {
   printf("dppix_frame_info_t size %zu 0\n", sizeof(dppix_frame_info_t));
   F(dppix_frame_desc_t, pitch); F(dppix_frame_desc_t, eps_bg); F(dppix_frame_desc_t, seed);
   F(dppix_frame_desc_t, frame_index); F(dppix_frame_desc_t, tile_cells);
-  F(dppix_sizes_t, n_tiles); F(dppix_sizes_t, total_pixels); F(dppix_sizes_t, store_state_bytes);
+  F(dppix_sizes_t, n_tiles); F(dppix_sizes_t, total_pixels); F(dppix_sizes_t, store_state_bytes); F(dppix_sizes_t, forward_launches);
   F(dppix_store_t, counts); F(dppix_store_t, state); F(dppix_store_t, noise);
   F(dppix_frame_info_t, cell_offset); F(dppix_frame_info_t, sigma_fg);
   return 0;

@@ -171,6 +171,23 @@ def test_latency_stats():
     assert st["n"] == 100 and abs(st["p50_ms"] - 50.5) < 1e-9 and abs(st["p99_ms"] - 99.01) < 1e-9
 
 
+def test_latency_split():
+    """The split of each latency: memory wait, launch wait, in flight, and
+    the backend's own timing keys, each with mean and p99."""
+    rs = []
+    for i in range(10):
+        r = Request(i, 0, i, 1, 1, 1, 1, 1, 1, 1.0, 1.0, 1, 0, arrival=0.0)
+        r.admitted, r.launched, r.done = 0.001 * i, 0.002 * i, 0.004 * i
+        r.timing = dict(gpu=0.5, d2h=float(i))
+        rs.append(r)
+    st = latency_stats(rs)
+    assert abs(st["split_queue_mean_ms"] - 4.5) < 1e-9
+    assert abs(st["split_wait_launch_mean_ms"] - 4.5) < 1e-9
+    assert abs(st["split_in_flight_mean_ms"] - 9.0) < 1e-9
+    assert st["split_gpu_mean_ms"] == 0.5 and st["split_gpu_p99_ms"] == 0.5
+    assert abs(st["split_d2h_p99_ms"] - np.percentile(np.arange(10.0), 99)) < 1e-9
+
+
 def test_stream_counters_unique_and_resumable(tmp_path):
     """Every (stream, frame) gets its own Philox counter; a saved and
     restored counter state continues each stream where it stopped."""
