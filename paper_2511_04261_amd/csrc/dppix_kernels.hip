@@ -117,7 +117,14 @@ __device__ __forceinline__ double ln_unit(double x)
 // Laplace CDF (Eq. 9) in fp64.
 __device__ __forceinline__ double laplace_sample(const FrameRec& F, uint32_t id, int ch, int level, double sigma)
 {
-    const uint4 w = philox10(make_uint4(id, (uint32_t)ch | ((uint32_t)level << 8), F.fi0, F.fi1), F.key0, F.key1);
+    // The key is one frame's, the same in every lane.  The empty asm makes it
+    // opaque here, so the ten round keys are recomputed by one scalar add per
+    // round instead of being hoisted out of the caller's release loop: there
+    // they would take 20 scalar registers the tile kernels do not have, and
+    // be spilled to vector lanes and read back by a vector instruction each.
+    uint32_t k0 = F.key0, k1 = F.key1;
+    asm volatile("" : "+s"(k0), "+s"(k1));
+    const uint4 w = philox10(make_uint4(id, (uint32_t)ch | ((uint32_t)level << 8), F.fi0, F.fi1), k0, k1);
     const uint64_t bits = ((uint64_t)w.y << 32) | (uint64_t)w.x;
     const double u = (double)(((bits >> 12) << 1) | 1ull) * 0x1p-53;
     // one log per lane: the two tails differ only in its argument and sign
@@ -193,14 +200,18 @@ __device__ __forceinline__ void lds_barrier()
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
+// Bytes 1 and 3 of a dword in the low bytes of its two 16-bit halves: one
+// byte permute (selector bytes 1, zero, 3, zero) instead of a shift and a mask.
+__device__ __forceinline__ uint32_t odd_bytes(uint32_t w) { return __builtin_amdgcn_perm(0u, w, 0x0C030C01u); }
+
 // Add the bytes of one 16-byte strip into 16-bit lane pairs: e[d] holds bytes
 // 4d and 4d+2, o[d] bytes 4d+1 and 4d+3.
 __device__ __forceinline__ void acc_bytes(const v4u& w, uint32_t (&e)[4], uint32_t (&o)[4])
 {
-    e[0] += w.x & 0x00FF00FFu; o[0] += (w.x >> 8) & 0x00FF00FFu;
-    e[1] += w.y & 0x00FF00FFu; o[1] += (w.y >> 8) & 0x00FF00FFu;
-    e[2] += w.z & 0x00FF00FFu; o[2] += (w.z >> 8) & 0x00FF00FFu;
-    e[3] += w.w & 0x00FF00FFu; o[3] += (w.w >> 8) & 0x00FF00FFu;
+    e[0] += w.x & 0x00FF00FFu; o[0] += odd_bytes(w.x);
+    e[1] += w.y & 0x00FF00FFu; o[1] += odd_bytes(w.y);
+    e[2] += w.z & 0x00FF00FFu; o[2] += odd_bytes(w.z);
+    e[3] += w.w & 0x00FF00FFu; o[3] += odd_bytes(w.w);
 }
 
 // Nonzero bytes of a dword as 0/1 bytes.
@@ -728,6 +739,19 @@ __device__ __forceinline__ void strip_rows_q(const uint8_t* base, uint32_t off, 
         for (int d = 0; d < 4; ++d)
             e[j][d] = o[j][d] = 0u;
     v4u w[Q * S];
+    if (qq == Q) {
+        // every row of the item (the common case): no per-load guards
+#pragma unroll
+        for (int i = 0; i < Q * S; ++i)
+            w[i] = ld16_nt(base + (off + (uint32_t)i * upitch));
+#pragma unroll
+        for (int i = 0; i < Q * S; ++i)
+            acc_bytes(w[i], e[i / S], o[i / S]);
+#pragma unroll
+        for (int j = 0; j < Q; ++j)
+            store_colsums16(dst + j * rowbuf, e[j], o[j]);
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < Q * S; ++i)
         if (i < qq * S)
