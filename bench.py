@@ -396,6 +396,8 @@ def run_kernel_legs(plan, imgs, masks, outs, reps=20):
     rec_ms = time_launches(rec, reps, stream)
     edge_out = [torch.empty_like(m) for m in masks]
     edge_ms = time_launches(lambda: plan.edge_masks(imgs, 24, out=edge_out), reps, stream)
+    labels_ms = time_launches(lambda: plan.plan_labels(imgs, 24), reps, stream)
+    plan.plan(masks)
     met_ms = time_launches(lambda: plan.metrics(imgs, outs), reps, stream)
     plan_call, _ = plan.bound_calls(masks, imgs, outs, stream)
     plan_ms = time_launches(plan_call, reps, stream)
@@ -406,6 +408,9 @@ def run_kernel_legs(plan, imgs, masks, outs, reps=20):
                                        note="store read (statistics + flags), frames written (3 B/px)"),
         "edge_mask": kernel_entry("k_edge_mask<3>", edge_ms, ab["image"] + ab["mask"],
                                   note="frames read (3 B/px), mask written (1 B/px)"),
+        "plan_labels": kernel_entry("k_plan_labels + k_scan_prefix", labels_ms, ab["image"] + ab["cells"],
+                                    launches=2, note="frames read (3 B/px), flags written (1 B/cell); "
+                                                     "replaces edge_mask followed by plan"),
         "metrics": kernel_entry("k_metrics<3>", met_ms, 2 * ab["image"],
                                 note="frame and reconstruction read (3 + 3 B/px)"),
     }

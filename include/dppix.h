@@ -216,6 +216,22 @@ dppix_status_t dp_pix_plan_bind(dppix_plan_t plan, void* workspace, size_t bytes
 dppix_status_t dp_pix_plan(dppix_plan_t plan, const uint8_t* const* masks, const dppix_store_t* store,
                            dppix_stream_t stream);
 
+/* dp_pix_plan with the region mask computed from the frames in the same pass
+ * (Sec. VI-A: the mask may come from an edge detector such as the Sobel
+ * operator): a cell's count is the number of its b x b mirror-padded positions
+ * whose pixel is an edge pixel by the rule of dp_pix_edge_mask (a padded
+ * position takes the label of the real pixel it folds onto; NONE counts real
+ * positions only).  Gives exactly the flags, counts and state of
+ * dp_pix_edge_mask followed by dp_pix_plan on its masks, without writing or
+ * reading an H x W mask.
+ *   images     device array of n_frames device pointers (U8_HWC frames only)
+ *   threshold  0..4096, per-channel units, as dp_pix_edge_mask
+ * A label computed from the frame depends on the data: the released flags
+ * then carry information the Laplace noise does not cover.
+ * Kernels only: safe under stream capture. */
+dppix_status_t dp_pix_plan_labels(dppix_plan_t plan, const void* const* images, int32_t threshold,
+                                  const dppix_store_t* store, dppix_stream_t stream);
+
 /* Rebuild a store's counts and state from its flags alone (Table IV: the
  * flags are the grid layout), for a store whose flags and statistics were
  * written elsewhere, e.g. decoded from its serialised form: frames are

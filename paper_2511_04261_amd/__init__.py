@@ -250,7 +250,10 @@ class Plan:
 
     MAX_TABLES = 64
 
-    def __init__(self, frames: Sequence[FrameParams], device=None, threads: int = 0, persistent: int = 0):
+    def __init__(self, frames: Sequence[FrameParams], device=None, threads: int = 0, persistent: int = 0,
+                 default_store: bool = True):
+        """default_store=False: no store is allocated for the plan itself
+        (every call then names its own ``Store``)."""
         import collections
         torch = _torch()
         self.lib = _lib.load()
@@ -279,7 +282,15 @@ class Plan:
         _lib.check(self.lib.dp_pix_plan_bind(self.handle, ctypes.c_void_p(self.workspace.data_ptr()),
                                              self.workspace.numel(), _stream_handle(setup)))
         self._tables = collections.OrderedDict()
-        self.store = Store(self)
+        self._default = Store(self) if default_store else None
+
+    @property
+    def store(self) -> Store:
+        """The plan's default store (allocated on first use when the plan was
+        made without one)."""
+        if self._default is None:
+            self._default = Store(self)
+        return self._default
 
     # default store's buffers, for callers that use one store per plan
     @property
@@ -386,6 +397,15 @@ class Plan:
         st = self._store(store, stream)
         tab = self.pointer_table(masks, stream)
         _lib.check(self.lib.dp_pix_plan(self.handle, self._ptr(tab), ctypes.byref(st.c), _stream_handle(stream)))
+
+    def plan_labels(self, images, threshold: int, stream=None, store: Optional[Store] = None):
+        """Classify cells from the frames' Sobel labels in the same pass (no
+        mask written): the flags ``edge_masks`` followed by ``plan`` would give."""
+        self._check_images(images, "images")
+        st = self._store(store, stream)
+        it = self.pointer_table(images, stream)
+        _lib.check(self.lib.dp_pix_plan_labels(self.handle, self._ptr(it), int(threshold), ctypes.byref(st.c),
+                                               _stream_handle(stream)))
 
     def index_store(self, store: Optional[Store] = None, stream=None):
         """Rebuild a store's counts and state from its flags (a store loaded

@@ -66,6 +66,7 @@ SYMBOLS = {
     "dp_pix_plan_frame_info": (_st, [_vp, ctypes.c_int32, _P(FrameInfo)]),
     "dp_pix_plan_bind": (_st, [_vp, _vp, ctypes.c_size_t, _vp]),
     "dp_pix_plan": (_st, [_vp, _vp, _P(Store), _vp]),
+    "dp_pix_plan_labels": (_st, [_vp, _vp, ctypes.c_int32, _P(Store), _vp]),
     "dp_pix_store_index": (_st, [_vp, _P(Store), _vp]),
     "dp_pix_noise_advance": (_st, [_vp, ctypes.c_int32, ctypes.c_uint64, _vp]),
     "dp_pix_edge_mask": (_st, [_vp, _vp, ctypes.c_int32, _vp, _vp]),

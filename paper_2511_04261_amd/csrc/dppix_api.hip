@@ -719,6 +719,30 @@ dppix_status_t dp_pix_plan(dppix_plan_t p, const uint8_t* const* masks, const dp
     return DPPIX_OK;
 }
 
+dppix_status_t dp_pix_plan_labels(dppix_plan_t p, const void* const* images, int32_t threshold,
+                                  const dppix_store_t* store, dppix_stream_t stream)
+{
+    dppix_status_t st = need_bound(p);
+    if (st != DPPIX_OK)
+        return st;
+    if (p->any_f32)
+        return fail(DPPIX_EINVAL, "labels are computed from U8_HWC frames");
+    if (images == nullptr)
+        return fail(DPPIX_EINVAL, "images is NULL");
+    if (threshold < 0 || threshold > 4 * 1024)
+        return fail(DPPIX_EINVAL, "threshold must be in 0..4096");
+    if ((st = check_store(store, false)) != DPPIX_OK)
+        return st;
+    TileArgs a = base_args(p, store);
+    a.images = images;
+    a.edge_threshold = threshold;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = launch_plan_labels(a, p->n_units, plain_threads(p), p->lds[kPlan], p->prefix_scan, s);
+    if (e != hipSuccess)
+        return dev_fail(e, "plan launch");
+    return DPPIX_OK;
+}
+
 dppix_status_t dp_pix_store_index(dppix_plan_t p, const dppix_store_t* store, dppix_stream_t stream)
 {
     dppix_status_t st = need_bound(p);

@@ -178,6 +178,17 @@ __device__ __forceinline__ int fold(int x, int L, int mode)
 // by its real pixel count.
 constexpr int kPadNone = 2;
 
+// Mirror index of a coordinate in [-1, 2L) for the Sobel stencil: -1 mirrors
+// like the frame's own padding, the unpadded mode mirrors like the symmetric one.
+__device__ __forceinline__ int edge_fold(int x, int L, int mode)
+{
+    if (mode == kPadNone)   // the Sobel stencil mirrors like the symmetric mode
+        mode = 0;
+    if (x < 0)
+        return (mode == 0 || L == 1) ? 0 : 1;
+    return fold(x, L, mode);
+}
+
 // Real-pixel area of the statistic whose (sub)cell starts at padded (y0, x0)
 // with the given side: side^2 when the frame is mirror-padded; h*w real
 // pixels in the unpadded mode (0 for a subcell wholly past the frame).
@@ -560,9 +571,12 @@ __device__ void plan_count(const TileArgs& a, const FrameRec& F, const uint8_t* 
     }
 }
 
-__global__ __launch_bounds__(kMaxThreads) void k_plan(TileArgs a)
+// One plan unit: its cell counters cleared, counted by `count(F, f, r0, nb, c0,
+// KC, KCs, cellcnt)`, then every cell flagged (count >= tau) and the complex
+// cells of every tile counted.
+template <typename Count>
+__device__ __forceinline__ void plan_unit(const TileArgs& a, uint8_t* lds, Count count)
 {
-    extern __shared__ __align__(16) uint8_t lds[];
     const int tid = threadIdx.x, NT = blockDim.x;
     const int f = (int)uniform_u32((uint32_t)a.unit_map[2 * (int64_t)blockIdx.x]);
     const int lu = (int)uniform_u32((uint32_t)a.unit_map[2 * (int64_t)blockIdx.x + 1]);
@@ -585,9 +599,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_plan(TileArgs a)
     if (blockIdx.x == 0 && tid < kTicketWords)
         a.ticket[tid] = 0u;
     lds_barrier();
-    const uint8_t* mask = a.masks ? a.masks[f] : nullptr;
-    if (mask != nullptr)
-        plan_count(a, F, mask, r0, nb, c0, KC, KCs, cellcnt);
+    count(F, f, r0, nb, c0, KC, KCs, cellcnt);
     lds_barrier();
     for (int i = tid; i < nb * KC; i += NT) {
         const int j = i / KC, kc = i - j * KC;
@@ -604,6 +616,181 @@ __global__ __launch_bounds__(kMaxThreads) void k_plan(TileArgs a)
         const int j = i / nt, ti = i - j * nt;
         a.tile_cnt[F.tile_base + (int64_t)(r0 + j) * F.TX + t0 + ti] = tcnt[j * F.ctx + ti];
     }
+}
+
+__global__ __launch_bounds__(kMaxThreads) void k_plan(TileArgs a)
+{
+    extern __shared__ __align__(16) uint8_t lds[];
+    plan_unit(a, lds, [&](const FrameRec& F, int f, int r0, int nb, int c0, int KC, int KCs, uint32_t* cellcnt) {
+        const uint8_t* mask = a.masks ? a.masks[f] : nullptr;
+        if (mask != nullptr)
+            plan_count(a, F, mask, r0, nb, c0, KC, KCs, cellcnt);
+    });
+}
+
+// --------------------------------------------------------------------------
+// Plan from complexity labels (Sec. VI-A names an edge detector such as the
+// Sobel operator as a source of the region mask), in the same pass: a cell's
+// count is the number of edge pixels among its b x b mirror-padded
+// positions, each position taking the label of the real pixel it folds onto
+// (the label dp_pix_edge_mask writes).  No mask is written or read.  The 3x3
+// stencil evaluated on the padded grid of channel sums, every coordinate
+// folded as the label's border rule folds it (edge_fold), gives exactly the
+// label of the folded pixel: a mirror maps the pair of neighbours of a padded
+// position onto the pair of neighbours of its image, at most swapped, and a
+// swap only flips the sign of Gy.  So each chunk of padded rows and columns is
+// staged as channel sums in LDS (one halo row and column on every side) and
+// counted without knowing which positions are real.
+// --------------------------------------------------------------------------
+constexpr int kLabRows = 32;                      // padded rows per chunk (within one band)
+constexpr int kLabCols = 256;                     // padded columns per chunk
+constexpr int kLabPad = 8;                        // LDS columns before column 0 (16-byte aligned rows)
+constexpr int kLabStride = kLabCols + 2 * kLabPad;
+
+// Channel sums of 16 consecutive pixels from their 16 C bytes, as eight
+// dwords of two 16-bit sums each (pixel 2k low, 2k + 1 high).
+template <int C>
+__device__ __forceinline__ void pixel_sums16(const v4u (&w)[C], v4u& lo, v4u& hi)
+{
+    uint32_t d[4 * C];
+#pragma unroll
+    for (int i = 0; i < C; ++i) {
+        d[4 * i + 0] = w[i].x;
+        d[4 * i + 1] = w[i].y;
+        d[4 * i + 2] = w[i].z;
+        d[4 * i + 3] = w[i].w;
+    }
+    uint32_t sum[16];
+#pragma unroll
+    for (int px = 0; px < 16; ++px) {
+        uint32_t t = 0u;
+#pragma unroll
+        for (int ch = 0; ch < C; ++ch) {
+            const int q = px * C + ch;
+            t += (d[q >> 2] >> (8 * (q & 3))) & 0xFFu;
+        }
+        sum[px] = t;
+    }
+    lo = v4u{sum[0] | (sum[1] << 16), sum[2] | (sum[3] << 16), sum[4] | (sum[5] << 16), sum[6] | (sum[7] << 16)};
+    hi = v4u{sum[8] | (sum[9] << 16), sum[10] | (sum[11] << 16), sum[12] | (sum[13] << 16),
+             sum[14] | (sum[15] << 16)};
+}
+
+template <int C>
+__device__ void plan_count_labels(const TileArgs& a, const FrameRec& F, const uint8_t* img, int r0, int nb, int c0,
+                                  int KC, int KCs, uint32_t* cellcnt, uint16_t* S)
+{
+    const int tid = threadIdx.x, NT = blockDim.x;
+    const int b = F.b, H = F.H, W = F.W, pad = F.pad;
+    const int64_t pitch = F.pitch;
+    const int thr = a.edge_threshold * C;
+    const int X0 = c0 * b, XW = KC * b;
+    const int R = min(b, kLabRows);
+    const bool aligned = ((reinterpret_cast<uintptr_t>(img) | (uintptr_t)pitch) & 15) == 0;
+    // b a power of two up to 64: chunks start on cell boundaries and the
+    // lanes of one cell add their counts by shuffles first (one LDS atomic
+    // per cell and chunk instead of one per lane)
+    const bool groups = (b & (b - 1)) == 0 && b <= 64;
+    for (int j = 0; j < nb; ++j) {
+        const int band0 = (r0 + j) * b;
+        for (int k0 = 0; k0 < b; k0 += R) {
+            const int rows = min(R, b - k0);
+            const int py0 = band0 + k0;
+            // unpadded mode: rows past the frame are absent
+            const int ylim = pad == kPadNone ? min(rows, H - py0) : rows;
+            if (ylim <= 0)
+                break;
+            for (int cx = 0; cx < XW; cx += kLabCols) {
+                const int cols = min(kLabCols, XW - cx);
+                const int px0 = X0 + cx;
+                // staged row yy is padded row py0 - 1 + yy, staged column xx
+                // padded column px0 + xx (xx = -1 .. cols); whole 16-pixel
+                // groups inside the frame are read as vectors
+                const int gfast = (aligned && (px0 & 15) == 0) ? max(0, min(cols, W - px0)) >> 4 : 0;
+                for (int it = tid; it < (rows + 2) * gfast; it += NT) {
+                    const int yy = it / gfast, g = it - yy * gfast;
+                    const int ry = edge_fold(py0 - 1 + yy, H, pad);
+                    const uint8_t* src = img + (int64_t)ry * pitch + (int64_t)(px0 + 16 * g) * C;
+                    v4u w[C];
+#pragma unroll
+                    for (int i = 0; i < C; ++i)
+                        w[i] = ld16_nt(src + 16 * i);
+                    v4u lo, hi;
+                    pixel_sums16<C>(w, lo, hi);
+                    v4u* dst = reinterpret_cast<v4u*>(S + yy * kLabStride + kLabPad + 16 * g);
+                    dst[0] = lo;
+                    dst[1] = hi;
+                }
+                // the left halo column and every column from 16 * gfast on
+                // (right edge, folded, misaligned): one pixel per item
+                const int nrest = cols + 2 - 16 * gfast;
+                for (int it = tid; it < (rows + 2) * nrest; it += NT) {
+                    const int yy = it / nrest, q = it - yy * nrest;
+                    const int xx = q == 0 ? -1 : 16 * gfast + q - 1;
+                    const int ry = edge_fold(py0 - 1 + yy, H, pad);
+                    const int rx = edge_fold(px0 + xx, W, pad);
+                    const uint8_t* px = img + (int64_t)ry * pitch + (int64_t)rx * C;
+                    uint32_t sum = 0u;
+#pragma unroll
+                    for (int ch = 0; ch < C; ++ch)
+                        sum += px[ch];
+                    S[yy * kLabStride + kLabPad + xx] = (uint16_t)sum;
+                }
+                lds_barrier();
+                // one lane per padded column, down the chunk's rows: Sobel
+                // Gx = dx(-1) + 2 dx(0) + dx(+1), Gy = sx(+1) - sx(-1), with
+                // dx(r) = S[r][+1] - S[r][-1], sx(r) = S[r][-1] + 2 S[r][0] + S[r][+1]
+                for (int xb = 0; xb < cols; xb += NT) {
+                    const int x = xb + tid;
+                    uint32_t cnt = 0u;
+                    if (x < cols && (pad != kPadNone || px0 + x < W)) {
+                        const uint16_t* col = S + kLabPad + x;
+                        int dxa = (int)col[1] - (int)col[-1];
+                        int sxa = (int)col[-1] + 2 * (int)col[0] + (int)col[1];
+                        col += kLabStride;
+                        int dxb = (int)col[1] - (int)col[-1];
+                        int sxb = (int)col[-1] + 2 * (int)col[0] + (int)col[1];
+                        for (int y = 0; y < ylim; ++y) {
+                            col += kLabStride;
+                            const int dxc = (int)col[1] - (int)col[-1];
+                            const int sxc = (int)col[-1] + 2 * (int)col[0] + (int)col[1];
+                            const int gx = dxa + 2 * dxb + dxc, gy = sxc - sxa;
+                            cnt += (uint32_t)(abs(gx) + abs(gy) >= thr);
+                            dxa = dxb;
+                            sxa = sxb;
+                            dxb = dxc;
+                            sxb = sxc;
+                        }
+                    }
+                    const int cell = (cx + x) / b;
+                    if (groups) {
+                        for (int m = 1; m < b; m <<= 1)
+                            cnt += __shfl_xor(cnt, m, 64);
+                        if ((tid & (b - 1)) == 0 && cnt != 0u && cell < KC)
+                            atomicAdd(cellcnt + j * KCs + cell, cnt);
+                    } else if (cnt != 0u && cell < KC) {
+                        atomicAdd(cellcnt + j * KCs + cell, cnt);
+                    }
+                }
+                lds_barrier();
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(kMaxThreads) void k_plan_labels(TileArgs a)
+{
+    extern __shared__ __align__(16) uint8_t lds[];
+    __shared__ __align__(16) uint16_t S[(kLabRows + 2) * kLabStride];
+    plan_unit(a, lds, [&](const FrameRec& F, int f, int r0, int nb, int c0, int KC, int KCs, uint32_t* cellcnt) {
+        const uint8_t* img = static_cast<const uint8_t*>(a.images[f]);
+        switch (F.C) {
+        case 1: plan_count_labels<1>(a, F, img, r0, nb, c0, KC, KCs, cellcnt, S); break;
+        case 2: plan_count_labels<2>(a, F, img, r0, nb, c0, KC, KCs, cellcnt, S); break;
+        case 3: plan_count_labels<3>(a, F, img, r0, nb, c0, KC, KCs, cellcnt, S); break;
+        default: plan_count_labels<4>(a, F, img, r0, nb, c0, KC, KCs, cellcnt, S); break;
+        }
+    });
 }
 
 // One workgroup per frame: exclusive scan of the per-tile complex counts into
@@ -1781,15 +1968,6 @@ __global__ __launch_bounds__(kMaxThreads) void k_backward_mirror(TileArgs a)
 constexpr int kEdgeRows = 8;
 constexpr int kEdgeCols = 512;
 
-// Mirror index of a coordinate in [-1, 2L).
-__device__ __forceinline__ int edge_fold(int x, int L, int mode)
-{
-    if (mode == kPadNone)   // the Sobel stencil mirrors like the symmetric mode
-        mode = 0;
-    if (x < 0)
-        return (mode == 0 || L == 1) ? 0 : 1;
-    return fold(x, L, mode);
-}
 
 template <int C>
 __device__ void edge_tile(const TileArgs& a, const FrameRec& F, const TileCoord& tc, uint16_t* S)
@@ -2057,6 +2235,21 @@ hipError_t launch_plan(const TileArgs& a, int64_t n_units, int threads, size_t l
     if (e != hipSuccess)
         return e;
     hipLaunchKernelGGL(k_plan, dim3((unsigned)n_units), dim3(threads), lds, s, a);
+    e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    return launch_scan(a, prefix_scan, s);
+}
+
+hipError_t launch_plan_labels(const TileArgs& a, int64_t n_units, int threads, size_t lds, bool prefix_scan,
+                              hipStream_t s)
+{
+    if (n_units == 0)
+        return hipSuccess;
+    hipError_t e = allow_lds(k_plan_labels, lds);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_plan_labels, dim3((unsigned)n_units), dim3(threads), lds, s, a);
     e = hipGetLastError();
     if (e != hipSuccess)
         return e;

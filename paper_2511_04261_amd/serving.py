@@ -233,7 +233,7 @@ class GpuBackend:
     of its composition.  Each plan keeps a few stores, one per batch in
     flight."""
 
-    MAX_PLANS = 64
+    MAX_PLANS = 512
 
     def __init__(self, device=None, reconstruct: bool = False, persistent: int = 0):
         import torch
@@ -305,7 +305,8 @@ class GpuBackend:
             self._plans.move_to_end(keys)
             self.plan_hits += 1
             return ent
-        plan = self.dp.Plan([self.frame_params(r) for r in reqs], device=self.device, persistent=self.persistent)
+        plan = self.dp.Plan([self.frame_params(r) for r in reqs], device=self.device, persistent=self.persistent,
+                            default_store=False)
         ent = dict(plan=plan, free=[])
         self._plans[keys] = ent
         self.plans_built += 1

@@ -1,0 +1,113 @@
+"""GPU tests of the plan from complexity labels (dp_pix_plan_labels): the
+Sobel label of every mirror-padded position counted in the plan pass, with no
+mask written.  Its flags, counts and store index must equal, bit for bit,
+those of dp_pix_edge_mask followed by dp_pix_plan on the same frames, and the
+whole path driven by it must match the oracle driven by the oracle's own
+labels (flags and counts exact, statistics within 1e-3, uint8 within 1 LSB)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from tests.helpers import compare_frame, oracle_params
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+dp = pytest.importorskip("paper_2511_04261_amd")
+from paper_2511_04261_amd import synth  # noqa: E402
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+# (H, W, C, b, s_b, threshold, pad): padded and unpadded borders, b a power of
+# two (lane groups) and not (12, 48), b above the 32-row chunk (64, 128),
+# frames smaller than a cell, rows whose pitch is no multiple of 16 bytes
+# (37 x 53 x 3) and a full 1080p frame
+CASES = [(75, 97, 3, 16, 4, 60, 0), (270, 480, 3, 32, 8, 40, 0), (33, 40, 1, 8, 2, 30, 1),
+         (1080, 1920, 3, 32, 8, 48, 0), (5, 3, 3, 8, 4, 10, 0), (45, 70, 3, 16, 4, 40, 2),
+         (61, 83, 3, 12, 4, 50, 0), (130, 300, 3, 64, 16, 40, 1), (37, 53, 3, 16, 8, 30, 0),
+         (200, 333, 1, 128, 32, 20, 0), (96, 144, 4, 48, 16, 35, 1), (29, 31, 2, 32, 8, 25, 2),
+         (1, 1, 3, 4, 2, 0, 0), (7, 260, 3, 16, 4, 45, 1)]
+
+
+def _frames(seed):
+    r = np.random.Generator(np.random.PCG64(seed))
+    imgs = []
+    for (H, W, C, b, sb, T, pad) in CASES:
+        img = synth.gradient_image(r, H, W, C)
+        img[H // 4: H // 2 + 1, W // 5: W // 2 + 1] = 250    # a bright block: strong edges
+        imgs.append(img)
+    return imgs
+
+
+def _run(dev, threshold_of, threads=0, seed=41):
+    imgs = _frames(seed)
+    frames = [dp.FrameParams(H, W, C, dp.U8_HWC, b=b, sb=sb, m=16, eps_bg=1.0, eps_fg=0.3, tau=3, pad_mode=pad,
+                             seed=6, frame_index=i) for i, (H, W, C, b, sb, T, pad) in enumerate(CASES)]
+    plan = dp.Plan(frames, device=dev, threads=threads)
+    ti = [torch.from_numpy(x).to(dev) for x in imgs]
+    T = threshold_of(frames)
+    # two-step path: masks written, then planned from them
+    s_two = plan.new_store()
+    masks = plan.edge_masks(ti, T)
+    plan.plan(masks, store=s_two)
+    # fused path
+    s_one = plan.new_store()
+    plan.plan_labels(ti, T, store=s_one)
+    outs = [torch.empty_like(t) for t in ti]
+    plan.forward(ti, out=outs, store=s_one)
+    torch.cuda.synchronize()
+    return plan, imgs, s_one, s_two, outs, T
+
+
+def test_plan_labels_equals_edge_mask_then_plan(dev):
+    """Fused and two-step plans agree bit for bit (flags, per-frame counts
+    and offsets) on one batch of every case, and the fused path's releases,
+    which read the store index it wrote, match the oracle driven by the
+    oracle's labels."""
+    for T in (0, 30, 60):
+        say("case: plan_labels batch of %d frames, threshold %d" % (len(CASES), T))
+        plan, imgs, s_one, s_two, outs, _ = _run(dev, lambda frames: T)
+        assert torch.equal(s_one.flags, s_two.flags)
+        assert torch.equal(s_one.counts, s_two.counts)
+        got = s_one.host()
+        for i, (H, W, C, b, sb, _, pad) in enumerate(CASES):
+            want_mask = oracle.edge_mask(imgs[i], T, pad)
+            want = oracle.forward(imgs[i], want_mask, oracle_params(plan.frames[i]))
+            compare_frame(got[i], want, outs[i].cpu().numpy(), "labels %dx%dx%d b%d pad%d T%d" % (H, W, C, b, pad, T))
+
+
+@pytest.mark.parametrize("threads", [64, 128, 512])
+def test_plan_labels_any_workgroup_size(dev, threads):
+    """Workgroup sizes other than the default give the same flags and counts
+    (lane groups of a cell span several waves at 512 lanes)."""
+    say("case: plan_labels with %d threads" % threads)
+    plan, imgs, s_one, s_two, outs, _ = _run(dev, lambda frames: 40, threads=threads, seed=43)
+    assert torch.equal(s_one.flags, s_two.flags)
+    assert torch.equal(s_one.counts, s_two.counts)
+
+
+def test_plan_labels_rejects_bad_arguments(dev):
+    """Thresholds outside 0..4096 and fp32 frames are refused before any launch."""
+    fp = dp.FrameParams(16, 16, 3, dp.U8_HWC, b=8, sb=4, m=16, eps_bg=1.0, eps_fg=0.3, tau=1)
+    plan = dp.Plan([fp], device=dev)
+    x = torch.zeros((16, 16, 3), dtype=torch.uint8, device=dev)
+    with pytest.raises(dp.DppixError):
+        plan.plan_labels([x], -1)
+    with pytest.raises(dp.DppixError):
+        plan.plan_labels([x], 5000)
+    f32 = dp.Plan([dp.FrameParams(16, 16, 3, dp.F32_CHW, b=8, sb=4, m=16, eps_bg=1.0, eps_fg=0.3, tau=1)],
+                  device=dev)
+    with pytest.raises(dp.DppixError):
+        f32.plan_labels([torch.zeros((3, 16, 16), dtype=torch.float32, device=dev)], 10)
