@@ -117,12 +117,14 @@ __device__ __forceinline__ double ln_unit(double x)
 // Laplace CDF (Eq. 9) in fp64.
 __device__ __forceinline__ double laplace_sample(const FrameRec& F, uint32_t id, int ch, int level, double sigma)
 {
-    // The key is one frame's, the same in every lane.  The empty asm makes it
-    // opaque here, so the ten round keys are recomputed by one scalar add per
-    // round instead of being hoisted out of the caller's release loop: there
-    // they would take 20 scalar registers the tile kernels do not have, and
-    // be spilled to vector lanes and read back by a vector instruction each.
-    uint32_t k0 = F.key0, k1 = F.key1;
+    // The key is one frame's, the same in every lane (readfirstlane states
+    // that, so it sits in scalar registers at any optimisation level).  The
+    // empty asm makes it opaque here, so the ten round keys are recomputed by
+    // one scalar add per round instead of being hoisted out of the caller's
+    // release loop: there they would take 20 scalar registers the tile
+    // kernels do not have, and be spilled to vector lanes and read back by a
+    // vector instruction each.
+    uint32_t k0 = __builtin_amdgcn_readfirstlane(F.key0), k1 = __builtin_amdgcn_readfirstlane(F.key1);
     asm volatile("" : "+s"(k0), "+s"(k1));
     const uint4 w = philox10(make_uint4(id, (uint32_t)ch | ((uint32_t)level << 8), F.fi0, F.fi1), k0, k1);
     const uint64_t bits = ((uint64_t)w.y << 32) | (uint64_t)w.x;
@@ -135,15 +137,17 @@ __device__ __forceinline__ double laplace_sample(const FrameRec& F, uint32_t id,
 
 // Release one statistic: mean = sum / area, plus noise (Eq. 11 scale given by
 // the host), clipped to [0, 255] (Algorithm 3 steps 10, 17), one rounding to
-// fp32.  pass = the clip did not bind (gradient flows).
-__device__ __forceinline__ float release(double sum, double area, int noisy, double sigma, const FrameRec& F,
-                                         uint32_t id, int ch, int level, uint8_t& pass)
+// fp32.  pass = the clip did not bind (gradient flows).  inv_area: 1 / area
+// when that is exact (area a power of two: the product then equals the
+// quotient bit for bit), else 0 (divide).
+__device__ __forceinline__ float release(double sum, double area, double inv_area, int noisy, double sigma,
+                                         const FrameRec& F, uint32_t id, int ch, int level, uint8_t& pass)
 {
     if (area == 0.0) {   // unpadded mode: a subcell with no real pixel releases nothing
         pass = 0;
         return 0.f;
     }
-    const double mu = sum / area;
+    const double mu = inv_area != 0.0 ? sum * inv_area : sum / area;
     const double z = noisy ? mu + laplace_sample(F, id, ch, level, sigma) : mu;
     pass = (uint8_t)(z >= 0.0 && z <= 255.0);
     const double v = z < 0.0 ? 0.0 : (z > 255.0 ? 255.0 : z);
@@ -187,6 +191,13 @@ __device__ __forceinline__ int edge_fold(int x, int L, int mode)
     if (x < 0)
         return (mode == 0 || L == 1) ? 0 : 1;
     return fold(x, L, mode);
+}
+
+// 1 / side^2 when that is exact and every statistic of that side has area
+// side^2 (mirror padding, side a power of two), else 0.
+__device__ __forceinline__ double exact_inv_area(const FrameRec& F, int side)
+{
+    return (F.pad != kPadNone && (side & (side - 1)) == 0) ? 1.0 / ((double)side * (double)side) : 0.0;
 }
 
 // Real-pixel area of the statistic whose (sub)cell starts at padded (y0, x0)
@@ -1050,6 +1061,51 @@ __device__ __forceinline__ void expand_row_u8(uint8_t* exb, int kn, int n, int s
     }
 }
 
+// Sums per channel of one subcell's s_b packed 16-bit column sums of one
+// subgrid row (s_b pixels of C channels, contiguous in LDS).  For even s_b * C
+// the span starts on a dword and is read two columns at a time.
+template <int C>
+__device__ __forceinline__ void subcell_sums(const uint16_t* cp, int s, uint32_t (&S)[C])
+{
+#pragma unroll
+    for (int ch = 0; ch < C; ++ch)
+        S[ch] = 0u;
+    if (((s * C) & 1) != 0) {
+        for (int x = 0; x < s; ++x)
+#pragma unroll
+            for (int ch = 0; ch < C; ++ch)
+                S[ch] += cp[x * C + ch];
+        return;
+    }
+    const uint32_t* w = reinterpret_cast<const uint32_t*>(cp);
+    const int dw = (s * C) >> 1;
+    if (C == 3) {
+        // two pixels per three dwords: (c0 c1) (c2 c0) (c1 c2)
+        for (int k = 0; k < dw; k += 3) {
+            const uint32_t w0 = w[k], w1 = w[k + 1], w2 = w[k + 2];
+            S[0] += (w0 & 0xFFFFu) + (w1 >> 16);
+            S[1 % C] += (w0 >> 16) + (w2 & 0xFFFFu);
+            S[2 % C] += (w1 & 0xFFFFu) + (w2 >> 16);
+        }
+    } else if (C == 1) {
+        for (int k = 0; k < dw; ++k)
+            S[0] += (w[k] & 0xFFFFu) + (w[k] >> 16);
+    } else if (C == 2) {
+        for (int k = 0; k < dw; ++k) {
+            S[0] += w[k] & 0xFFFFu;
+            S[1 % C] += w[k] >> 16;
+        }
+    } else {
+        // C = 4: one pixel per two dwords, (c0 c1) (c2 c3)
+        for (int k = 0; k < dw; k += 2) {
+            S[0] += w[k] & 0xFFFFu;
+            S[1 % C] += w[k] >> 16;
+            S[2 % C] += w[k + 1] & 0xFFFFu;
+            S[3 % C] += w[k + 1] >> 16;
+        }
+    }
+}
+
 // Phase 2a of the u8 forward for even s_b: one lane per subcell column
 // adds, for every subgrid row of the group, the subcell's s_b * C packed
 // 16-bit column sums (contiguous in LDS: s_b pixels of C channels) read two
@@ -1064,43 +1120,14 @@ __device__ __forceinline__ void subcell_sums_pairs(const uint16_t* col16, int ro
                                                    uint32_t* cspart, uint32_t* dbg, int64_t dbg_base, int64_t dbg_row)
 {
     const int tid = threadIdx.x, NT = blockDim.x;
-    const int dw = (s * C) >> 1;   // dwords per (subgrid row, subcell column)
     for (int fc = tid; fc < kn; fc += NT) {
         uint32_t tot[C];
 #pragma unroll
         for (int ch = 0; ch < C; ++ch)
             tot[ch] = fr0 == 0 ? 0u : cspart[fc * C + ch];
         for (int g = 0; g < ng; ++g) {
-            const uint32_t* cp = reinterpret_cast<const uint32_t*>(col16 + g * rowbuf + fc * s * C);
             uint32_t S[C];
-#pragma unroll
-            for (int ch = 0; ch < C; ++ch)
-                S[ch] = 0u;
-            if (C == 3) {
-                // two pixels per three dwords: (c0 c1) (c2 c0) (c1 c2)
-                for (int k = 0; k < dw; k += 3) {
-                    const uint32_t w0 = cp[k], w1 = cp[k + 1], w2 = cp[k + 2];
-                    S[0] += (w0 & 0xFFFFu) + (w1 >> 16);
-                    S[1 % C] += (w0 >> 16) + (w2 & 0xFFFFu);
-                    S[2 % C] += (w1 & 0xFFFFu) + (w2 >> 16);
-                }
-            } else if (C == 1) {
-                for (int k = 0; k < dw; ++k)
-                    S[0] += (cp[k] & 0xFFFFu) + (cp[k] >> 16);
-            } else if (C == 2) {
-                for (int k = 0; k < dw; ++k) {
-                    S[0] += cp[k] & 0xFFFFu;
-                    S[1 % C] += cp[k] >> 16;
-                }
-            } else {
-                // C = 4: one pixel per two dwords, (c0 c1) (c2 c3)
-                for (int k = 0; k < dw; k += 2) {
-                    S[0] += cp[k] & 0xFFFFu;
-                    S[1 % C] += cp[k] >> 16;
-                    S[2 % C] += cp[k + 1] & 0xFFFFu;
-                    S[3 % C] += cp[k + 1] >> 16;
-                }
-            }
+            subcell_sums<C>(col16 + g * rowbuf + fc * s * C, s, S);
 #pragma unroll
             for (int ch = 0; ch < C; ++ch) {
                 tot[ch] += S[ch];
@@ -1158,6 +1185,7 @@ __device__ void forward_tile_u8(const TileArgs& a, const FrameRec& F, const Tile
     const int items = Kt * n * C;
     const int nn = n * n;
     const int rowbuf = 16 * nstr;           // 16-bit column sums of one subgrid row
+    const double area_s = (double)s * (double)s, inv_s = exact_inv_area(F, s);
 
     // ---- subgrid rows, up to kRowGroup at a time: each lane streams its strip
     // down all rows of the group (exact 16-bit column sums per subgrid row,
@@ -1256,31 +1284,37 @@ __device__ void forward_tile_u8(const TileArgs& a, const FrameRec& F, const Tile
         }
         // releases of the complex cells' subcells, spread evenly over the
         // lanes (only complex cells draw noise, so a lane-per-subcell loop
-        // would leave the lanes of simple cells idle); each sum is re-read
-        // from the column sums
+        // would leave the lanes of simple cells idle): one item per (complex
+        // cell, subgrid row, subcell column) re-reads the subcell's column
+        // sums and releases its C channels
         const int ncx = (int)s_ncx;
-        const int per_cx = ng * n * C;
+        const int per_cx = ng * n;
         for (int it = tid; it < ncx * per_cx; it += NT) {
             const int q = it / per_cx;
             const int rem = it - q * per_cx;
-            const int g = rem / (n * C);
-            const int rem2 = rem - g * (n * C);
-            const int jj = rem2 / C, ch = rem2 - jj * C;
+            const int g = rem / n, jj = rem - g * n;
             const int kc = cxl[q];
             const int fc = kc * n + jj, fr = fr0 + g;
-            const uint16_t* cp = col16 + g * rowbuf + fc * s * C + ch;
-            uint32_t S = 0;
-            for (int x = 0; x < s; ++x)
-                S += cp[x * C];
+            uint32_t S[C];
+            subcell_sums<C>(col16 + g * rowbuf + fc * s * C, s, S);
             const uint32_t id = (uint32_t)(r * n + fr) * (uint32_t)(F.GC * n) + (uint32_t)(x0c * n + fc);
-            uint8_t pass;
-            const double area = stat_area(F, r * b + fr * s, x0c * b + fc * s, s);
-            const float v = release((double)S, area, F.noise_fg, F.sigma_fg, F, id, ch, 1, pass);
-            const uint64_t at = fg_base + ((uint64_t)cidx[kc] * nn + fr * n + jj) * C + ch;
-            a.fg[at] = v;
-            if (a.clip_fg)
-                a.clip_fg[at] = pass;
-            vgc[(fr * Kt * n + fc) * C + ch] = to_u8(v);
+            const double area = pad == kPadNone ? stat_area(F, r * b + fr * s, x0c * b + fc * s, s) : area_s;
+            const uint64_t at = fg_base + ((uint64_t)cidx[kc] * nn + fr * n + jj) * C;
+            uint8_t* vd = vgc + (fr * Kt * n + fc) * C;
+            // one channel at a time (unrolled, the C draws would be live at once)
+#pragma unroll 1
+            for (int ch = 0; ch < C; ++ch) {
+                uint32_t Sc = S[0];
+#pragma unroll
+                for (int k = 1; k < C; ++k)
+                    Sc = ch == k ? S[k] : Sc;
+                uint8_t pass;
+                const float v = release((double)Sc, area, inv_s, F.noise_fg, F.sigma_fg, F, id, ch, 1, pass);
+                a.fg[at + ch] = v;
+                if (a.clip_fg)
+                    a.clip_fg[at + ch] = pass;
+                vd[ch] = to_u8(v);
+            }
         }
         lds_barrier();
     }
@@ -1296,8 +1330,8 @@ __device__ void forward_tile_u8(const TileArgs& a, const FrameRec& F, const Tile
         if (!cflag[kc]) {
             const uint32_t id = (uint32_t)(r * F.GC + x0c + kc);
             uint8_t pass;
-            const float v = release((double)S, stat_area(F, r * b, (x0c + kc) * b, b), F.noise_bg, F.sigma_bg, F,
-                                    id, ch, 0, pass);
+            const float v = release((double)S, stat_area(F, r * b, (x0c + kc) * b, b), exact_inv_area(F, b),
+                                    F.noise_bg, F.sigma_bg, F, id, ch, 0, pass);
             const uint64_t at = bg_base + (uint64_t)cidx[kc] * C + ch;
             a.bg[at] = v;
             if (a.clip_bg)
@@ -1422,6 +1456,7 @@ __device__ void forward_tile_f32(const TileArgs& a, const FrameRec& F, const Til
     float* out = a.outs ? static_cast<float*>(a.outs[tc.f]) : nullptr;
     const bool in_aligned = ((reinterpret_cast<uintptr_t>(img) | (uintptr_t)(pitch * 4) | (uintptr_t)(X0 * 4)) & 15) == 0;
 
+    const double inv_s = exact_inv_area(F, s), inv_b = exact_inv_area(F, b);
     const LdsPlan L = lds_plan(kFwdF32, F.K, b, n, C);
     float* colsum = reinterpret_cast<float*>(lds + L.colsum);
     double* cspart = reinterpret_cast<double*>(lds + L.cspart);
@@ -1498,8 +1533,8 @@ __device__ void forward_tile_f32(const TileArgs& a, const FrameRec& F, const Til
                     const int row0 = r * b + fr * s;
                     const uint32_t id = (uint32_t)(r * n + fr) * (uint32_t)(F.GC * n) + (uint32_t)(x0c * n + fc);
                     uint8_t pass;
-                    const float v = release(S, stat_area(F, row0, x0c * b + fc * s, s), F.noise_fg, F.sigma_fg, F, id,
-                                            ch, 1, pass);
+                    const float v = release(S, stat_area(F, row0, x0c * b + fc * s, s), inv_s, F.noise_fg,
+                                            F.sigma_fg, F, id, ch, 1, pass);
                     const uint64_t at = fg_base + ((uint64_t)cidx[kc] * nn + fr * n + jj) * C + ch;
                     a.fg[at] = v;
                     if (a.clip_fg)
@@ -1520,8 +1555,8 @@ __device__ void forward_tile_f32(const TileArgs& a, const FrameRec& F, const Til
             S += cspart[(kc * n + jj) * C + ch];
         const uint32_t id = (uint32_t)(r * F.GC + x0c + kc);
         uint8_t pass;
-        const float v = release(S, stat_area(F, r * b, (x0c + kc) * b, b), F.noise_bg, F.sigma_bg, F, id, ch, 0,
-                                pass);
+        const float v = release(S, stat_area(F, r * b, (x0c + kc) * b, b), inv_b, F.noise_bg, F.sigma_bg, F, id,
+                                ch, 0, pass);
         const uint64_t at = bg_base + (uint64_t)cidx[kc] * C + ch;
         a.bg[at] = v;
         if (a.clip_bg)
