@@ -193,7 +193,11 @@ class Store:
         _use_on((self.bg, self.fg, self.flags, self.counts, self.state, self.noise), self._streams, stream)
 
     def host(self):
-        """Copy the store to the host and split it per frame (synchronises)."""
+        """Copy the store to the host and split it per frame (synchronises).
+        Each frame's dict carries its privacy ledger (budgets per region, the
+        frame's eps by parallel composition, m, C times it for neighbours that
+        differ in whole pixels, and its Philox counter)."""
+        from .store_codec import privacy_ledger
         counts = self.counts.cpu().numpy()
         bg = self.bg.cpu().numpy()
         fg = self.fg.cpu().numpy()
@@ -203,10 +207,12 @@ class Store:
         for f, (fp, fi) in enumerate(zip(frames, info)):
             nb, nf, ob, of = (int(x) for x in counts[f])
             C, nn = fp.channels, fi.n * fi.n
+            eps_fg = fp.eps_bg if fp.eps_fg is None else fp.eps_fg
             out.append(dict(
                 flags=flags[fi.cell_offset: fi.cell_offset + fi.grid_rows * fi.grid_cols].reshape(fi.grid_rows, fi.grid_cols),
                 bg=bg[ob: ob + nb * C].reshape(nb, C), fg=fg[of: of + nf * nn * C].reshape(nf, nn, C),
-                counts=(nb, nf), offsets=(ob, of)))
+                counts=(nb, nf), offsets=(ob, of),
+                ledger=dict(privacy_ledger(C, fp.m, fp.eps_bg, eps_fg), frame_index=fp.frame_index)))
         return out
 
     def load_host(self, per_frame):

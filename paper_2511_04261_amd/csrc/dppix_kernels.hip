@@ -1144,7 +1144,9 @@ __device__ __forceinline__ void subcell_sums_pairs(const uint16_t* col16, int ro
 // ==========================================================================
 // Forward, uint8 HWC (Algorithm 3 steps 7-19, fused steps 11, 18-21).
 // ==========================================================================
-template <int C>
+// DBG: also write the exact sums of every cell and subcell (dp_pix_debug_sums);
+// a separate instantiation, so the release kernel carries none of that state.
+template <int C, bool DBG>
 __device__ void forward_tile_u8(const TileArgs& a, const FrameRec& F, const TileCoord& tc, uint8_t* lds)
 {
     const int tid = threadIdx.x, NT = blockDim.x;
@@ -1262,7 +1264,7 @@ __device__ void forward_tile_u8(const TileArgs& a, const FrameRec& F, const Tile
         lds_barrier();
         // running sums of every (subcell column, channel) for the coarse cells
         if ((s & 1) == 0) {
-            subcell_sums_pairs<C>(col16, rowbuf, Kt * n, s, ng, fr0, cspart, a.dbg_fine,
+            subcell_sums_pairs<C>(col16, rowbuf, Kt * n, s, ng, fr0, cspart, DBG ? a.dbg_fine : nullptr,
                                   F.fine_base + (int64_t)(r * n + fr0) * ((int64_t)F.GC * n) + (int64_t)x0c * n,
                                   (int64_t)F.GC * n);
         } else {
@@ -1275,7 +1277,7 @@ __device__ void forward_tile_u8(const TileArgs& a, const FrameRec& F, const Tile
                     for (int x = 0; x < s; ++x)
                         S += cp[x * C];
                     total += S;
-                    if (a.dbg_fine)
+                    if (DBG && a.dbg_fine)
                         a.dbg_fine[(F.fine_base + (int64_t)(r * n + fr0 + g) * ((int64_t)F.GC * n) +
                                     (int64_t)x0c * n + fc) * C + ch] = S;
                 }
@@ -1325,7 +1327,7 @@ __device__ void forward_tile_u8(const TileArgs& a, const FrameRec& F, const Tile
         uint32_t S = 0;
         for (int jj = 0; jj < n; ++jj)
             S += cspart[(kc * n + jj) * C + ch];
-        if (a.dbg_coarse)
+        if (DBG && a.dbg_coarse)
             a.dbg_coarse[(F.cell_base + (int64_t)r * F.GC + x0c + kc) * C + ch] = S;
         if (!cflag[kc]) {
             const uint32_t id = (uint32_t)(r * F.GC + x0c + kc);
@@ -1608,12 +1610,12 @@ __device__ __forceinline__ void run_tiles(const TileArgs& a, uint8_t* lds, Body 
 
 // Five waves per SIMD: enough resident tiles per CU to keep HBM busy while
 // other waves are in their LDS phases (the register budget still fits).
-template <int C>
+template <int C, bool DBG = false>
 __global__ __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(DPPIX_FWD_WAVES_PER_EU))) void
 k_forward_u8(TileArgs a)
 {
     extern __shared__ __align__(16) uint8_t lds[];
-    run_tiles(a, lds, [&](const FrameRec& F, const TileCoord& tc) { forward_tile_u8<C>(a, F, tc, lds); });
+    run_tiles(a, lds, [&](const FrameRec& F, const TileCoord& tc) { forward_tile_u8<C, DBG>(a, F, tc, lds); });
 }
 
 __global__ __launch_bounds__(kMaxThreads) void k_forward_f32(TileArgs a)
@@ -2060,22 +2062,85 @@ __global__ __launch_bounds__(kMaxThreads) void k_edge_mask(TileArgs a)
 // Utility metrics of the paper's evaluation (Sec. VII-A): MSE and SSIM
 // (Wang et al. 2004; 7 x 7 equal-weight windows fully inside the frame,
 // sample covariances, K1 = 0.01, K2 = 0.03, range 255, channels averaged).
-// With uint8 inputs every window sum of x, y, x^2, y^2 and xy is an integer
-// below 2^24, so the sums are exact (uint32, separable: 7-wide row sums in
-// LDS, then 7-high column sums); only the SSIM expression is fp64.  Each
-// tile writes its partial sums; k_metrics_reduce adds them per frame in tile
-// order (deterministic).
+// With uint8 inputs every window sum of x, y, x^2, y^2 and xy is an integer,
+// so the sums are exact and so are the numerators below; only the final
+// ratio is fp64.  Each tile writes its partial sums; k_metrics_reduce adds
+// them per frame in tile order (deterministic).
+//
+// SSIM of a window from its integer sums s0 = sum x, s1 = sum y, s2 = sum x^2,
+// s3 = sum y^2, s4 = sum xy over np = 49 pixels: with ux = s0/49, the sample
+// variances (49 s2 - s0^2) / (49 * 48) and covariance (49 s4 - s0 s1) / (49 * 48),
+// the four factors of SSIM share the denominators 49^2 and 49 * 48, which
+// cancel:  SSIM = (A B) / (D E) with
+//   A = 2 s0 s1 + 49^2 c1,            B = 2 (49 s4 - s0 s1) + 49 * 48 c2,
+//   D = s0^2 + s1^2 + 49^2 c1,        E = 49 (s2 + s3) - s0^2 - s1^2 + 49 * 48 c2,
+// every integer part below 2^31.
+//
+// A tile's window centres are covered in chunks of one lane per byte column
+// (pixel and channel) and up to kMetRowsMax centre rows; the chunk's rows,
+// with 3 more on each side, are staged in LDS (all of them inside the frame,
+// since every window is).  A lane walks down its column: the 7-wide sums of
+// the five moments of each new row go into a ring of the last 7 rows in
+// registers, and the window sum is updated by the new row minus the row that
+// leaves it.
 // ==========================================================================
-constexpr int kMetRows = 8;     // window-centre rows per chunk
-constexpr int kMetCols = 128;   // window-centre columns per chunk
+constexpr int kMetRowsMax = 32;                 // window-centre rows per chunk
+constexpr int kMetStage = kMetRowsMax + 6;      // staged rows per chunk
+constexpr int kMetCols = 256 + 24;              // staged bytes per row (lanes + 6 pixels of up to 4 channels)
 
 struct MetLds {
-    uint8_t x[kMetRows + 6][kMetCols + 8];
-    uint8_t y[kMetRows + 6][kMetCols + 8];
-    uint32_t h[5][kMetRows + 6][kMetCols];
+    uint8_t x[kMetStage][kMetCols];
+    uint8_t y[kMetStage][kMetCols];
     double red[kMaxThreads / 64];
     unsigned long long red_se[kMaxThreads / 64];
 };
+
+// Squared differences of the 16 bytes of two 16-byte vectors.
+__device__ __forceinline__ uint32_t sq_diff16(const v4u& x, const v4u& y)
+{
+    uint32_t acc = 0u;
+    const uint32_t xs[4] = {x.x, x.y, x.z, x.w}, ys[4] = {y.x, y.y, y.z, y.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int d = (int)((xs[k] >> (8 * q)) & 0xFFu) - (int)((ys[k] >> (8 * q)) & 0xFFu);
+            acc += (uint32_t)(d * d);
+        }
+    return acc;
+}
+
+struct Moments {
+    uint32_t s[5];   // sum x, sum y, sum x^2, sum y^2, sum xy
+};
+
+template <int C>
+__device__ __forceinline__ Moments row_moments(const uint8_t* xr, const uint8_t* yr, int q)
+{
+    Moments m = {{0u, 0u, 0u, 0u, 0u}};
+#pragma unroll
+    for (int d = 0; d < 7; ++d) {
+        const uint32_t u = xr[q + d * C], v = yr[q + d * C];
+        m.s[0] += u;
+        m.s[1] += v;
+        m.s[2] += u * u;
+        m.s[3] += v * v;
+        m.s[4] += u * v;
+    }
+    return m;
+}
+
+__device__ __forceinline__ double ssim_window(const uint32_t (&t)[5])
+{
+    const double c1 = (0.01 * 255.0) * (0.01 * 255.0), c2 = (0.03 * 255.0) * (0.03 * 255.0);
+    const int32_t s0 = (int32_t)t[0], s1 = (int32_t)t[1];
+    const int32_t p01 = s0 * s1, q = s0 * s0 + s1 * s1;
+    const double A = (double)(2 * p01) + 2401.0 * c1;
+    const double B = (double)(2 * (49 * (int32_t)t[4] - p01)) + 2352.0 * c2;
+    const double D = (double)q + 2401.0 * c1;
+    const double E = (double)(49 * (int32_t)(t[2] + t[3]) - q) + 2352.0 * c2;
+    return (A * B) / (D * E);
+}
 
 template <int C>
 __device__ void metrics_tile(const TileArgs& a, const FrameRec& F, const TileCoord& tc, MetLds& L)
@@ -2091,61 +2156,68 @@ __device__ void metrics_tile(const TileArgs& a, const FrameRec& F, const TileCoo
     const int64_t pitch = F.pitch;
     double ssim_acc = 0.0;
     unsigned long long se = 0;
-    // squared error over the tile's real pixels
+    // squared error over the tile's real pixels: 16-byte strips where the
+    // rows allow, single bytes for the rest
     if (y0 < H && xa < W) {
-        const int wpx = (xb - xa) * C;
-        for (int64_t q = tid; q < (int64_t)(y1 - y0) * wpx; q += NT) {
-            const int yy = y0 + (int)(q / wpx), xx = (int)(q % wpx);
-            const int d = (int)X[(int64_t)yy * pitch + (int64_t)xa * C + xx] - (int)Y[(int64_t)yy * pitch + (int64_t)xa * C + xx];
+        const int64_t b0 = (int64_t)xa * C, b1 = (int64_t)xb * C;
+        const bool aligned = ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Y) | (uintptr_t)pitch |
+                               (uintptr_t)b0) & 15) == 0;
+        const int nv = aligned ? (int)((b1 - b0) >> 4) : 0;
+        const int rows = y1 - y0;
+        for (int it = tid; it < rows * nv; it += NT) {
+            const int yy = it / nv, v = it - yy * nv;
+            const int64_t at = (int64_t)(y0 + yy) * pitch + b0 + 16 * v;
+            se += sq_diff16(ld16_nt(X + at), ld16_nt(Y + at));
+        }
+        const int nr = (int)(b1 - b0) - 16 * nv;
+        for (int it = tid; it < rows * nr; it += NT) {
+            const int yy = it / nr, q = it - yy * nr;
+            const int64_t at = (int64_t)(y0 + yy) * pitch + b0 + 16 * nv + q;
+            const int d = (int)X[at] - (int)Y[at];
             se += (unsigned long long)(d * d);
         }
     }
     // SSIM windows centred in this tile's real pixels, 3 away from every edge
     const int cy0 = max(y0, 3), cy1 = min(y1, H - 3);
     const int cx0 = max(xa, 3), cx1 = min(xb, W - 3);
-    const double R = 255.0, c1 = (0.01 * R) * (0.01 * R), c2 = (0.03 * R) * (0.03 * R);
-    for (int ch = 0; ch < C; ++ch)
-        for (int cy = cy0; cy < cy1; cy += kMetRows) {
-            const int rows = min(kMetRows, cy1 - cy);
-            for (int cx = cx0; cx < cx1; cx += kMetCols) {
-                const int cols = min(kMetCols, cx1 - cx);
-                for (int q = tid; q < (rows + 6) * (cols + 6); q += NT) {
-                    const int ly = q / (cols + 6), lx = q - ly * (cols + 6);
-                    const int64_t at = (int64_t)(cy - 3 + ly) * pitch + (int64_t)(cx - 3 + lx) * C + ch;
-                    L.x[ly][lx] = X[at];
-                    L.y[ly][lx] = Y[at];
-                }
-                lds_barrier();
-                for (int q = tid; q < (rows + 6) * cols; q += NT) {
-                    const int ly = q / cols, lx = q - ly * cols;
-                    uint32_t sx = 0, sy = 0, sxx = 0, syy = 0, sxy = 0;
-#pragma unroll
-                    for (int k = 0; k < 7; ++k) {
-                        const uint32_t u = L.x[ly][lx + k], v = L.y[ly][lx + k];
-                        sx += u; sy += v; sxx += u * u; syy += v * v; sxy += u * v;
-                    }
-                    L.h[0][ly][lx] = sx; L.h[1][ly][lx] = sy; L.h[2][ly][lx] = sxx;
-                    L.h[3][ly][lx] = syy; L.h[4][ly][lx] = sxy;
-                }
-                lds_barrier();
-                for (int q = tid; q < rows * cols; q += NT) {
-                    const int ly = q / cols, lx = q - ly * cols;
-                    uint32_t s[5] = {0, 0, 0, 0, 0};
-#pragma unroll
-                    for (int k = 0; k < 7; ++k)
-#pragma unroll
-                        for (int t = 0; t < 5; ++t)
-                            s[t] += L.h[t][ly + k][lx];
-                    const double np = 49.0;
-                    const double ux = s[0] / np, uy = s[1] / np;
-                    const double vx = ((double)s[2] / np - ux * ux) * np / (np - 1.0);
-                    const double vy = ((double)s[3] / np - uy * uy) * np / (np - 1.0);
-                    const double vxy = ((double)s[4] / np - ux * uy) * np / (np - 1.0);
-                    ssim_acc += ((2.0 * ux * uy + c1) * (2.0 * vxy + c2)) / ((ux * ux + uy * uy + c1) * (vx + vy + c2));
-                }
-                lds_barrier();
+    const int CW = min(NT / C, kMetCols / C - 6);   // window-centre pixels per chunk (lanes, and the staged row)
+    for (int cxb = cx0; cxb < cx1; cxb += CW) {
+        const int cw = min(CW, cx1 - cxb);
+        const int sb = (cw + 6) * C;                        // staged bytes per row
+        const int64_t bx = (int64_t)(cxb - 3) * C;
+        for (int cyb = cy0; cyb < cy1; cyb += kMetRowsMax) {
+            const int rb = min(kMetRowsMax, cy1 - cyb);
+            const int nrs = rb + 6;
+            for (int it = tid; it < nrs * sb; it += NT) {
+                const int k = it / sb, q = it - k * sb;
+                const int64_t at = (int64_t)(cyb - 3 + k) * pitch + bx + q;
+                L.x[k][q] = X[at];
+                L.y[k][q] = Y[at];
             }
+            lds_barrier();
+            const int q = tid;
+            if (q < cw * C) {
+                Moments ring[7];
+                uint32_t t[5] = {0u, 0u, 0u, 0u, 0u};
+                for (int k0 = 0; k0 < nrs; k0 += 7) {
+#pragma unroll
+                    for (int j = 0; j < 7; ++j) {
+                        const int k = k0 + j;
+                        if (k < nrs) {
+                            const Moments h = row_moments<C>(L.x[k], L.y[k], q);
+#pragma unroll
+                            for (int m = 0; m < 5; ++m)
+                                t[m] += h.s[m] - (k >= 7 ? ring[j].s[m] : 0u);
+                            ring[j] = h;
+                            if (k >= 6)
+                                ssim_acc += ssim_window(t);
+                        }
+                    }
+                }
+            }
+            lds_barrier();
         }
+    }
     // workgroup reduction in a fixed order
     const int lane = tid & 63, wid = tid >> 6;
     for (int d = 32; d > 0; d >>= 1) {
@@ -2158,13 +2230,13 @@ __device__ void metrics_tile(const TileArgs& a, const FrameRec& F, const TileCoo
     }
     lds_barrier();
     if (tid == 0) {
-        double t = 0.0;
+        double tt = 0.0;
         unsigned long long e = 0;
         for (int w = 0; w < (NT + 63) / 64; ++w) {
-            t += L.red[w];
+            tt += L.red[w];
             e += L.red_se[w];
         }
-        a.met_partial[2 * tc.t] = t;
+        a.met_partial[2 * tc.t] = tt;
         reinterpret_cast<unsigned long long*>(a.met_partial)[2 * tc.t + 1] = e;
     }
     lds_barrier();
@@ -2319,6 +2391,14 @@ hipError_t launch_forward(const TileArgs& a, int layout, int C, int threads, siz
 {
     if (layout == 1)
         return launch_tiles(k_forward_f32, a, threads, lds, grid, s);
+    if (a.dbg_coarse != nullptr || a.dbg_fine != nullptr) {
+        switch (C) {
+        case 1: return launch_tiles(k_forward_u8<1, true>, a, threads, lds, grid, s);
+        case 2: return launch_tiles(k_forward_u8<2, true>, a, threads, lds, grid, s);
+        case 3: return launch_tiles(k_forward_u8<3, true>, a, threads, lds, grid, s);
+        default: return launch_tiles(k_forward_u8<4, true>, a, threads, lds, grid, s);
+        }
+    }
     switch (C) {
     case 1: return launch_tiles(k_forward_u8<1>, a, threads, lds, grid, s);
     case 2: return launch_tiles(k_forward_u8<2>, a, threads, lds, grid, s);

@@ -27,6 +27,8 @@ from typing import Any, Deque, Dict, List, Optional
 
 import numpy as np
 
+from .store_codec import privacy_ledger
+
 
 @dataclass
 class Request:
@@ -317,14 +319,16 @@ class GpuBackend:
 
     def _store_for(self, ent: dict) -> dict:
         """A store of the plan that no batch in flight uses, with its device
-        noise array and the pinned host buffer that fills it."""
+        table and the pinned host buffer that fills it: per frame the noise
+        counters (seed, frame_index), then the image, mask and output pointer
+        arrays the kernels read (one host-to-device copy per batch)."""
         if ent["free"]:
             return ent["free"].pop()
         torch = self.torch
         n = len(ent["plan"].frames)
-        noise = torch.zeros((n, 2), dtype=torch.int64, device=self.device)
-        return dict(store=ent["plan"].new_store(noise=noise), noise=noise,
-                    host_noise=torch.zeros((n, 2), dtype=torch.int64).pin_memory())
+        table = torch.zeros(5 * n, dtype=torch.int64, device=self.device)
+        return dict(store=ent["plan"].new_store(noise=table[: 2 * n].view(n, 2)), table=table,
+                    host=torch.zeros(5 * n, dtype=torch.int64).pin_memory())
 
     def launch(self, batch: List[Request]):
         torch = self.torch
@@ -335,21 +339,32 @@ class GpuBackend:
         ent = self._plan_for(keys, reqs)
         plan = ent["plan"]
         st = self._store_for(ent)
-        hn = st["host_noise"].numpy()
+        n = len(reqs)
+        ht = st["host"].numpy().view(np.uint64)
+        outs = [self._buf(tuple(r.state["img"].shape), torch.uint8) for r in reqs] if self.reconstruct else None
+        any_mask = False
         for i, r in enumerate(reqs):
-            hn[i, 0] = np.int64(np.uint64(r.seed & (2**64 - 1)).view(np.int64))
-            hn[i, 1] = np.int64(np.uint64(r.frame_index & (2**64 - 1)).view(np.int64))
+            ht[2 * i] = r.seed & (2**64 - 1)
+            ht[2 * i + 1] = r.frame_index & (2**64 - 1)
+            ht[2 * n + i] = r.state["img"].data_ptr()
+            mk = r.state["mask"]
+            ht[3 * n + i] = 0 if mk is None else mk.data_ptr()
+            any_mask = any_mask or mk is not None
+            ht[4 * n + i] = 0 if outs is None else outs[i].data_ptr()
+        lib, h, sc = plan.lib, plan.handle, ctypes.byref(st["store"].c)
+        base = st["table"].data_ptr()
+        imgs_p = ctypes.c_void_p(base + 8 * 2 * n)
+        masks_p = ctypes.c_void_p(base + 8 * 3 * n) if any_mask else None
+        outs_p = ctypes.c_void_p(base + 8 * 4 * n) if outs is not None else None
         with torch.cuda.stream(self.compute_stream):
             for r in reqs:
                 self.compute_stream.wait_event(r.state["ev"])
             start = torch.cuda.Event(enable_timing=True)
             start.record(self.compute_stream)
-            st["noise"].copy_(st["host_noise"], non_blocking=True)
-            imgs = [r.state["img"] for r in reqs]
-            masks = [r.state["mask"] for r in reqs]
-            outs = [self._buf(tuple(t.shape), torch.uint8) for t in imgs] if self.reconstruct else None
-            plan.plan(masks if any(m is not None for m in masks) else None, store=st["store"])
-            plan.forward(imgs, out=outs, store=st["store"])
+            st["table"].copy_(st["host"], non_blocking=True)
+            sh = ctypes.c_void_p(self.compute_stream.cuda_stream)
+            self.dp._lib.check(lib.dp_pix_plan(h, masks_p, sc, sh))
+            self.dp._lib.check(lib.dp_pix_forward(h, imgs_p, sc, None, None, outs_p, sh))
             done = torch.cuda.Event(enable_timing=True)
             done.record(self.compute_stream)
         # store back to pinned host memory on the copy stream
@@ -384,6 +399,10 @@ class GpuBackend:
                 fg=fg[of: of + nf * nn * C].reshape(nf, nn, C).copy(), counts=(nb, nf))
             if "recon" in host:
                 d["recon"] = host["recon"][f].numpy()
+            # the request's own parameters: a cached plan's frame records keep
+            # the counters of the batch it was built for
+            r = handle["batch"][handle["order"][f]]
+            d["ledger"] = dict(privacy_ledger(C, r.m, r.eps_bg, r.eps_fg), frame_index=r.frame_index)
             res[handle["order"][f]] = d
         for r in handle["batch"]:
             r.timing = dict(timing)

@@ -226,6 +226,12 @@ def test_serving_alone_equals_mix(dev):
     done = serve_streams(streams, sch, params, keep_results=True)
     assert not sch.rejected and len(done) > 100
     assert max(sch.batch_sizes) > 1
+    for q in done:
+        # every served frame carries its privacy ledger (Thm. 1: max of the
+        # region budgets per channel value, C times that per whole pixel)
+        led = q.result["ledger"]
+        assert (led["eps_bg"], led["eps_fg"], led["eps_frame"], led["eps_pixel"], led["m"]) == (1.0, 0.3, 1.0, 3.0, 16)
+        assert led["frame_index"] == q.frame_index
     r = np.random.Generator(np.random.PCG64(5))
     for k in r.choice(len(done), size=12, replace=False):
         q = done[int(k)]

@@ -26,18 +26,23 @@ def dev():
     return torch.device("cuda:0")
 
 
-def test_metrics_match_oracle(dev):
+@pytest.mark.parametrize("threads", [0, 512])
+def test_metrics_match_oracle(dev, threads):
     """MSE exact (integer squared errors), SSIM within 1e-9 of the oracle, on
-    a mixed batch of frames and their DP reconstructions."""
-    say("case: metrics")
+    a mixed batch of frames and their DP reconstructions (every channel count,
+    rows with and without 16-byte alignment, frames at and below the 7 x 7
+    window, tiles taller than one chunk of window rows at b = 64)."""
+    say("case: metrics, threads", threads)
     r = np.random.Generator(np.random.PCG64(31))
-    shapes = [(64, 80, 3), (37, 300, 1), (270, 480, 3), (7, 7, 2), (5, 30, 3), (1080, 1920, 3)]
+    shapes = [(64, 80, 3), (37, 300, 1), (270, 480, 3), (7, 7, 2), (5, 30, 3), (1080, 1920, 3), (45, 71, 4),
+              (33, 50, 2), (200, 130, 3)]
     frames, imgs = [], []
     for i, (H, W, C) in enumerate(shapes):
-        frames.append(dp.FrameParams(H, W, C, dp.U8_HWC, b=16, sb=4, m=16, eps_bg=1.0, eps_fg=0.3, tau=1, seed=4,
+        b = 64 if (H, W) == (200, 130) else 16
+        frames.append(dp.FrameParams(H, W, C, dp.U8_HWC, b=b, sb=4, m=16, eps_bg=1.0, eps_fg=0.3, tau=1, seed=4,
                                      frame_index=i))
         imgs.append(synth.gradient_image(r, H, W, C))
-    plan = dp.Plan(frames, device=dev)
+    plan = dp.Plan(frames, device=dev, threads=threads)
     ti = [torch.from_numpy(x).to(dev) for x in imgs]
     outs = [torch.empty_like(t) for t in ti]
     plan.plan(None)
@@ -53,7 +58,7 @@ def test_metrics_match_oracle(dev):
             assert got[i, 0] == pytest.approx(((imgs[i].astype(float) - rec.astype(float)) ** 2).mean(), rel=1e-15)
             assert got[i, 1] == 0.0
     same = plan.metrics(ti, ti).cpu().numpy()
-    assert (same[:, 0] == 0).all() and np.allclose(same[[0, 1, 2, 3, 5], 1], 1.0, atol=1e-12)
+    assert (same[:, 0] == 0).all() and np.allclose(same[[0, 1, 2, 3, 5, 6, 7, 8], 1], 1.0, atol=1e-12)
 
 
 def test_storage_study_small(dev):
