@@ -509,6 +509,40 @@ def class_batch_run(spec, dev, launches=5):
                       "kernel_source_sha256_16": kernel_source_hash()}), flush=True)
 
 
+SWEEP_B = (2, 4, 8, 12, 16, 20, 32)
+
+
+def sweep_b_run(dev, steps=20):
+    """Step time against the cell size b (Sec. VII's timing against block
+    size, in shape): 64 RGB 1920x1080 frames and 300 RGB 768x576 frames (about
+    the same pixel count), s_b = b / 2 (1 at b = 2), 8-rectangle masks,
+    eps 1.0 / 0.3, m 16, default tiles, plan + forward replayed from a HIP
+    graph.  Frames whose sides b does not divide are padded virtually, so a
+    bandwidth-bound pass should give about the same rate at every b."""
+    import torch
+    from paper_2511_04261_amd import synth
+    rows = []
+    for (H, W, n) in ((1080, 1920, 64), (576, 768, 300)):
+        for b in SWEEP_B:
+            sb = max(1, b // 2)
+            frames_s = synth.region_batch(n, height=H, width=W, b=b, sb=sb)
+            plan = make_plan(frames_s, dev)
+            imgs, masks = load_inputs(frames_s, dev)
+            outs = [torch.empty_like(t) for t in imgs]
+            r = run_batched(plan, imgs, masks, outs, 5, steps, graph=True)
+            ab = r["bytes"]
+            row = dict(frame="%dx%d" % (W, H), frames=n, b=b, s_b=sb, step_ms=round(r["step_ms"], 4),
+                       megapixels_per_s=round(r["pixels"] / (r["step_ms"] * 1e-3) / 1e6, 1),
+                       step_frac_hbm=frac(ab["step"], r["step_ms"])[1], forward_ms=round(r["fwd_ms"], 4),
+                       forward_frac_hbm=frac(ab["forward"], r["fwd_ms"])[1], plan_ms=round(r["plan_ms"], 4))
+            log("sweep b: %s" % row)
+            rows.append(row)
+            plan.close()
+            del plan, imgs, masks, outs
+            torch.cuda.empty_cache()
+    print(json.dumps({"sweep_b": rows, "kernel_source_sha256_16": kernel_source_hash()}), flush=True)
+
+
 def dump_inputs(ub, dev, path):
     """Render the batch on the device and save it as .npy files (for the
     counter runs, which must not launch the rendering kernels)."""
@@ -664,6 +698,7 @@ def main():
     ap.add_argument("--inputs", default=None, help="directory of .npy inputs from --dump-inputs")
     ap.add_argument("--dump-inputs", default=None, help="write the uneven batch's inputs here and exit")
     ap.add_argument("--class-batch", default=None, help="profiling run over one class, HxW:b:s_b:frames")
+    ap.add_argument("--sweep-b", action="store_true", help="step time against the cell size b, then exit")
     ap.add_argument("--cpu-worker", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--cpu-index", type=int, default=0, help=argparse.SUPPRESS)
     ap.add_argument("--cpu-procs", type=int, default=1, help=argparse.SUPPRESS)
@@ -683,6 +718,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.class_batch:
         class_batch_run(args.class_batch, dev)
+        return
+    if args.sweep_b:
+        sweep_b_run(dev)
         return
     log("bench: uneven batch of %d frames" % args.frames)
     ub = synth.uneven_batch(args.frames)

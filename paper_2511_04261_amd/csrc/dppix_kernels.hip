@@ -687,6 +687,71 @@ __device__ __forceinline__ void pixel_sums16(const v4u (&w)[C], v4u& lo, v4u& hi
              sum[14] | (sum[15] << 16)};
 }
 
+// Channel sums of the staged chunk: staged row yy is padded row py0 - 1 + yy,
+// staged column xx padded column px0 + xx (xx = -1 .. cols), each folded into
+// the frame as the label's border rule folds it; whole 16-pixel groups inside
+// the frame are read as vectors (aligned rows), the rest one pixel at a time.
+template <int C>
+__device__ __forceinline__ void stage_label_sums(const uint8_t* img, int64_t pitch, int H, int W, int pad, int py0,
+                                                 int rows, int px0, int cols, bool aligned, uint16_t* S)
+{
+    const int tid = threadIdx.x, NT = blockDim.x;
+    const int gfast = (aligned && (px0 & 15) == 0) ? max(0, min(cols, W - px0)) >> 4 : 0;
+    for (int it = tid; it < (rows + 2) * gfast; it += NT) {
+        const int yy = it / gfast, g = it - yy * gfast;
+        const int ry = edge_fold(py0 - 1 + yy, H, pad);
+        const uint8_t* src = img + (int64_t)ry * pitch + (int64_t)(px0 + 16 * g) * C;
+        v4u w[C];
+#pragma unroll
+        for (int i = 0; i < C; ++i)
+            w[i] = ld16_nt(src + 16 * i);
+        v4u lo, hi;
+        pixel_sums16<C>(w, lo, hi);
+        v4u* dst = reinterpret_cast<v4u*>(S + yy * kLabStride + kLabPad + 16 * g);
+        dst[0] = lo;
+        dst[1] = hi;
+    }
+    const int nrest = cols + 2 - 16 * gfast;
+    for (int it = tid; it < (rows + 2) * nrest; it += NT) {
+        const int yy = it / nrest, q = it - yy * nrest;
+        const int xx = q == 0 ? -1 : 16 * gfast + q - 1;
+        const int ry = edge_fold(py0 - 1 + yy, H, pad);
+        const int rx = edge_fold(px0 + xx, W, pad);
+        const uint8_t* px = img + (int64_t)ry * pitch + (int64_t)rx * C;
+        uint32_t sum = 0u;
+#pragma unroll
+        for (int ch = 0; ch < C; ++ch)
+            sum += px[ch];
+        S[yy * kLabStride + kLabPad + xx] = (uint16_t)sum;
+    }
+}
+
+// Sobel labels of one staged column x down rows 0 .. ylim - 1 of the chunk:
+// Gx = dx(-1) + 2 dx(0) + dx(+1), Gy = sx(+1) - sx(-1), with
+// dx(r) = S[r][+1] - S[r][-1], sx(r) = S[r][-1] + 2 S[r][0] + S[r][+1];
+// label(y) = |Gx| + |Gy| >= thr, passed to emit(y, label).
+template <typename Emit>
+__device__ __forceinline__ void label_column(const uint16_t* S, int x, int ylim, int thr, Emit emit)
+{
+    const uint16_t* col = S + kLabPad + x;
+    int dxa = (int)col[1] - (int)col[-1];
+    int sxa = (int)col[-1] + 2 * (int)col[0] + (int)col[1];
+    col += kLabStride;
+    int dxb = (int)col[1] - (int)col[-1];
+    int sxb = (int)col[-1] + 2 * (int)col[0] + (int)col[1];
+    for (int y = 0; y < ylim; ++y) {
+        col += kLabStride;
+        const int dxc = (int)col[1] - (int)col[-1];
+        const int sxc = (int)col[-1] + 2 * (int)col[0] + (int)col[1];
+        const int gx = dxa + 2 * dxb + dxc, gy = sxc - sxa;
+        emit(y, abs(gx) + abs(gy) >= thr);
+        dxa = dxb;
+        sxa = sxb;
+        dxb = dxc;
+        sxb = sxc;
+    }
+}
+
 template <int C>
 __device__ void plan_count_labels(const TileArgs& a, const FrameRec& F, const uint8_t* img, int r0, int nb, int c0,
                                   int KC, int KCs, uint32_t* cellcnt, uint16_t* S)
@@ -714,65 +779,14 @@ __device__ void plan_count_labels(const TileArgs& a, const FrameRec& F, const ui
             for (int cx = 0; cx < XW; cx += kLabCols) {
                 const int cols = min(kLabCols, XW - cx);
                 const int px0 = X0 + cx;
-                // staged row yy is padded row py0 - 1 + yy, staged column xx
-                // padded column px0 + xx (xx = -1 .. cols); whole 16-pixel
-                // groups inside the frame are read as vectors
-                const int gfast = (aligned && (px0 & 15) == 0) ? max(0, min(cols, W - px0)) >> 4 : 0;
-                for (int it = tid; it < (rows + 2) * gfast; it += NT) {
-                    const int yy = it / gfast, g = it - yy * gfast;
-                    const int ry = edge_fold(py0 - 1 + yy, H, pad);
-                    const uint8_t* src = img + (int64_t)ry * pitch + (int64_t)(px0 + 16 * g) * C;
-                    v4u w[C];
-#pragma unroll
-                    for (int i = 0; i < C; ++i)
-                        w[i] = ld16_nt(src + 16 * i);
-                    v4u lo, hi;
-                    pixel_sums16<C>(w, lo, hi);
-                    v4u* dst = reinterpret_cast<v4u*>(S + yy * kLabStride + kLabPad + 16 * g);
-                    dst[0] = lo;
-                    dst[1] = hi;
-                }
-                // the left halo column and every column from 16 * gfast on
-                // (right edge, folded, misaligned): one pixel per item
-                const int nrest = cols + 2 - 16 * gfast;
-                for (int it = tid; it < (rows + 2) * nrest; it += NT) {
-                    const int yy = it / nrest, q = it - yy * nrest;
-                    const int xx = q == 0 ? -1 : 16 * gfast + q - 1;
-                    const int ry = edge_fold(py0 - 1 + yy, H, pad);
-                    const int rx = edge_fold(px0 + xx, W, pad);
-                    const uint8_t* px = img + (int64_t)ry * pitch + (int64_t)rx * C;
-                    uint32_t sum = 0u;
-#pragma unroll
-                    for (int ch = 0; ch < C; ++ch)
-                        sum += px[ch];
-                    S[yy * kLabStride + kLabPad + xx] = (uint16_t)sum;
-                }
+                stage_label_sums<C>(img, pitch, H, W, pad, py0, rows, px0, cols, aligned, S);
                 lds_barrier();
-                // one lane per padded column, down the chunk's rows: Sobel
-                // Gx = dx(-1) + 2 dx(0) + dx(+1), Gy = sx(+1) - sx(-1), with
-                // dx(r) = S[r][+1] - S[r][-1], sx(r) = S[r][-1] + 2 S[r][0] + S[r][+1]
+                // one lane per padded column, down the chunk's rows
                 for (int xb = 0; xb < cols; xb += NT) {
                     const int x = xb + tid;
                     uint32_t cnt = 0u;
-                    if (x < cols && (pad != kPadNone || px0 + x < W)) {
-                        const uint16_t* col = S + kLabPad + x;
-                        int dxa = (int)col[1] - (int)col[-1];
-                        int sxa = (int)col[-1] + 2 * (int)col[0] + (int)col[1];
-                        col += kLabStride;
-                        int dxb = (int)col[1] - (int)col[-1];
-                        int sxb = (int)col[-1] + 2 * (int)col[0] + (int)col[1];
-                        for (int y = 0; y < ylim; ++y) {
-                            col += kLabStride;
-                            const int dxc = (int)col[1] - (int)col[-1];
-                            const int sxc = (int)col[-1] + 2 * (int)col[0] + (int)col[1];
-                            const int gx = dxa + 2 * dxb + dxc, gy = sxc - sxa;
-                            cnt += (uint32_t)(abs(gx) + abs(gy) >= thr);
-                            dxa = dxb;
-                            sxa = sxb;
-                            dxb = dxc;
-                            sxb = sxc;
-                        }
-                    }
+                    if (x < cols && (pad != kPadNone || px0 + x < W))
+                        label_column(S, x, ylim, thr, [&](int, bool l) { cnt += (uint32_t)l; });
                     const int cell = (cx + x) / b;
                     if (groups) {
                         for (int m = 1; m < b; m <<= 1)
@@ -1999,13 +2013,11 @@ __global__ __launch_bounds__(kMaxThreads) void k_backward_mirror(TileArgs a)
 // source of the region mask): per real pixel, the 3x3 Sobel responses of the
 // channel sum S, with neighbours past the border mirrored; the pixel is an
 // edge pixel when |Gx| + |Gy| >= threshold * C.  Each tile's real pixels are
-// processed in chunks of kEdgeRows x kEdgeCols whose sums, with a one-pixel
-// mirrored halo, are staged in LDS.
+// processed in chunks of up to kLabRows x kLabCols whose channel sums, with a
+// one-pixel mirrored halo, are staged in LDS exactly as the plan from labels
+// stages them; one lane per column walks down the chunk and writes its mask
+// byte of every row.
 // ==========================================================================
-constexpr int kEdgeRows = 8;
-constexpr int kEdgeCols = 512;
-
-
 template <int C>
 __device__ void edge_tile(const TileArgs& a, const FrameRec& F, const TileCoord& tc, uint16_t* S)
 {
@@ -2021,29 +2033,16 @@ __device__ void edge_tile(const TileArgs& a, const FrameRec& F, const TileCoord&
     uint8_t* out = a.masks_out[tc.f];
     const int64_t pitch = F.pitch;
     const int thr = a.edge_threshold * C;
-    constexpr int SW = kEdgeCols + 2;
-    for (int cy = y0; cy < y1; cy += kEdgeRows) {
-        const int rows = min(kEdgeRows, y1 - cy);
-        for (int cx = xa; cx < xb; cx += kEdgeCols) {
-            const int cols = min(kEdgeCols, xb - cx);
-            // channel sums of the chunk and its halo
-            for (int q = tid; q < (rows + 2) * (cols + 2); q += NT) {
-                const int ly = q / (cols + 2), lx = q - ly * (cols + 2);
-                const int y = edge_fold(cy + ly - 1, H, pad), x = edge_fold(cx + lx - 1, W, pad);
-                const uint8_t* p = img + (int64_t)y * pitch + (int64_t)x * C;
-                uint32_t sum = 0;
-#pragma unroll
-                for (int ch = 0; ch < C; ++ch)
-                    sum += p[ch];
-                S[ly * SW + lx] = (uint16_t)sum;
-            }
+    const bool aligned = ((reinterpret_cast<uintptr_t>(img) | (uintptr_t)pitch) & 15) == 0;
+    for (int cy = y0; cy < y1; cy += kLabRows) {
+        const int rows = min(kLabRows, y1 - cy);
+        for (int cx = xa; cx < xb; cx += kLabCols) {
+            const int cols = min(kLabCols, xb - cx);
+            stage_label_sums<C>(img, pitch, H, W, pad, cy, rows, cx, cols, aligned, S);
             lds_barrier();
-            for (int q = tid; q < rows * cols; q += NT) {
-                const int ly = q / cols, lx = q - ly * cols;
-                const uint16_t* s = S + ly * SW + lx;   // top-left of the 3x3 window
-                const int gx = (s[2] + 2 * s[SW + 2] + s[2 * SW + 2]) - (s[0] + 2 * s[SW] + s[2 * SW]);
-                const int gy = (s[2 * SW] + 2 * s[2 * SW + 1] + s[2 * SW + 2]) - (s[0] + 2 * s[1] + s[2]);
-                out[(int64_t)(cy + ly) * W + cx + lx] = (uint8_t)(abs(gx) + abs(gy) >= thr);
+            for (int x = tid; x < cols; x += NT) {
+                uint8_t* o = out + (int64_t)cy * W + cx + x;
+                label_column(S, x, rows, thr, [&](int y, bool l) { o[(int64_t)y * W] = (uint8_t)l; });
             }
             lds_barrier();
         }
@@ -2053,7 +2052,7 @@ __device__ void edge_tile(const TileArgs& a, const FrameRec& F, const TileCoord&
 template <int C>
 __global__ __launch_bounds__(kMaxThreads) void k_edge_mask(TileArgs a)
 {
-    __shared__ __align__(16) uint16_t S[(kEdgeRows + 2) * (kEdgeCols + 2)];
+    __shared__ __align__(16) uint16_t S[(kLabRows + 2) * kLabStride];
     extern __shared__ __align__(16) uint8_t lds[];
     run_tiles(a, lds, [&](const FrameRec& F, const TileCoord& tc) { edge_tile<C>(a, F, tc, S); });
 }

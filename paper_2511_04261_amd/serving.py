@@ -11,6 +11,8 @@ own Philox counter (its stream and its sequence number in it), so its result
 is the same alone or in any mix; streams differ in the counter's high bits,
 so no two frames of any streams share noise (``StreamCounters``, which also
 saves and restores the counters so that resumed streams continue them).
+Completions, admissions and launches are ROCTx ranges (``markers``), so a
+marker trace shows the loop's host phases beside its kernels.
 
 The scheduler is host logic over a small backend interface; ``GpuBackend``
 drives libdppix, and the tests drive the same scheduler with a CPU backend.
@@ -27,6 +29,7 @@ from typing import Any, Deque, Dict, List, Optional
 
 import numpy as np
 
+from .markers import marker_range
 from .store_codec import privacy_ledger
 
 
@@ -133,7 +136,8 @@ class Scheduler:
         while self.inflight and self.backend.poll(self.inflight[0][0]):
             handle, reqs = self.inflight.popleft()
             now = self.clock()
-            results = self.backend.collect(handle)
+            with marker_range("dppix.serve.collect[%d]" % len(reqs)):
+                results = self.backend.collect(handle)
             for r, res in zip(reqs, results):
                 r.result = res
                 r.done = now
@@ -148,7 +152,8 @@ class Scheduler:
         while self.queue and self.ledger.try_reserve(self.queue[0].nbytes):
             r = self.queue.popleft()
             r.admitted = self.clock()
-            self.backend.admit(r)
+            with marker_range("dppix.serve.admit"):
+                self.backend.admit(r)
             self.admitted.append(r)
             moved += 1
         # launch everything admitted (up to max_batch) when a batch slot is free
@@ -159,14 +164,18 @@ class Scheduler:
             for r in batch:
                 r.launched = now
             try:
-                self.inflight.append((self.backend.launch(batch), batch))
+                with marker_range("dppix.serve.launch[%d]" % len(batch)):
+                    handle = self.backend.launch(batch)
+                self.inflight.append((handle, batch))
                 self.batches += 1
                 self.batch_sizes.append(len(batch))
             except Exception:
                 # isolate the request that fails: relaunch each one alone
                 for r in batch:
                     try:
-                        self.inflight.append((self.backend.launch([r]), [r]))
+                        with marker_range("dppix.serve.launch[1]"):
+                            handle = self.backend.launch([r])
+                        self.inflight.append((handle, [r]))
                         self.batches += 1
                         self.batch_sizes.append(1)
                     except Exception as e:  # this request alone is bad
