@@ -699,6 +699,8 @@ def main():
     ap.add_argument("--dump-inputs", default=None, help="write the uneven batch's inputs here and exit")
     ap.add_argument("--class-batch", default=None, help="profiling run over one class, HxW:b:s_b:frames")
     ap.add_argument("--sweep-b", action="store_true", help="step time against the cell size b, then exit")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="only the serving leg (--serve-seconds of camera streams), then exit")
     ap.add_argument("--cpu-worker", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--cpu-index", type=int, default=0, help=argparse.SUPPRESS)
     ap.add_argument("--cpu-procs", type=int, default=1, help=argparse.SUPPRESS)
@@ -721,6 +723,10 @@ def main():
         return
     if args.sweep_b:
         sweep_b_run(dev)
+        return
+    if args.serve_only:
+        log("bench: serving %.0f s of 16 camera streams" % args.serve_seconds)
+        print(json.dumps({"serving": run_serving(dev, args.serve_seconds)}), flush=True)
         return
     log("bench: uneven batch of %d frames" % args.frames)
     ub = synth.uneven_batch(args.frames)

@@ -49,6 +49,10 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 // space, and flat accesses would make every wait cover LDS traffic as well.
 typedef __attribute__((address_space(1))) v4u g_v4u;
 typedef __attribute__((address_space(1))) v4f g_v4f;
+typedef __attribute__((address_space(1))) const uint8_t g_u8;
+typedef __attribute__((address_space(1))) uint8_t g_u8w;
+typedef __attribute__((address_space(1))) const float g_f32;
+typedef __attribute__((address_space(1))) float g_f32w;
 
 __device__ __forceinline__ v4u ld16_nt(const void* p) { return __builtin_nontemporal_load((const g_v4u*)p); }
 __device__ __forceinline__ v4f ld16f_nt(const void* p) { return __builtin_nontemporal_load((const g_v4f*)p); }
@@ -260,7 +264,6 @@ __device__ __forceinline__ void store_colsums16(uint16_t* dst, const uint32_t (&
 template <int C>
 __device__ __noinline__ v4u gather_strip_u8(const uint8_t* row, int p0, int tile_end, int W, int pad)
 {
-    typedef __attribute__((address_space(1))) const uint8_t g_u8;
     const g_u8* src = (const g_u8*)row;
     // source offsets first (folding branches), then 16 unconditional byte
     // loads issued back to back; bytes past the tile end are masked after
@@ -717,7 +720,7 @@ __device__ __forceinline__ void stage_label_sums(const uint8_t* img, int64_t pit
         const int xx = q == 0 ? -1 : 16 * gfast + q - 1;
         const int ry = edge_fold(py0 - 1 + yy, H, pad);
         const int rx = edge_fold(px0 + xx, W, pad);
-        const uint8_t* px = img + (int64_t)ry * pitch + (int64_t)rx * C;
+        const g_u8* px = (const g_u8*)(img + (int64_t)ry * pitch + (int64_t)rx * C);
         uint32_t sum = 0u;
 #pragma unroll
         for (int ch = 0; ch < C; ++ch)
@@ -726,25 +729,43 @@ __device__ __forceinline__ void stage_label_sums(const uint8_t* img, int64_t pit
     }
 }
 
-// Sobel labels of one staged column x down rows 0 .. ylim - 1 of the chunk:
+// Sobel labels of the staged column pair (2p, 2p + 1) down rows y0 .. y1 - 1
+// of the chunk, the two columns in the 16-bit halves of one register:
 // Gx = dx(-1) + 2 dx(0) + dx(+1), Gy = sx(+1) - sx(-1), with
-// dx(r) = S[r][+1] - S[r][-1], sx(r) = S[r][-1] + 2 S[r][0] + S[r][+1];
-// label(y) = |Gx| + |Gy| >= thr, passed to emit(y, label).
-template <typename Emit>
-__device__ __forceinline__ void label_column(const uint16_t* S, int x, int ylim, int thr, Emit emit)
+// dx(r) = S[r][+1] - S[r][-1], sx(r) = S[r][-1] + 2 S[r][0] + S[r][+1].
+// With S <= 4 * 255 every intermediate fits a signed 16-bit half exactly
+// (|Gx|, |Gy| <= 4080), and so does thr - 1 - (|Gx| + |Gy|) for thr <= 16384:
+// its sign is the label.  emit(y, d) gets that difference, bit 15 = label of
+// column 2p, bit 31 = label of column 2p + 1.  Each row is three dword reads
+// (the pair and its two neighbouring pairs, 4-byte aligned).
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ void sobel_row_pair(const uint32_t* r, s16x2& dx, s16x2& sx)
 {
-    const uint16_t* col = S + kLabPad + x;
-    int dxa = (int)col[1] - (int)col[-1];
-    int sxa = (int)col[-1] + 2 * (int)col[0] + (int)col[1];
-    col += kLabStride;
-    int dxb = (int)col[1] - (int)col[-1];
-    int sxb = (int)col[-1] + 2 * (int)col[0] + (int)col[1];
-    for (int y = 0; y < ylim; ++y) {
-        col += kLabStride;
-        const int dxc = (int)col[1] - (int)col[-1];
-        const int sxc = (int)col[-1] + 2 * (int)col[0] + (int)col[1];
-        const int gx = dxa + 2 * dxb + dxc, gy = sxc - sxa;
-        emit(y, abs(gx) + abs(gy) >= thr);
+    const uint32_t w0 = r[-1], w1 = r[0], w2 = r[1];
+    const s16x2 l = __builtin_bit_cast(s16x2, __builtin_amdgcn_alignbit(w1, w0, 16));   // S[-1], S[0]
+    const s16x2 c = __builtin_bit_cast(s16x2, w1);                                      // S[0], S[+1]
+    const s16x2 rr = __builtin_bit_cast(s16x2, __builtin_amdgcn_alignbit(w2, w1, 16));  // S[+1], S[+2]
+    dx = rr - l;
+    sx = (l + rr) + (c + c);
+}
+
+template <typename Emit>
+__device__ __forceinline__ void label_pair(const uint16_t* S, int p, int y0, int y1, int thr, Emit emit)
+{
+    constexpr int RW = kLabStride / 2;                       // dwords per staged row
+    const uint32_t* row = reinterpret_cast<const uint32_t*>(S + kLabPad) + y0 * RW + p;
+    const s16x2 t = {(short)(thr - 1), (short)(thr - 1)};
+    s16x2 dxa, sxa, dxb, sxb;
+    sobel_row_pair(row, dxa, sxa);
+    sobel_row_pair(row + RW, dxb, sxb);
+    row += 2 * RW;
+    for (int y = y0; y < y1; ++y, row += RW) {
+        s16x2 dxc, sxc;
+        sobel_row_pair(row, dxc, sxc);
+        const s16x2 gx = (dxa + dxc) + (dxb + dxb), gy = sxc - sxa;
+        const s16x2 mag = __builtin_elementwise_abs(gx) + __builtin_elementwise_abs(gy);
+        emit(y, __builtin_bit_cast(uint32_t, t - mag));
         dxa = dxb;
         sxa = sxb;
         dxb = dxc;
@@ -752,11 +773,30 @@ __device__ __forceinline__ void label_column(const uint16_t* S, int x, int ylim,
     }
 }
 
+// Lanes over the column pairs of a chunk: pairs 0 .. np - 1, and when the
+// pairs are fewer than the lanes, the rows split over up to 4 lane groups
+// (each group whole waves).  split = this lane's row group (>= splits: idle).
+struct PairLanes {
+    int step, pl, split, splits, rper;
+};
+
+__device__ __forceinline__ PairLanes pair_lanes(int np, int rows)
+{
+    const int tid = threadIdx.x, NT = blockDim.x;
+    const int npr = (np + 63) & ~63;
+    PairLanes L;
+    L.splits = npr >= NT ? 1 : min(4, NT / npr);
+    L.step = L.splits == 1 ? NT : npr;
+    L.pl = L.splits == 1 ? tid : tid % npr;
+    L.split = L.splits == 1 ? 0 : tid / npr;
+    L.rper = (rows + L.splits - 1) / L.splits;
+    return L;
+}
+
 template <int C>
 __device__ void plan_count_labels(const TileArgs& a, const FrameRec& F, const uint8_t* img, int r0, int nb, int c0,
                                   int KC, int KCs, uint32_t* cellcnt, uint16_t* S)
 {
-    const int tid = threadIdx.x, NT = blockDim.x;
     const int b = F.b, H = F.H, W = F.W, pad = F.pad;
     const int64_t pitch = F.pitch;
     const int thr = a.edge_threshold * C;
@@ -781,20 +821,39 @@ __device__ void plan_count_labels(const TileArgs& a, const FrameRec& F, const ui
                 const int px0 = X0 + cx;
                 stage_label_sums<C>(img, pitch, H, W, pad, py0, rows, px0, cols, aligned, S);
                 lds_barrier();
-                // one lane per padded column, down the chunk's rows
-                for (int xb = 0; xb < cols; xb += NT) {
-                    const int x = xb + tid;
-                    uint32_t cnt = 0u;
-                    if (x < cols && (pad != kPadNone || px0 + x < W))
-                        label_column(S, x, ylim, thr, [&](int, bool l) { cnt += (uint32_t)l; });
+                // a lane per pair of padded columns, down its share of the rows
+                const int np = (cols + 1) >> 1;
+                const PairLanes L = pair_lanes(np, ylim);
+                const int ya = L.split * L.rper, yb = min(ylim, ya + L.rper);
+                for (int pb = 0; pb < np; pb += L.step) {
+                    const int p = pb + L.pl, x = 2 * p;
+                    // valid columns: inside the chunk, and real in the unpadded mode
+                    const int xend = pad == kPadNone ? min(cols, W - px0) : cols;
+                    const uint32_t vm = (x < xend ? 0x8000u : 0u) | (x + 1 < xend ? 0x80000000u : 0u);
+                    uint32_t cnt = 0u, cnt_hi = 0u;
+                    if (vm != 0u && L.split < L.splits && ya < yb) {
+                        if ((b & 1) == 0)
+                            label_pair(S, p, ya, yb, thr, [&](int, uint32_t d) { cnt += __builtin_popcount(d & vm); });
+                        else
+                            label_pair(S, p, ya, yb, thr, [&](int, uint32_t d) {
+                                d &= vm;
+                                cnt += (d >> 15) & 1u;
+                                cnt_hi += d >> 31;
+                            });
+                    }
+                    // b even: both columns lie in one cell
                     const int cell = (cx + x) / b;
-                    if (groups) {
-                        for (int m = 1; m < b; m <<= 1)
+                    if (groups && b >= 2) {
+                        for (int m = 1; m < (b >> 1); m <<= 1)
                             cnt += __shfl_xor(cnt, m, 64);
-                        if ((tid & (b - 1)) == 0 && cnt != 0u && cell < KC)
+                        if ((L.pl & ((b >> 1) - 1)) == 0 && cnt != 0u && cell < KC)
                             atomicAdd(cellcnt + j * KCs + cell, cnt);
-                    } else if (cnt != 0u && cell < KC) {
-                        atomicAdd(cellcnt + j * KCs + cell, cnt);
+                    } else {
+                        if (cnt != 0u && cell < KC)
+                            atomicAdd(cellcnt + j * KCs + cell, cnt);
+                        const int cell_hi = (cx + x + 1) / b;
+                        if (cnt_hi != 0u && cell_hi < KC)
+                            atomicAdd(cellcnt + j * KCs + cell_hi, cnt_hi);
                     }
                 }
                 lds_barrier();
@@ -1395,7 +1454,7 @@ __device__ void forward_tile_u8(const TileArgs& a, const FrameRec& F, const Tile
             } else {
                 const uint8_t* vb = exb + 16 * st;
                 for (int k = k0; k < k1; ++k) {
-                    uint8_t* op = out + (int64_t)(row0 + k) * pitch;
+                    g_u8w* op = (g_u8w*)(out + (int64_t)(row0 + k) * pitch);
                     for (int q = 0; q < 16 && p0 + q < lim; ++q)
                         op[p0 + q] = vb[q];
                 }
@@ -1445,9 +1504,10 @@ __device__ void broadcast_tile_f32(const FrameRec& F, int r, int64_t X0, int64_t
                         st16f_nt(pl + (int64_t)(row0 + k) * pitch + p0, v);
                 } else {
                     const float vv[4] = {v.x, v.y, v.z, v.w};
+                    g_f32w* pg = (g_f32w*)pl;
                     for (int k = 0; k < rows; ++k)
                         for (int q = 0; q < 4 && p0 + q < lim; ++q)
-                            pl[(int64_t)(row0 + k) * pitch + p0 + q] = vv[q];
+                            pg[(int64_t)(row0 + k) * pitch + p0 + q] = vv[q];
                 }
             }
         }
@@ -1522,7 +1582,7 @@ __device__ void forward_tile_f32(const TileArgs& a, const FrameRec& F, const Til
                     acc += ld16f_nt(pl + (int64_t)fold(row0 + k, H, pad) * pitch + p0);
             } else {
                 for (int k = 0; k < srows; ++k) {
-                    const float* rk = pl + (int64_t)fold(row0 + k, H, pad) * pitch;
+                    const g_f32* rk = (const g_f32*)(pl + (int64_t)fold(row0 + k, H, pad) * pitch);
                     float v[4];
 #pragma unroll
                     for (int q = 0; q < 4; ++q)
@@ -1714,7 +1774,7 @@ __device__ void reconstruct_tile_u8(const TileArgs& a, const FrameRec& F, const 
             } else {
                 const uint8_t* vb = exb + 16 * st;
                 for (int k = k0; k < k1; ++k) {
-                    uint8_t* op = out + (int64_t)(row0 + k) * pitch;
+                    g_u8w* op = (g_u8w*)(out + (int64_t)(row0 + k) * pitch);
                     for (int q = 0; q < 16 && p0 + q < lim; ++q)
                         op[p0 + q] = vb[q];
                 }
@@ -1785,9 +1845,10 @@ __device__ void reconstruct_tile_f32(const TileArgs& a, const FrameRec& F, const
                         st16f_nt(pl + (int64_t)(row0 + k) * pitch + p0, v);
                 } else {
                     const float vv[4] = {v.x, v.y, v.z, v.w};
+                    g_f32w* pg = (g_f32w*)pl;
                     for (int k = 0; k < rows; ++k)
                         for (int q = 0; q < 4 && p0 + q < lim; ++q)
-                            pl[(int64_t)(row0 + k) * pitch + p0 + q] = vv[q];
+                            pg[(int64_t)(row0 + k) * pitch + p0 + q] = vv[q];
                 }
             }
         }
@@ -1872,7 +1933,7 @@ __device__ void backward_reduce_tile(const TileArgs& a, const FrameRec& F, const
                     acc += ld16f_nt(col + (int64_t)k * pitch);
             } else {
                 for (int k = 0; k < rows; ++k) {
-                    const float* rk = pl + (int64_t)(row0 + k) * pitch;
+                    const g_f32* rk = (const g_f32*)(pl + (int64_t)(row0 + k) * pitch);
                     acc.x += (p0 + 0 < lim) ? rk[p0 + 0] : 0.f;
                     acc.y += (p0 + 1 < lim) ? rk[p0 + 1] : 0.f;
                     acc.z += (p0 + 2 < lim) ? rk[p0 + 2] : 0.f;
@@ -1997,7 +2058,7 @@ __device__ void backward_mirror_tile(const TileArgs& a, const FrameRec& F, const
                 if (fold(xx, W, pad) == x)
                     acc += g_at(a, F, tc.f, y, xx, ch);
             if (acc != 0.f)
-                gi[plane * ch + (int64_t)y * pitch + x] += acc;
+                ((g_f32w*)gi)[plane * ch + (int64_t)y * pitch + x] += acc;
         }
     }
 }
@@ -2021,7 +2082,6 @@ __global__ __launch_bounds__(kMaxThreads) void k_backward_mirror(TileArgs a)
 template <int C>
 __device__ void edge_tile(const TileArgs& a, const FrameRec& F, const TileCoord& tc, uint16_t* S)
 {
-    const int tid = threadIdx.x, NT = blockDim.x;
     const int b = F.b, H = F.H, W = F.W, pad = F.pad;
     const int x0c = tc.ct * F.K;
     const int Kt = min(F.K, F.GC - x0c);
@@ -2040,9 +2100,21 @@ __device__ void edge_tile(const TileArgs& a, const FrameRec& F, const TileCoord&
             const int cols = min(kLabCols, xb - cx);
             stage_label_sums<C>(img, pitch, H, W, pad, cy, rows, cx, cols, aligned, S);
             lds_barrier();
-            for (int x = tid; x < cols; x += NT) {
-                uint8_t* o = out + (int64_t)cy * W + cx + x;
-                label_column(S, x, rows, thr, [&](int y, bool l) { o[(int64_t)y * W] = (uint8_t)l; });
+            const int np = (cols + 1) >> 1;
+            const PairLanes L = pair_lanes(np, rows);
+            const int ya = L.split * L.rper, yb = min(rows, ya + L.rper);
+            if (L.split < L.splits && ya < yb) {
+                for (int p = L.pl; p < np; p += L.step) {
+                    g_u8w* o = (g_u8w*)(out + (int64_t)cy * W + cx + 2 * p);
+                    if (2 * p + 1 < cols)
+                        label_pair(S, p, ya, yb, thr, [&](int y, uint32_t d) {
+                            o[(int64_t)y * W] = (uint8_t)((d >> 15) & 1u);
+                            o[(int64_t)y * W + 1] = (uint8_t)(d >> 31);
+                        });
+                    else
+                        label_pair(S, p, ya, yb, thr,
+                                   [&](int y, uint32_t d) { o[(int64_t)y * W] = (uint8_t)((d >> 15) & 1u); });
+                }
             }
             lds_barrier();
         }
@@ -2152,6 +2224,8 @@ __device__ void metrics_tile(const TileArgs& a, const FrameRec& F, const TileCoo
     const int xa = x0c * b, xb = min((x0c + Kt) * b, W);
     const uint8_t* X = static_cast<const uint8_t*>(a.images[tc.f]);
     const uint8_t* Y = static_cast<const uint8_t*>(a.outs[tc.f]);
+    const g_u8* Xg = (const g_u8*)X;
+    const g_u8* Yg = (const g_u8*)Y;
     const int64_t pitch = F.pitch;
     double ssim_acc = 0.0;
     unsigned long long se = 0;
@@ -2172,7 +2246,7 @@ __device__ void metrics_tile(const TileArgs& a, const FrameRec& F, const TileCoo
         for (int it = tid; it < rows * nr; it += NT) {
             const int yy = it / nr, q = it - yy * nr;
             const int64_t at = (int64_t)(y0 + yy) * pitch + b0 + 16 * nv + q;
-            const int d = (int)X[at] - (int)Y[at];
+            const int d = (int)Xg[at] - (int)Yg[at];
             se += (unsigned long long)(d * d);
         }
     }
@@ -2190,8 +2264,8 @@ __device__ void metrics_tile(const TileArgs& a, const FrameRec& F, const TileCoo
             for (int it = tid; it < nrs * sb; it += NT) {
                 const int k = it / sb, q = it - k * sb;
                 const int64_t at = (int64_t)(cyb - 3 + k) * pitch + bx + q;
-                L.x[k][q] = X[at];
-                L.y[k][q] = Y[at];
+                L.x[k][q] = Xg[at];
+                L.y[k][q] = Yg[at];
             }
             lds_barrier();
             const int q = tid;
