@@ -509,6 +509,24 @@ def class_batch_run(spec, dev, launches=5):
                       "kernel_source_sha256_16": kernel_source_hash()}), flush=True)
 
 
+def kernel_legs_run(dev, reps=3):
+    """Profiling run of the standalone kernels (plan, reconstruction, Sobel
+    labels as a mask and in the plan, metrics) on the 64-frame 1080p batch:
+    inputs rendered on the host, a few calls of each, one JSON line with the
+    per-call times and the kernel source hash."""
+    import torch
+    from paper_2511_04261_amd import synth
+    c2 = synth.region_batch(64)
+    plan = make_plan(c2, dev)
+    imgs, masks = load_inputs(c2, dev, host_render=True)
+    outs = [torch.empty_like(t) for t in imgs]
+    torch.cuda.synchronize()
+    log("kernel legs: inputs ready")
+    legs = run_kernel_legs(plan, imgs, masks, outs, reps=reps)
+    plan.close()
+    print(json.dumps({"kernel_legs": legs, "kernel_source_sha256_16": kernel_source_hash()}), flush=True)
+
+
 SWEEP_B = (2, 4, 8, 12, 16, 20, 32)
 
 
@@ -699,6 +717,8 @@ def main():
     ap.add_argument("--dump-inputs", default=None, help="write the uneven batch's inputs here and exit")
     ap.add_argument("--class-batch", default=None, help="profiling run over one class, HxW:b:s_b:frames")
     ap.add_argument("--sweep-b", action="store_true", help="step time against the cell size b, then exit")
+    ap.add_argument("--kernel-legs", action="store_true",
+                    help="profiling run of the standalone kernels on the 64-frame 1080p batch (host-rendered inputs)")
     ap.add_argument("--serve-only", action="store_true",
                     help="only the serving leg (--serve-seconds of camera streams), then exit")
     ap.add_argument("--cpu-worker", action="store_true", help=argparse.SUPPRESS)
@@ -723,6 +743,9 @@ def main():
         return
     if args.sweep_b:
         sweep_b_run(dev)
+        return
+    if args.kernel_legs:
+        kernel_legs_run(dev)
         return
     if args.serve_only:
         log("bench: serving %.0f s of 16 camera streams" % args.serve_seconds)

@@ -418,6 +418,7 @@ dppix_status_t dp_pix_plan_create(const dppix_frame_desc_t* descs, int32_t n_fra
     }
     p->n_border = (int64_t)border.size() / 2;
     w.border_map = o;  o = align256(o + sizeof(int32_t) * border.size());
+    w.simple_counts = o; o = align256(o + sizeof(uint64_t) * 4 * (size_t)n_frames);
     w.total = o;
     // Per-call state carried by each store.
     StateLayout& sl = p->st;
@@ -441,6 +442,21 @@ dppix_status_t dp_pix_plan_create(const dppix_frame_desc_t* descs, int32_t n_fra
         xcd_runs(map, g.lo, g.hi);
     if (!border.empty())
         std::memcpy(p->host_tables.data() + w.border_map, border.data(), sizeof(int32_t) * border.size());
+    {
+        // without masks every cell is simple: n_bg = cells, n_fg = 0, and the
+        // frames' statistics packed back to back in batch order
+        uint64_t* sc = reinterpret_cast<uint64_t*>(p->host_tables.data() + w.simple_counts);
+        uint64_t bg_off = 0;
+        for (int32_t f = 0; f < n_frames; ++f) {
+            const FrameRec& F = p->frames[f];
+            const uint64_t cells = (uint64_t)F.GR * (uint64_t)F.GC;
+            sc[4 * f + 0] = cells;
+            sc[4 * f + 1] = 0;
+            sc[4 * f + 2] = bg_off;
+            sc[4 * f + 3] = 0;
+            bg_off += cells * (uint64_t)F.C;
+        }
+    }
     int32_t* umap = reinterpret_cast<int32_t*>(p->host_tables.data() + w.unit_map);
     for (int32_t f = 0, u = 0; f < n_frames; ++f)
         for (int32_t i = 0; i < p->frames[f].cunits; ++i, ++u) {
@@ -567,6 +583,8 @@ TileArgs base_args(dppix_plan_t p, const dppix_store_t* store)
     a.n_frames = (int32_t)p->frames.size();
     a.n_tiles = p->n_tiles;
     a.unit_map = reinterpret_cast<const int32_t*>(w + p->ws.unit_map);
+    a.simple_counts = reinterpret_cast<const uint64_t*>(w + p->ws.simple_counts);
+    a.total_cells = p->total_cells;
     a.persistent = p->persistent;
     if (store != nullptr) {
         uint8_t* st = static_cast<uint8_t*>(store->state);

@@ -43,6 +43,7 @@ struct WsLayout {
     size_t tile_map;      // int32[n_tiles][2]: (frame, tile within frame) per scheduling index
     size_t unit_map;      // int32[n_units][2]: (frame, plan unit within frame), frame-major
     size_t border_map;    // int32[n_border][2]: (frame, tile) of the tiles the adjoint's mirror pass visits
+    size_t simple_counts; // uint64[n_frames][4]: store counts of a call without masks (every cell simple)
     size_t total;
 };
 
@@ -68,6 +69,8 @@ struct TileArgs {
     int32_t persistent;
     // per-frame pointer tables (device arrays of device pointers)
     const uint8_t* const* masks;
+    const uint64_t* simple_counts;   // store counts when no frame has a mask (geometry only)
+    int64_t total_cells;             // cells of the whole batch (store flags)
     const void* const* images;
     void* const* outs;
     // products of the plan, held by the caller's store

@@ -674,20 +674,41 @@ __device__ __forceinline__ void pixel_sums16(const v4u (&w)[C], v4u& lo, v4u& hi
         d[4 * i + 2] = w[i].z;
         d[4 * i + 3] = w[i].w;
     }
-    uint32_t sum[16];
+    uint32_t pr[8];   // pixel pairs (2k low, 2k + 1 high)
+    if constexpr (C == 1) {
+        // each byte is its own sum: bytes 0, 1 and 2, 3 of a dword into halves
 #pragma unroll
-    for (int px = 0; px < 16; ++px) {
-        uint32_t t = 0u;
-#pragma unroll
-        for (int ch = 0; ch < C; ++ch) {
-            const int q = px * C + ch;
-            t += (d[q >> 2] >> (8 * (q & 3))) & 0xFFu;
+        for (int i = 0; i < 4; ++i) {
+            pr[2 * i] = __builtin_amdgcn_perm(0u, d[i], 0x0C010C00u);
+            pr[2 * i + 1] = __builtin_amdgcn_perm(0u, d[i], 0x0C030C02u);
         }
-        sum[px] = t;
+    } else if constexpr (C == 2) {
+        // a dword is two pixels: (b0 + b1, b2 + b3) as halves
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            pr[i] = __builtin_amdgcn_perm(0u, d[i], 0x0C020C00u) + __builtin_amdgcn_perm(0u, d[i], 0x0C030C01u);
+    } else if constexpr (C == 3) {
+        // three dwords are four pixels: bytes 0-2 | 3-5 | 6-8 | 9-11, each
+        // pixel's bytes added by byte dot products with 0/1 weights
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t a = d[3 * i], b = d[3 * i + 1], c = d[3 * i + 2];
+            const uint32_t s0 = __builtin_amdgcn_udot4(a, 0x00010101u, 0u, false);
+            const uint32_t s1 = __builtin_amdgcn_udot4(b, 0x00000101u, __builtin_amdgcn_udot4(a, 0x01000000u, 0u, false), false);
+            const uint32_t s2 = __builtin_amdgcn_udot4(c, 0x00000001u, __builtin_amdgcn_udot4(b, 0x01010000u, 0u, false), false);
+            const uint32_t s3 = __builtin_amdgcn_udot4(c, 0x01010100u, 0u, false);
+            pr[2 * i] = s0 | (s1 << 16);
+            pr[2 * i + 1] = s2 | (s3 << 16);
+        }
+    } else {
+        // a dword is one pixel
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            pr[i] = __builtin_amdgcn_udot4(d[2 * i], 0x01010101u, 0u, false) |
+                    (__builtin_amdgcn_udot4(d[2 * i + 1], 0x01010101u, 0u, false) << 16);
     }
-    lo = v4u{sum[0] | (sum[1] << 16), sum[2] | (sum[3] << 16), sum[4] | (sum[5] << 16), sum[6] | (sum[7] << 16)};
-    hi = v4u{sum[8] | (sum[9] << 16), sum[10] | (sum[11] << 16), sum[12] | (sum[13] << 16),
-             sum[14] | (sum[15] << 16)};
+    lo = v4u{pr[0], pr[1], pr[2], pr[3]};
+    hi = v4u{pr[4], pr[5], pr[6], pr[7]};
 }
 
 // Channel sums of the staged chunk: staged row yy is padded row py0 - 1 + yy,
@@ -875,6 +896,26 @@ __global__ __launch_bounds__(kMaxThreads) void k_plan_labels(TileArgs a)
         default: plan_count_labels<4>(a, F, img, r0, nb, c0, KC, KCs, cellcnt, S); break;
         }
     });
+}
+
+// Plan of a call without masks (Algorithm 3 with every cell simple): flags
+// cleared, no complex cell in any tile, and each frame's counts and offsets
+// copied from the table the host derived from the geometry alone.  One
+// launch in place of the count and scan passes.
+__global__ __launch_bounds__(256) void k_plan_simple(TileArgs a)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i0 < kTicketWords)
+        a.ticket[i0] = 0u;
+    for (int64_t i = i0; i < a.total_cells; i += stride)
+        a.flags[i] = 0;
+    for (int64_t i = i0; i < a.n_tiles; i += stride) {
+        a.tile_cnt[i] = 0u;
+        a.tile_fg[i] = 0u;
+    }
+    for (int64_t i = i0; i < 4 * (int64_t)a.n_frames; i += stride)
+        a.counts[i] = a.simple_counts[i];
 }
 
 // One workgroup per frame: exclusive scan of the per-tile complex counts into
@@ -2157,11 +2198,12 @@ __global__ __launch_bounds__(kMaxThreads) void k_edge_mask(TileArgs a)
 // ==========================================================================
 constexpr int kMetRowsMax = 32;                 // window-centre rows per chunk
 constexpr int kMetStage = kMetRowsMax + 6;      // staged rows per chunk
-constexpr int kMetCols = 256 + 24;              // staged bytes per row (lanes + 6 pixels of up to 4 channels)
+constexpr int kMetSpan = 256 + 24;              // staged bytes per row (lanes + 6 pixels of up to 4 channels)
+constexpr int kMetCols = 304;                   // LDS row: a span shifted by up to 15 bytes, 16-byte rows
 
 struct MetLds {
-    uint8_t x[kMetStage][kMetCols];
-    uint8_t y[kMetStage][kMetCols];
+    alignas(16) uint8_t x[kMetStage][kMetCols];
+    alignas(16) uint8_t y[kMetStage][kMetCols];
     double red[kMaxThreads / 64];
     unsigned long long red_se[kMaxThreads / 64];
 };
@@ -2213,6 +2255,73 @@ __device__ __forceinline__ double ssim_window(const uint32_t (&t)[5])
     return (A * B) / (D * E);
 }
 
+// Stage nrs rows of the byte span [bx, bx + sb) of both frames (row k starts
+// at byte r0 + k * pitch): byte bx + q of row k goes to L.x[k][sh + q] with
+// sh = bx mod 16 when the rows are 16-byte aligned, so that the 16-byte blocks
+// inside the span land on 16-byte LDS positions and move as vectors; the
+// bytes before the first block and after the last one move singly.  Loads of
+// a batch of items are all issued before the first LDS write.
+__device__ __forceinline__ void stage_metrics_rows(const g_u8* X, const g_u8* Y, int64_t pitch, int64_t r0, int64_t bx,
+                                                   int sb, int nrs, bool rows16, MetLds& L)
+{
+    const int tid = threadIdx.x, NT = blockDim.x;
+    const int sh = rows16 ? (int)(bx & 15) : 0;
+    const int64_t a0 = (bx + 15) & ~(int64_t)15, a1 = (bx + sb) & ~(int64_t)15;
+    const int nblk = (rows16 && a1 > a0) ? (int)((a1 - a0) >> 4) : 0;
+    const int head = nblk ? (int)(a0 - bx) : sb;           // single bytes before the first block
+    const int tail = nblk ? (int)(bx + sb - a1) : 0;        // and after the last
+    const int qb = head;                                     // span offset of the first block
+    constexpr int kB = 3, kBb = 4;
+    const int nv = nrs * nblk;
+    for (int base = 0; base < nv; base += kB * NT) {
+        v4u wx[kB], wy[kB];
+#pragma unroll
+        for (int i = 0; i < kB; ++i) {
+            const int it = base + i * NT + tid;
+            if (it < nv) {
+                const int k = it / nblk, g = it - k * nblk;
+                const int64_t at = r0 + (int64_t)k * pitch + a0 + 16 * g;
+                wx[i] = ld16_nt((const void*)(X + at));
+                wy[i] = ld16_nt((const void*)(Y + at));
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < kB; ++i) {
+            const int it = base + i * NT + tid;
+            if (it < nv) {
+                const int k = it / nblk, g = it - k * nblk;
+                *reinterpret_cast<v4u*>(&L.x[k][sh + qb + 16 * g]) = wx[i];
+                *reinterpret_cast<v4u*>(&L.y[k][sh + qb + 16 * g]) = wy[i];
+            }
+        }
+    }
+    const int nsb = head + tail, ns = nrs * nsb;
+    for (int base = 0; base < ns; base += kBb * NT) {
+        uint8_t bxv[kBb], byv[kBb];
+#pragma unroll
+        for (int i = 0; i < kBb; ++i) {
+            const int it = base + i * NT + tid;
+            if (it < ns) {
+                const int k = it / nsb, j = it - k * nsb;
+                const int q = j < head ? j : sb - tail + (j - head);
+                const int64_t at = r0 + (int64_t)k * pitch + bx + q;
+                bxv[i] = X[at];
+                byv[i] = Y[at];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < kBb; ++i) {
+            const int it = base + i * NT + tid;
+            if (it < ns) {
+                const int k = it / nsb, j = it - k * nsb;
+                const int q = j < head ? j : sb - tail + (j - head);
+                L.x[k][sh + q] = bxv[i];
+                L.y[k][sh + q] = byv[i];
+            }
+        }
+    }
+}
+
 template <int C>
 __device__ void metrics_tile(const TileArgs& a, const FrameRec& F, const TileCoord& tc, MetLds& L)
 {
@@ -2237,10 +2346,23 @@ __device__ void metrics_tile(const TileArgs& a, const FrameRec& F, const TileCoo
                                (uintptr_t)b0) & 15) == 0;
         const int nv = aligned ? (int)((b1 - b0) >> 4) : 0;
         const int rows = y1 - y0;
-        for (int it = tid; it < rows * nv; it += NT) {
-            const int yy = it / nv, v = it - yy * nv;
-            const int64_t at = (int64_t)(y0 + yy) * pitch + b0 + 16 * v;
-            se += sq_diff16(ld16_nt(X + at), ld16_nt(Y + at));
+        constexpr int kB = 4;   // items whose loads are all in flight together
+        for (int base = 0; base < rows * nv; base += kB * NT) {
+            v4u wx[kB], wy[kB];
+#pragma unroll
+            for (int i = 0; i < kB; ++i) {
+                const int it = base + i * NT + tid;
+                if (it < rows * nv) {
+                    const int yy = it / nv, v = it - yy * nv;
+                    const int64_t at = (int64_t)(y0 + yy) * pitch + b0 + 16 * v;
+                    wx[i] = ld16_nt(X + at);
+                    wy[i] = ld16_nt(Y + at);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < kB; ++i)
+                if (base + i * NT + tid < rows * nv)
+                    se += sq_diff16(wx[i], wy[i]);
         }
         const int nr = (int)(b1 - b0) - 16 * nv;
         for (int it = tid; it < rows * nr; it += NT) {
@@ -2253,7 +2375,8 @@ __device__ void metrics_tile(const TileArgs& a, const FrameRec& F, const TileCoo
     // SSIM windows centred in this tile's real pixels, 3 away from every edge
     const int cy0 = max(y0, 3), cy1 = min(y1, H - 3);
     const int cx0 = max(xa, 3), cx1 = min(xb, W - 3);
-    const int CW = min(NT / C, kMetCols / C - 6);   // window-centre pixels per chunk (lanes, and the staged row)
+    const int CW = min(NT / C, kMetSpan / C - 6);   // window-centre pixels per chunk (lanes, and the staged row)
+    const bool rows16 = ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Y) | (uintptr_t)pitch) & 15) == 0;
     for (int cxb = cx0; cxb < cx1; cxb += CW) {
         const int cw = min(CW, cx1 - cxb);
         const int sb = (cw + 6) * C;                        // staged bytes per row
@@ -2261,13 +2384,9 @@ __device__ void metrics_tile(const TileArgs& a, const FrameRec& F, const TileCoo
         for (int cyb = cy0; cyb < cy1; cyb += kMetRowsMax) {
             const int rb = min(kMetRowsMax, cy1 - cyb);
             const int nrs = rb + 6;
-            for (int it = tid; it < nrs * sb; it += NT) {
-                const int k = it / sb, q = it - k * sb;
-                const int64_t at = (int64_t)(cyb - 3 + k) * pitch + bx + q;
-                L.x[k][q] = Xg[at];
-                L.y[k][q] = Yg[at];
-            }
+            stage_metrics_rows(Xg, Yg, pitch, (int64_t)(cyb - 3) * pitch, bx, sb, nrs, rows16, L);
             lds_barrier();
+            const int sh = rows16 ? (int)(bx & 15) : 0;
             const int q = tid;
             if (q < cw * C) {
                 Moments ring[7];
@@ -2277,7 +2396,7 @@ __device__ void metrics_tile(const TileArgs& a, const FrameRec& F, const TileCoo
                     for (int j = 0; j < 7; ++j) {
                         const int k = k0 + j;
                         if (k < nrs) {
-                            const Moments h = row_moments<C>(L.x[k], L.y[k], q);
+                            const Moments h = row_moments<C>(L.x[k] + sh, L.y[k] + sh, q);
 #pragma unroll
                             for (int m = 0; m < 5; ++m)
                                 t[m] += h.s[m] - (k >= 7 ? ring[j].s[m] : 0u);
@@ -2411,6 +2530,12 @@ hipError_t launch_plan(const TileArgs& a, int64_t n_units, int threads, size_t l
 {
     if (n_units == 0)
         return hipSuccess;
+    if (a.masks == nullptr) {
+        const int64_t n = std::max<int64_t>(std::max<int64_t>(a.total_cells, a.n_tiles), 4 * (int64_t)a.n_frames);
+        const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 2048);
+        hipLaunchKernelGGL(k_plan_simple, dim3(grid), dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
     hipError_t e = allow_lds(k_plan, lds);
     if (e != hipSuccess)
         return e;
