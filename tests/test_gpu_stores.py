@@ -243,3 +243,40 @@ def test_store_arguments_checked_before_launch(dev):
         plan.forward([img], out=[img])
     with pytest.raises(ValueError, match="CUDA"):
         plan.plan([torch.zeros((32, 32), dtype=torch.uint8)])
+
+
+def test_plan_without_masks_equals_empty_masks(dev):
+    """A plan without masks (one launch, counts from the geometry) lays out
+    the store exactly as the count and scan launches do for all-zero masks:
+    flags, per-frame counts and offsets, and the per-call state the forward
+    reads; frames of 1, 3 and 4 channels, padded and unpadded borders and a
+    stale store from an earlier masked plan included.  The forward that
+    follows matches the oracle with no mask."""
+    geo = [(37, 53, 1, 8, 4, dp.PAD_SYMMETRIC), (120, 200, 3, 16, 8, dp.PAD_REFLECT),
+           (65, 33, 4, 12, 4, dp.PAD_NONE), (256, 256, 3, 32, 8, dp.PAD_SYMMETRIC)]
+    r = rng(71)
+    frames = [dp.FrameParams(H, W, C, dp.U8_HWC, b=b, sb=sb, m=8, eps_bg=0.8, eps_fg=0.4, tau=2, pad_mode=pad,
+                             seed=3, frame_index=i) for i, (H, W, C, b, sb, pad) in enumerate(geo)]
+    plan = dp.Plan(frames, device=dev)
+    imgs = [torch.from_numpy(synth.gradient_image(r, H, W, C)).to(dev) for (H, W, C, _, _, _) in geo]
+    zeros = [torch.zeros((H, W), dtype=torch.uint8, device=dev) for (H, W, _, _, _, _) in geo]
+    busy = [torch.from_numpy((r.random((H, W)) < 0.5).astype(np.uint8)).to(dev) for (H, W, _, _, _, _) in geo]
+    s_zero = plan.new_store()
+    s_none = plan.new_store()
+    s_zero.state.zero_()                    # alignment gaps between the state's arrays compare equal
+    s_none.state.zero_()
+    plan.plan(zeros, store=s_zero)
+    plan.plan(busy, store=s_none)          # leave complex cells and offsets behind first
+    say("case: plan without masks over a stale store")
+    plan.plan(None, store=s_none)
+    torch.cuda.synchronize()
+    assert torch.equal(s_none.flags, s_zero.flags) and int(s_none.flags.sum()) == 0
+    assert torch.equal(s_none.counts, s_zero.counts)
+    assert torch.equal(s_none.state, s_zero.state)
+    outs = [torch.empty_like(t) for t in imgs]
+    plan.forward(imgs, out=outs, store=s_none)
+    torch.cuda.synchronize()
+    got = s_none.host()
+    for i, fp in enumerate(frames):
+        want = oracle.forward(imgs[i].cpu().numpy(), None, oracle_params(fp))
+        compare_frame(got[i], want, outs[i].cpu().numpy(), "no-mask frame %d" % i)
