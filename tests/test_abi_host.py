@@ -283,3 +283,15 @@ def test_host_masks_and_in_place_outputs_are_refused():
     big = torch.zeros((16, 12, 3), dtype=torch.uint8)
     dp.check_no_alias([big[:8]], [big[8:]])
     dp.check_no_alias([x], [torch.zeros_like(x)])
+
+
+@pytest.mark.parametrize("H,W,b,K", [(576, 768, 16, 24), (576, 768, 32, 12), (1080, 1920, 32, 20), (1080, 1920, 16, 40),
+                                     (4000, 6000, 16, 42), (4000, 6000, 32, 21), (2160, 3840, 16, 40)])
+def test_default_tile_width(H, W, b, K):
+    """The library's tile width for RGB frames: each band's padded row cut
+    into the fewest tiles of at most about 2 KB (a band of 2304 bytes is two
+    tiles), the widths the profiled batches ran with."""
+    st, h, L = create([dp.FrameParams(H, W, 3, b=b, sb=b // 4, m=16, eps_bg=1.0, eps_fg=0.3)])
+    assert st == 0
+    assert info(h, L).tile_cells == K
+    L.dp_pix_plan_destroy(h)
