@@ -288,3 +288,29 @@ def test_on_done_hook_sees_results_and_replay_drops_them():
     kept = serve_streams(_tiny_streams(rng), Scheduler(CpuBackend(), MemoryLedger(1 << 20), clock=FakeClock()), params,
                          keep_results=True, clock=FakeClock())
     assert all(r.result is not None for r in kept)
+
+
+def test_stream_that_stops_sending_does_not_hold_back_the_others():
+    """One stream sends two frames and goes silent; the other streams keep
+    arriving.  Every frame sent is served with its own result, in per-stream
+    order, nothing waits for the silent stream, and its saved counter state
+    resumes it after the two frames it did send."""
+    from paper_2511_04261_amd.serving import StreamSpec, serve_streams
+    rng = np.random.Generator(np.random.PCG64(8))
+    streams = _tiny_streams(rng, n_streams=3, frames=6)
+    s = streams[1]
+    streams[1] = StreamSpec(s.stream, s.height, s.width, s.arrivals[:2], s.pool_images, s.pool_masks)
+    params = dict(b=8, sb=4, m=4, eps_bg=1.0, eps_fg=0.5, tau=1)
+    counters = StreamCounters(12)
+    done = serve_streams(streams, Scheduler(CpuBackend(), MemoryLedger(1 << 20), clock=FakeClock()), params,
+                         keep_results=True, clock=FakeClock(), counters=counters)
+    assert len(done) == 6 + 2 + 6 and all(r.error is None and r.result is not None for r in done)
+    for sid, n in ((0, 6), (1, 2), (2, 6)):
+        mine = [r for r in done if r.stream == sid]
+        assert len(mine) == n
+        seq = [r.frame_index & ((1 << StreamCounters.STREAM_SHIFT) - 1) for r in mine]
+        assert seq == sorted(seq) == list(range(n))
+    # the silent stream resumes after the frames it sent
+    restored = StreamCounters.from_state(counters.state())
+    assert restored.take(1) & ((1 << StreamCounters.STREAM_SHIFT) - 1) == 2
+    assert restored.take(0) & ((1 << StreamCounters.STREAM_SHIFT) - 1) == 6
