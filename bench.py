@@ -687,7 +687,7 @@ def headline_entry(out, res, plan, tinfo, launch, warmup):
                      "timing": "HIP events around back-to-back dp_pix_forward calls on the library stream; a call "
                                "is one launch per group of frames sharing a workgroup size, and per-launch figures "
                                "are the call's divided by its launches"},
-        "plan_kernel": {"kernel": "k_plan + k_scan_prefix or k_scan (one dp_pix_plan call)",
+        "plan_kernel": {"kernel": "k_plan + k_scan_prefix, or k_plan + k_scan_tiles + k_scan_frames (one dp_pix_plan call)",
                         "avg_call_ms": round(res["plan_ms"], 4), "alg_bytes_per_call": ab["plan"],
                         "gbs": frac(ab["plan"], res["plan_ms"])[0]},
         "step_gbs_algorithmic": step_gbs,

@@ -17,8 +17,7 @@ constexpr int kStrip = 16;             // bytes one lane moves per row (dwordx4)
 constexpr int kMaxThreads = 512;
 constexpr int kMaxB = 256;             // 255 * 256 rows fits a 16-bit lane sum
 constexpr int kMaxGroups = 16;         // launch groups: layout x channels x workgroup size
-constexpr int kTicketWords = 2 * kMaxGroups + 1;  // two per launch group ...
-constexpr int kScanWord = 2 * kMaxGroups;         // ... and the scan's count of finished frames
+constexpr int kTicketWords = 2 * kMaxGroups;      // two per launch group (resident-grid tickets)
 
 // One frame as the kernels see it (host computes everything derivable).
 struct FrameRec {
@@ -53,8 +52,7 @@ struct WsLayout {
 struct StateLayout {
     size_t tile_cnt;      // uint32[n_tiles]: complex cells per tile
     size_t tile_fg;       // uint32[n_tiles]: complex cells of the frame before the tile
-    size_t counters;      // uint32[kTicketWords]: tickets of persistent launches (two per group) and
-                          // the scan's finished-frame count
+    size_t counters;      // uint32[kTicketWords]: tickets of persistent launches (two per group)
     size_t total;
 };
 

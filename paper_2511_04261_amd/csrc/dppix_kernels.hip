@@ -392,11 +392,9 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T* wave_tot, T& total)
     return excl;
 }
 
-// Frame-level pass of the scan: store offsets of every frame (frames
-// concatenated in batch order) into the store counts, ticket reset.  Run by
-// the last workgroup of k_scan; the per-frame totals the others wrote into
-// counts[4f], counts[4f + 1] are read with agent-scope atomic loads after an
-// acquire fence.
+// Frame-level pass of the scan (k_scan_frames, one workgroup, launched after
+// k_scan_tiles): store offsets of every frame (frames concatenated in batch
+// order) from the per-frame counts the tile pass wrote, ticket words reset.
 __device__ void scan_frames(const TileArgs& a, uint64_t* wave_tot)
 {
     uint64_t carry_bg = 0, carry_fg = 0;
@@ -405,10 +403,8 @@ __device__ void scan_frames(const TileArgs& a, uint64_t* wave_tot)
         uint64_t vb = 0, vf = 0;
         if (f < a.n_frames) {
             const FrameRec F = a.frames[f];
-            const uint64_t nb = __hip_atomic_load(&a.counts[4 * f], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const uint64_t nf = __hip_atomic_load(&a.counts[4 * f + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            vb = nb * (uint64_t)F.C;
-            vf = nf * (uint64_t)F.n * (uint64_t)F.n * (uint64_t)F.C;
+            vb = a.counts[4 * f] * (uint64_t)F.C;
+            vf = a.counts[4 * f + 1] * (uint64_t)F.n * (uint64_t)F.n * (uint64_t)F.C;
         }
         uint64_t tb, tf;
         const uint64_t eb = block_exclusive_scan<uint64_t>(vb, wave_tot, tb);
@@ -420,13 +416,14 @@ __device__ void scan_frames(const TileArgs& a, uint64_t* wave_tot)
         carry_bg += tb;
         carry_fg += tf;
     }
-    if (threadIdx.x < kScanWord)
+    if (threadIdx.x < kTicketWords)
         a.ticket[threadIdx.x] = 0;
 }
 
 // ==========================================================================
 // Plan (Algorithm 3 steps 3-6): classify every cell from the mirror-padded
-// mask (k_plan), then scan the complex counts into store offsets (k_scan).
+// mask (k_plan), then scan the complex counts into store offsets (k_scan_prefix,
+// or k_scan_tiles and k_scan_frames).
 // A plan unit is `cnb` bands x `ctx` tiles of one frame.  Each lane sums one
 // 16-byte strip of the mask down up to kPlanRows padded rows with all its
 // loads in flight, then hands the strip's column counts to per-cell counters
@@ -919,15 +916,14 @@ __global__ __launch_bounds__(256) void k_plan_simple(TileArgs a)
 }
 
 // One workgroup per frame: exclusive scan of the per-tile complex counts into
-// each tile's count of complex cells before it; the last workgroup to finish
-// then runs the frame-level pass.  (A separate launch: electing a last
-// workgroup per plan unit would need an agent-scope fence — an L2 write-back
-// and invalidate — in every unit.)
-__global__ __launch_bounds__(256) void k_scan(TileArgs a)
+// each tile's count of complex cells before it, and the frame's simple and
+// complex cell counts; k_scan_frames, launched next, turns the per-frame
+// counts into store offsets.  (Electing a last workgroup here instead needs
+// an agent-scope release in every workgroup, an L2 write-back on gfx950: the
+// plan call of the 256-frame batch took 3 us longer that way.)
+__global__ __launch_bounds__(256) void k_scan_tiles(TileArgs a)
 {
     __shared__ uint32_t wave_tot[9];
-    __shared__ uint64_t wave_tot64[9];
-    __shared__ int s_last;
     const int f = blockIdx.x;
     const FrameRec F = a.frames[f];
     const int64_t nt = (int64_t)F.GR * F.TX;
@@ -943,19 +939,15 @@ __global__ __launch_bounds__(256) void k_scan(TileArgs a)
     }
     if (threadIdx.x == 0) {
         const uint64_t cells = (uint64_t)F.GR * F.GC;
-        __hip_atomic_store(&a.counts[4 * f + 0], cells - carry, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&a.counts[4 * f + 1], (uint64_t)carry, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();                                    // release the totals
-        s_last = atomicAdd(&a.ticket[kScanWord], 1u) == gridDim.x - 1;
+        a.counts[4 * f + 0] = cells - carry;
+        a.counts[4 * f + 1] = (uint64_t)carry;
     }
-    __syncthreads();
-    if (!s_last)
-        return;
-    __threadfence();                                        // acquire the others' totals
+}
+
+__global__ __launch_bounds__(256) void k_scan_frames(TileArgs a)
+{
+    __shared__ uint64_t wave_tot64[9];
     scan_frames(a, wave_tot64);
-    __syncthreads();
-    if (threadIdx.x == 0)
-        atomicExch(&a.ticket[kScanWord], 0u);
 }
 
 // The scan without a hand-off between workgroups, for batches whose frames
@@ -1006,7 +998,7 @@ __global__ __launch_bounds__(256) void k_scan_prefix(TileArgs a)
         a.counts[4 * f + 2] = bb;
         a.counts[4 * f + 3] = fb;
     }
-    if (f == 0 && tid < kScanWord)
+    if (f == 0 && tid < kTicketWords)
         a.ticket[tid] = 0;
 }
 
@@ -2521,8 +2513,13 @@ static hipError_t launch_scan(const TileArgs& a, bool prefix_scan, hipStream_t s
 {
     if (prefix_scan)
         hipLaunchKernelGGL(k_scan_prefix, dim3((unsigned)a.n_frames), dim3(256), 0, s, a);
-    else
-        hipLaunchKernelGGL(k_scan, dim3((unsigned)a.n_frames), dim3(256), 0, s, a);
+    else {
+        hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)a.n_frames), dim3(256), 0, s, a);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(k_scan_frames, dim3(1), dim3(256), 0, s, a);
+    }
     return hipGetLastError();
 }
 
