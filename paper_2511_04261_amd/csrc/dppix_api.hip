@@ -760,7 +760,10 @@ dppix_status_t dp_pix_plan_labels(dppix_plan_t p, const void* const* images, int
     a.images = images;
     a.edge_threshold = threshold;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    hipError_t e = launch_plan_labels(a, p->n_units, plain_threads(p), p->lds[kPlan], p->prefix_scan, s);
+    unsigned channel_mask = 0;
+    for (const FrameRec& F : p->frames)
+        channel_mask |= 1u << F.C;
+    hipError_t e = launch_plan_labels(a, p->n_units, plain_threads(p), p->lds[kPlan], channel_mask, p->prefix_scan, s);
     if (e != hipSuccess)
         return dev_fail(e, "plan launch");
     return DPPIX_OK;

@@ -107,9 +107,10 @@ struct TileArgs {
 constexpr int64_t kPrefixScanTiles = 16384;
 hipError_t launch_plan(const TileArgs& a, int64_t n_units, int threads, size_t lds, bool prefix_scan,
                        hipStream_t s);
-// Plan from the frames' Sobel labels (edge_threshold, images), then the scan.
-hipError_t launch_plan_labels(const TileArgs& a, int64_t n_units, int threads, size_t lds, bool prefix_scan,
-                              hipStream_t s);
+// Plan from the frames' Sobel labels (edge_threshold, images), then the scan;
+// channel_mask: bit C set for every channel count C among the frames.
+hipError_t launch_plan_labels(const TileArgs& a, int64_t n_units, int threads, size_t lds, unsigned channel_mask,
+                              bool prefix_scan, hipStream_t s);
 // Tile counts of complex cells from the store's flags alone, then the scan.
 hipError_t launch_store_index(const TileArgs& a, bool prefix_scan, hipStream_t s);
 hipError_t launch_forward(const TileArgs& a, int layout, int C, int threads, size_t lds, int grid, hipStream_t s);

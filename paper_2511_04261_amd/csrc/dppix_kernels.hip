@@ -880,18 +880,20 @@ __device__ void plan_count_labels(const TileArgs& a, const FrameRec& F, const ui
     }
 }
 
+// One launch per channel count present in the batch: a workgroup whose unit
+// belongs to a frame of another channel count leaves it to that launch (the
+// unit's frame decides before anything is written), so each instantiation
+// carries one pixel width only.
+template <int C>
 __global__ __launch_bounds__(kMaxThreads) void k_plan_labels(TileArgs a)
 {
     extern __shared__ __align__(16) uint8_t lds[];
     __shared__ __align__(16) uint16_t S[(kLabRows + 2) * kLabStride];
+    const int f0 = (int)uniform_u32((uint32_t)a.unit_map[2 * (int64_t)blockIdx.x]);
+    if (a.frames[f0].C != C)
+        return;
     plan_unit(a, lds, [&](const FrameRec& F, int f, int r0, int nb, int c0, int KC, int KCs, uint32_t* cellcnt) {
-        const uint8_t* img = static_cast<const uint8_t*>(a.images[f]);
-        switch (F.C) {
-        case 1: plan_count_labels<1>(a, F, img, r0, nb, c0, KC, KCs, cellcnt, S); break;
-        case 2: plan_count_labels<2>(a, F, img, r0, nb, c0, KC, KCs, cellcnt, S); break;
-        case 3: plan_count_labels<3>(a, F, img, r0, nb, c0, KC, KCs, cellcnt, S); break;
-        default: plan_count_labels<4>(a, F, img, r0, nb, c0, KC, KCs, cellcnt, S); break;
-        }
+        plan_count_labels<C>(a, F, static_cast<const uint8_t*>(a.images[f]), r0, nb, c0, KC, KCs, cellcnt, S);
     });
 }
 
@@ -2543,16 +2545,30 @@ hipError_t launch_plan(const TileArgs& a, int64_t n_units, int threads, size_t l
     return launch_scan(a, prefix_scan, s);
 }
 
-hipError_t launch_plan_labels(const TileArgs& a, int64_t n_units, int threads, size_t lds, bool prefix_scan,
-                              hipStream_t s)
+template <int C>
+static hipError_t launch_plan_labels_c(const TileArgs& a, int64_t n_units, int threads, size_t lds, hipStream_t s)
+{
+    hipError_t e = allow_lds(k_plan_labels<C>, lds);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_plan_labels<C>, dim3((unsigned)n_units), dim3(threads), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_plan_labels(const TileArgs& a, int64_t n_units, int threads, size_t lds, unsigned channel_mask,
+                              bool prefix_scan, hipStream_t s)
 {
     if (n_units == 0)
         return hipSuccess;
-    hipError_t e = allow_lds(k_plan_labels, lds);
-    if (e != hipSuccess)
-        return e;
-    hipLaunchKernelGGL(k_plan_labels, dim3((unsigned)n_units), dim3(threads), lds, s, a);
-    e = hipGetLastError();
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess && (channel_mask & 2u))
+        e = launch_plan_labels_c<1>(a, n_units, threads, lds, s);
+    if (e == hipSuccess && (channel_mask & 4u))
+        e = launch_plan_labels_c<2>(a, n_units, threads, lds, s);
+    if (e == hipSuccess && (channel_mask & 8u))
+        e = launch_plan_labels_c<3>(a, n_units, threads, lds, s);
+    if (e == hipSuccess && (channel_mask & 16u))
+        e = launch_plan_labels_c<4>(a, n_units, threads, lds, s);
     if (e != hipSuccess)
         return e;
     return launch_scan(a, prefix_scan, s);
