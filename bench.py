@@ -509,6 +509,62 @@ def class_batch_run(spec, dev, launches=5):
                       "kernel_source_sha256_16": kernel_source_hash()}), flush=True)
 
 
+def ceilings_run(dev, reps=20):
+    """Practical HBM ceilings of this machine, from the streaming probes
+    (libdppix_probes.so, hand-written 16-byte non-temporal accesses): a linear
+    copy, read and write of 1 GiB, and copies in the forward's tile shape --
+    a workgroup reads a whole tile, waits at a barrier, then writes it -- over
+    64 frames of 1088 rows x 5760 bytes cut into 32-row x 1920-byte tiles (the
+    64-frame 1080p batch at b = 32), and over 5 frames of 4000 rows x 18000
+    bytes (6000-pixel RGB rows, not a whole number of 128-byte lines) cut
+    into 16-row and 32-row x 2016-byte tiles."""
+    import ctypes
+    import torch
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2511_04261_amd", "libdppix_probes.so"))
+    lib.dppix_probe_stream.restype = ctypes.c_int
+    lib.dppix_probe_stream.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                       ctypes.c_uint32, ctypes.c_void_p]
+    lib.dppix_probe_tiles.restype = ctypes.c_int
+    lib.dppix_probe_tiles.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                      ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                      ctypes.c_void_p]
+    stream = torch.cuda.current_stream()
+    sh = ctypes.c_void_p(stream.cuda_stream)
+
+    def checked(rc):
+        if rc != 0:
+            raise RuntimeError("probe launch failed: hipError %d" % rc)
+
+    out = {}
+    n = 1 << 30
+    a = torch.full((n,), 1, dtype=torch.uint8, device=dev)     # every 16-byte word xors to 0
+    b = torch.empty(n, dtype=torch.uint8, device=dev)
+    for name, mode, moved in (("copy", 0, 2 * n), ("read", 1, n), ("write", 2, n)):
+        ms = time_launches(lambda: checked(lib.dppix_probe_stream(mode, a.data_ptr(), b.data_ptr(), n, 0xFFFFFFFF,
+                                                                  sh)), reps, stream)
+        gbs, fr = frac(moved, ms)
+        out["stream_" + name] = dict(bytes=moved, ms=round(ms, 4), gbs=gbs, frac_hbm=fr)
+        log("ceilings: %s %s" % (name, out["stream_" + name]))
+    del a, b
+    torch.cuda.empty_cache()
+    for name, frames, rows, pitch, tile_rows, tile_bytes in (("tiles_1080p_x64_b32", 64, 1088, 5760, 32, 1920),
+                                                            ("tiles_6000_x5_b16", 5, 4000, 18000, 16, 2016),
+                                                            ("tiles_6000_x5_b32", 5, 4000, 18000, 32, 2016)):
+        fb = rows * pitch
+        a = torch.full((frames * fb,), 1, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        ms = time_launches(lambda: checked(lib.dppix_probe_tiles(a.data_ptr(), b.data_ptr(), frames, fb, pitch, rows,
+                                                                 pitch, tile_rows, tile_bytes, sh)), reps, stream)
+        moved = 2 * frames * fb
+        gbs, fr = frac(moved, ms)
+        out[name] = dict(frames=frames, rows=rows, pitch=pitch, tile_rows=tile_rows, tile_bytes=tile_bytes,
+                         bytes=moved, ms=round(ms, 4), gbs=gbs, frac_hbm=fr)
+        log("ceilings: %s %s" % (name, out[name]))
+        del a, b
+        torch.cuda.empty_cache()
+    return out
+
+
 def kernel_legs_run(dev, reps=3):
     """Profiling run of the standalone kernels (plan, reconstruction, Sobel
     labels as a mask and in the plan, metrics) on the 64-frame 1080p batch:
@@ -717,6 +773,7 @@ def main():
     ap.add_argument("--dump-inputs", default=None, help="write the uneven batch's inputs here and exit")
     ap.add_argument("--class-batch", default=None, help="profiling run over one class, HxW:b:s_b:frames")
     ap.add_argument("--sweep-b", action="store_true", help="step time against the cell size b, then exit")
+    ap.add_argument("--ceilings", action="store_true", help="the streaming probes' HBM ceilings, then exit")
     ap.add_argument("--kernel-legs", action="store_true",
                     help="profiling run of the standalone kernels on the 64-frame 1080p batch (host-rendered inputs)")
     ap.add_argument("--serve-only", action="store_true",
@@ -746,6 +803,9 @@ def main():
         return
     if args.kernel_legs:
         kernel_legs_run(dev)
+        return
+    if args.ceilings:
+        print(json.dumps({"ceilings": ceilings_run(dev)}), flush=True)
         return
     if args.serve_only:
         log("bench: serving %.0f s of 16 camera streams" % args.serve_seconds)
@@ -805,6 +865,8 @@ def main():
         p2.close()
         del p2, i2, m2, o2, r2
         torch.cuda.empty_cache()
+        log("bench: HBM ceilings of the streaming probes")
+        out["ceilings"] = ceilings_run(dev)
         log("bench: single 256x256 frame latency")
         out["single_frame"] = run_single_frame(dev)
         log("bench: fp32 autograd batch (forward + adjoint)")

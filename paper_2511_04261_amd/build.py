@@ -9,6 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SOURCES = [os.path.join(HERE, "csrc", "dppix_kernels.hip"), os.path.join(HERE, "csrc", "dppix_api.hip")]
 OUT = os.path.join(HERE, "libdppix.so")
+PROBE_SOURCES = [os.path.join(HERE, "csrc", "dppix_probes.hip")]
+PROBE_OUT = os.path.join(HERE, "libdppix_probes.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed fp32 instructions are disabled: hipcc would form them from plain
@@ -20,8 +22,16 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
 
 
 def build(verbose: bool = False) -> str:
-    tmp = OUT + ".tmp%d" % os.getpid()
-    cmd = [HIPCC] + FLAGS + ["-o", tmp] + SOURCES
+    """libdppix.so, then the streaming probes' libdppix_probes.so (the HBM
+    ceilings bench.py --ceilings measures)."""
+    _compile(SOURCES, OUT, verbose)
+    _compile(PROBE_SOURCES, PROBE_OUT, verbose)
+    return OUT
+
+
+def _compile(sources, out, verbose):
+    tmp = out + ".tmp%d" % os.getpid()
+    cmd = [HIPCC] + FLAGS + ["-o", tmp] + sources
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -31,8 +41,7 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError("hipcc failed:\n" + "\n".join(noise))
     if verbose and noise:
         print("\n".join(noise), file=sys.stderr)
-    os.replace(tmp, OUT)
-    return OUT
+    os.replace(tmp, out)
 
 
 if __name__ == "__main__":
