@@ -11,10 +11,14 @@ s_b in {4, 8} and budgets, 8-rectangle foreground masks, tile shapes from the
 autotuner, plan + forward captured once in a HIP graph and replayed per step.
 Reported beside it: the 64-frame 1080p batch, both batches with the same
 kernels launched once per frame, every other kernel of the library on its own,
-the single-frame latency, the fp32 autograd batch, the serving loop at the
-camera rate and under heavier load, and the CPU oracle on a bounded sample.
+the HBM ceilings of the streaming probes (linear and tile-shaped copies), the
+single-frame latency, the fp32 autograd batch, the serving loop at the camera
+rate and under heavier load, and the CPU oracle on a bounded sample.
 
-Prints ONE JSON line.
+Prints ONE JSON line.  Other modes (each prints its own line and exits):
+--counters (short run for rocprofv3 --pmc), --class-batch, --kernel-legs
+(profiling runs), --ceilings, --sweep-b (time against the cell size),
+--serve-only, --dump-inputs.
 """
 from __future__ import annotations
 
