@@ -653,8 +653,8 @@ __global__ __launch_bounds__(kMaxThreads) void k_plan(TileArgs a)
 // staged as channel sums in LDS (one halo row and column on every side) and
 // counted without knowing which positions are real.
 // --------------------------------------------------------------------------
-constexpr int kLabRows = 32;                      // padded rows per chunk (within one band)
-constexpr int kLabCols = 256;                     // padded columns per chunk
+constexpr int kLabRows = 16;                      // padded rows per chunk (within one band)
+constexpr int kLabCols = 512;                     // padded columns per chunk (16 x 512: fastest of 8-32 x 128-1024)
 constexpr int kLabPad = 8;                        // LDS columns before column 0 (16-byte aligned rows)
 constexpr int kLabStride = kLabCols + 2 * kLabPad;
 
