@@ -2237,16 +2237,26 @@ __device__ __forceinline__ Moments row_moments(const uint8_t* xr, const uint8_t*
     return m;
 }
 
+// Every factor of a product here is below 2^24 (s0, s1 <= 49 * 255, s4 and
+// s2 + s3 <= 2 * 49 * 255^2), so the 24-bit multiplier forms them exactly at
+// full rate.  The quotient: the hardware reciprocal refined by two Newton
+// steps, then one residual correction of the product (the denominator is a
+// normal number of at most 2^62, so no scaling is needed).
 __device__ __forceinline__ double ssim_window(const uint32_t (&t)[5])
 {
     const double c1 = (0.01 * 255.0) * (0.01 * 255.0), c2 = (0.03 * 255.0) * (0.03 * 255.0);
-    const int32_t s0 = (int32_t)t[0], s1 = (int32_t)t[1];
-    const int32_t p01 = s0 * s1, q = s0 * s0 + s1 * s1;
+    const uint32_t s0 = t[0], s1 = t[1];
+    const int32_t p01 = (int32_t)__umul24(s0, s1), q = (int32_t)(__umul24(s0, s0) + __umul24(s1, s1));
     const double A = (double)(2 * p01) + 2401.0 * c1;
-    const double B = (double)(2 * (49 * (int32_t)t[4] - p01)) + 2352.0 * c2;
+    const double B = (double)(2 * ((int32_t)__umul24(49u, t[4]) - p01)) + 2352.0 * c2;
     const double D = (double)q + 2401.0 * c1;
-    const double E = (double)(49 * (int32_t)(t[2] + t[3]) - q) + 2352.0 * c2;
-    return (A * B) / (D * E);
+    const double E = (double)((int32_t)__umul24(49u, t[2] + t[3]) - q) + 2352.0 * c2;
+    const double num = A * B, den = D * E;
+    double r = __builtin_amdgcn_rcp(den);
+    r = fma(r, fma(-den, r, 1.0), r);
+    r = fma(r, fma(-den, r, 1.0), r);
+    const double quo = num * r;
+    return fma(fma(-den, quo, num), r, quo);
 }
 
 // Stage nrs rows of the byte span [bx, bx + sb) of both frames (row k starts
