@@ -2182,22 +2182,33 @@ __global__ __launch_bounds__(kMaxThreads) void k_edge_mask(TileArgs a)
 //   D = s0^2 + s1^2 + 49^2 c1,        E = 49 (s2 + s3) - s0^2 - s1^2 + 49 * 48 c2,
 // every integer part below 2^31.
 //
-// A tile's window centres are covered in chunks of one lane per byte column
-// (pixel and channel) and up to kMetRowsMax centre rows; the chunk's rows,
-// with 3 more on each side, are staged in LDS (all of them inside the frame,
-// since every window is).  A lane walks down its column: the 7-wide sums of
-// the five moments of each new row go into a ring of the last 7 rows in
-// registers, and the window sum is updated by the new row minus the row that
-// leaves it.
+// A tile's window centres are covered in chunks of one lane per (channel,
+// pixel) pair and up to kMetRowsMax centre rows; the chunk's rows, with 3
+// more on each side, are staged in LDS as one plane per channel (all of them
+// inside the frame, since every window is), so that the 7 taps of a window
+// row are consecutive bytes: a lane reads them as two words and forms the
+// row's five moments with byte dot products.  A lane walks down its column:
+// the moments of each new row go into a ring of the last 7 rows in
+// registers, and the window sum is updated by the new row minus the row
+// that leaves it.
 // ==========================================================================
 constexpr int kMetRowsMax = 32;                 // window-centre rows per chunk
 constexpr int kMetStage = kMetRowsMax + 6;      // staged rows per chunk
-constexpr int kMetSpan = 256 + 24;              // staged bytes per row (lanes + 6 pixels of up to 4 channels)
-constexpr int kMetCols = 304;                   // LDS row: a span shifted by up to 15 bytes, 16-byte rows
 
+// Window-centre pixels per chunk (at most 256 lanes of (channel, pixel)) and
+// bytes per staged plane row: a row holds the chunk's pixels and the 6 of the
+// windows' reach, starting up to 15 pixels early at a 16-pixel boundary, and
+// a lane's three words read past its last tap stay inside it.
+template <int C>
+struct MetShape {
+    static constexpr int kCw = 256 / C;
+    static constexpr int kRow = (kCw + 26 + 15) & ~15;
+};
+
+template <int C>
 struct MetLds {
-    alignas(16) uint8_t x[kMetStage][kMetCols];
-    alignas(16) uint8_t y[kMetStage][kMetCols];
+    alignas(16) uint8_t x[C][kMetStage][MetShape<C>::kRow];
+    alignas(16) uint8_t y[C][kMetStage][MetShape<C>::kRow];
     double red[kMaxThreads / 64];
     unsigned long long red_se[kMaxThreads / 64];
 };
@@ -2221,27 +2232,30 @@ struct Moments {
     uint32_t s[5];   // sum x, sum y, sum x^2, sum y^2, sum xy
 };
 
-template <int C>
-__device__ __forceinline__ Moments row_moments(const uint8_t* xr, const uint8_t* yr, int q)
+// The five moments of the 7 taps that start `a` bytes into the word xr[0]
+// (and yr[0]) of a plane row: the taps as two words (the second one's top
+// byte cleared), byte sums and byte products by 4-way dot products.
+__device__ __forceinline__ Moments row_moments(const uint32_t* xr, const uint32_t* yr, uint32_t a)
 {
-    Moments m = {{0u, 0u, 0u, 0u, 0u}};
-#pragma unroll
-    for (int d = 0; d < 7; ++d) {
-        const uint32_t u = xr[q + d * C], v = yr[q + d * C];
-        m.s[0] += u;
-        m.s[1] += v;
-        m.s[2] += u * u;
-        m.s[3] += v * v;
-        m.s[4] += u * v;
-    }
+    const uint32_t x0 = __builtin_amdgcn_alignbyte(xr[1], xr[0], a);
+    const uint32_t x1 = __builtin_amdgcn_alignbyte(xr[2], xr[1], a) & 0x00FFFFFFu;
+    const uint32_t y0 = __builtin_amdgcn_alignbyte(yr[1], yr[0], a);
+    const uint32_t y1 = __builtin_amdgcn_alignbyte(yr[2], yr[1], a) & 0x00FFFFFFu;
+    constexpr uint32_t one = 0x01010101u;
+    Moments m;
+    m.s[0] = __builtin_amdgcn_udot4(x1, one, __builtin_amdgcn_udot4(x0, one, 0u, false), false);
+    m.s[1] = __builtin_amdgcn_udot4(y1, one, __builtin_amdgcn_udot4(y0, one, 0u, false), false);
+    m.s[2] = __builtin_amdgcn_udot4(x1, x1, __builtin_amdgcn_udot4(x0, x0, 0u, false), false);
+    m.s[3] = __builtin_amdgcn_udot4(y1, y1, __builtin_amdgcn_udot4(y0, y0, 0u, false), false);
+    m.s[4] = __builtin_amdgcn_udot4(x1, y1, __builtin_amdgcn_udot4(x0, y0, 0u, false), false);
     return m;
 }
 
 // Every factor of a product here is below 2^24 (s0, s1 <= 49 * 255, s4 and
 // s2 + s3 <= 2 * 49 * 255^2), so the 24-bit multiplier forms them exactly at
 // full rate.  The quotient: the hardware reciprocal refined by two Newton
-// steps, then one residual correction of the product (the denominator is a
-// normal number of at most 2^62, so no scaling is needed).
+// steps (the denominator is a normal number of at most 2^62, so no scaling
+// is needed), times the numerator.
 __device__ __forceinline__ double ssim_window(const uint32_t (&t)[5])
 {
     const double c1 = (0.01 * 255.0) * (0.01 * 255.0), c2 = (0.03 * 255.0) * (0.03 * 255.0);
@@ -2255,60 +2269,87 @@ __device__ __forceinline__ double ssim_window(const uint32_t (&t)[5])
     double r = __builtin_amdgcn_rcp(den);
     r = fma(r, fma(-den, r, 1.0), r);
     r = fma(r, fma(-den, r, 1.0), r);
-    const double quo = num * r;
-    return fma(fma(-den, quo, num), r, quo);
+    return num * r;
 }
 
-// Stage nrs rows of the byte span [bx, bx + sb) of both frames (row k starts
-// at byte r0 + k * pitch): byte bx + q of row k goes to L.x[k][sh + q] with
-// sh = bx mod 16 when the rows are 16-byte aligned, so that the 16-byte blocks
-// inside the span land on 16-byte LDS positions and move as vectors; the
-// bytes before the first block and after the last one move singly.  Loads of
-// a batch of items are all issued before the first LDS write.
-__device__ __forceinline__ void stage_metrics_rows(const g_u8* X, const g_u8* Y, int64_t pitch, int64_t r0, int64_t bx,
-                                                   int sb, int nrs, bool rows16, MetLds& L)
+// Sixteen pixels of C interleaved channels (C 16-byte vectors; pixel i's
+// channel c at byte C i + c) as C planes of 16 bytes, by byte permutes.
+template <int C>
+__device__ __forceinline__ void deinterleave16(const v4u (&v)[C], v4u (&p)[C])
+{
+    uint32_t d[4 * C], o[4 * C];   // o[4 c + j]: pixels 4 j .. 4 j + 3 of channel c
+#pragma unroll
+    for (int i = 0; i < C; ++i) {
+        d[4 * i] = v[i].x;
+        d[4 * i + 1] = v[i].y;
+        d[4 * i + 2] = v[i].z;
+        d[4 * i + 3] = v[i].w;
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if constexpr (C == 1) {
+                o[j] = d[j];
+            } else if constexpr (C == 2) {
+                o[4 * c + j] = __builtin_amdgcn_perm(d[2 * j + 1], d[2 * j], 0x06040200u + 0x01010101u * c);
+            } else if constexpr (C == 3) {
+                constexpr uint32_t lo[3] = {0x0C060300u, 0x0C070401u, 0x0C0C0502u};
+                constexpr uint32_t hi[3] = {0x05020100u, 0x06020100u, 0x07040100u};
+                o[4 * c + j] = __builtin_amdgcn_perm(d[3 * j + 2], __builtin_amdgcn_perm(d[3 * j + 1], d[3 * j], lo[c]),
+                                                     hi[c]);
+            } else {
+                const uint32_t sel = 0x0C0C0400u + 0x0101u * c;
+                o[4 * c + j] = __builtin_amdgcn_perm(__builtin_amdgcn_perm(d[4 * j + 3], d[4 * j + 2], sel),
+                                                     __builtin_amdgcn_perm(d[4 * j + 1], d[4 * j], sel), 0x05040100u);
+            }
+        }
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+        p[c] = v4u{o[4 * c], o[4 * c + 1], o[4 * c + 2], o[4 * c + 3]};
+}
+
+// Stage nrs rows (row k at byte r0 + k * pitch) of the pixels [p0, p0 + np)
+// of both frames, all inside the frame's width W, as channel planes: channel
+// c of pixel p0 + q in row k goes to L.x[c][k][q].  With 16-byte aligned rows
+// (`vec`) and p0 a multiple of 16, the 16-pixel groups that end inside the
+// width move as C 16-byte vectors per frame (the last one may stage pixels
+// past p0 + np, inside the frame and the plane row); the pixels after them
+// move byte by byte.  Loads of a batch of items are all issued before the
+// first LDS write.
+template <int C>
+__device__ __forceinline__ void stage_metrics_planes(const g_u8* X, const g_u8* Y, int64_t pitch, int64_t r0, int p0,
+                                                     int np, int nrs, int W, bool vec, MetLds<C>& L)
 {
     const int tid = threadIdx.x, NT = blockDim.x;
-    const int sh = rows16 ? (int)(bx & 15) : 0;
-    const int64_t a0 = (bx + 15) & ~(int64_t)15, a1 = (bx + sb) & ~(int64_t)15;
-    const int nblk = (rows16 && a1 > a0) ? (int)((a1 - a0) >> 4) : 0;
-    const int head = nblk ? (int)(a0 - bx) : sb;           // single bytes before the first block
-    const int tail = nblk ? (int)(bx + sb - a1) : 0;        // and after the last
-    const int qb = head;                                     // span offset of the first block
-    constexpr int kB = 3, kBb = 4;
-    const int nv = nrs * nblk;
-    for (int base = 0; base < nv; base += kB * NT) {
-        v4u wx[kB], wy[kB];
+    const int ngv = vec ? min((np + 15) >> 4, (W - p0) >> 4) : 0;
+    const int nv = nrs * ngv;
+    // items (frame, row, group): a lane holds one group's C vectors at a time
+    for (int it = tid; it < 2 * nv; it += NT) {
+        const int fy = it >= nv, r = it - fy * nv;
+        const int k = r / ngv, g = r - k * ngv;
+        const g_u8* src = fy ? Y : X;
+        const int64_t at = r0 + (int64_t)k * pitch + (int64_t)(p0 + 16 * g) * C;
+        v4u w[C], pl[C];
 #pragma unroll
-        for (int i = 0; i < kB; ++i) {
-            const int it = base + i * NT + tid;
-            if (it < nv) {
-                const int k = it / nblk, g = it - k * nblk;
-                const int64_t at = r0 + (int64_t)k * pitch + a0 + 16 * g;
-                wx[i] = ld16_nt((const void*)(X + at));
-                wy[i] = ld16_nt((const void*)(Y + at));
-            }
-        }
+        for (int c = 0; c < C; ++c)
+            w[c] = ld16_nt((const void*)(src + at + 16 * c));
+        deinterleave16<C>(w, pl);
+        uint8_t(&dst)[C][kMetStage][MetShape<C>::kRow] = fy ? L.y : L.x;
 #pragma unroll
-        for (int i = 0; i < kB; ++i) {
-            const int it = base + i * NT + tid;
-            if (it < nv) {
-                const int k = it / nblk, g = it - k * nblk;
-                *reinterpret_cast<v4u*>(&L.x[k][sh + qb + 16 * g]) = wx[i];
-                *reinterpret_cast<v4u*>(&L.y[k][sh + qb + 16 * g]) = wy[i];
-            }
-        }
+        for (int c = 0; c < C; ++c)
+            *reinterpret_cast<v4u*>(&dst[c][k][16 * g]) = pl[c];
     }
-    const int nsb = head + tail, ns = nrs * nsb;
+    const int q0 = 16 * ngv, nb = max(0, np - q0) * C, ns = nrs * nb;
+    constexpr int kBb = 4;
     for (int base = 0; base < ns; base += kBb * NT) {
         uint8_t bxv[kBb], byv[kBb];
 #pragma unroll
         for (int i = 0; i < kBb; ++i) {
             const int it = base + i * NT + tid;
             if (it < ns) {
-                const int k = it / nsb, j = it - k * nsb;
-                const int q = j < head ? j : sb - tail + (j - head);
-                const int64_t at = r0 + (int64_t)k * pitch + bx + q;
+                const int k = it / nb, j = it - k * nb;
+                const int64_t at = r0 + (int64_t)k * pitch + (int64_t)(p0 + q0) * C + j;
                 bxv[i] = X[at];
                 byv[i] = Y[at];
             }
@@ -2317,17 +2358,17 @@ __device__ __forceinline__ void stage_metrics_rows(const g_u8* X, const g_u8* Y,
         for (int i = 0; i < kBb; ++i) {
             const int it = base + i * NT + tid;
             if (it < ns) {
-                const int k = it / nsb, j = it - k * nsb;
-                const int q = j < head ? j : sb - tail + (j - head);
-                L.x[k][sh + q] = bxv[i];
-                L.y[k][sh + q] = byv[i];
+                const int k = it / nb, j = it - k * nb;
+                const int q = j / C, c = j - q * C;
+                L.x[c][k][q0 + q] = bxv[i];
+                L.y[c][k][q0 + q] = byv[i];
             }
         }
     }
 }
 
 template <int C>
-__device__ void metrics_tile(const TileArgs& a, const FrameRec& F, const TileCoord& tc, MetLds& L)
+__device__ void metrics_tile(const TileArgs& a, const FrameRec& F, const TileCoord& tc, MetLds<C>& L)
 {
     const int tid = threadIdx.x, NT = blockDim.x;
     const int b = F.b, H = F.H, W = F.W;
@@ -2379,20 +2420,25 @@ __device__ void metrics_tile(const TileArgs& a, const FrameRec& F, const TileCoo
     // SSIM windows centred in this tile's real pixels, 3 away from every edge
     const int cy0 = max(y0, 3), cy1 = min(y1, H - 3);
     const int cx0 = max(xa, 3), cx1 = min(xb, W - 3);
-    const int CW = min(NT / C, kMetSpan / C - 6);   // window-centre pixels per chunk (lanes, and the staged row)
-    const bool rows16 = ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Y) | (uintptr_t)pitch) & 15) == 0;
+    const int CW = min(NT, 256) / C;                  // window-centre pixels per chunk
+    constexpr int kRowW = MetShape<C>::kRow / 4;      // words per plane row
+    const bool vec = ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Y) | (uintptr_t)pitch) & 15) == 0;
     for (int cxb = cx0; cxb < cx1; cxb += CW) {
         const int cw = min(CW, cx1 - cxb);
-        const int sb = (cw + 6) * C;                        // staged bytes per row
-        const int64_t bx = (int64_t)(cxb - 3) * C;
+        const int pa = cxb - 3;                         // first pixel a window of the chunk reads
+        const int p0 = vec ? (pa & ~15) : pa;
+        const int sh = pa - p0;
+        const int np = sh + cw + 6;                     // staged pixels from p0
+        const int ch = tid / cw, px = tid - ch * cw;    // this lane's (channel, centre pixel)
+        const uint32_t o = (uint32_t)(sh + px);
         for (int cyb = cy0; cyb < cy1; cyb += kMetRowsMax) {
             const int rb = min(kMetRowsMax, cy1 - cyb);
             const int nrs = rb + 6;
-            stage_metrics_rows(Xg, Yg, pitch, (int64_t)(cyb - 3) * pitch, bx, sb, nrs, rows16, L);
+            stage_metrics_planes<C>(Xg, Yg, pitch, (int64_t)(cyb - 3) * pitch, p0, np, nrs, W, vec, L);
             lds_barrier();
-            const int sh = rows16 ? (int)(bx & 15) : 0;
-            const int q = tid;
-            if (q < cw * C) {
+            if (ch < C) {
+                const uint32_t* xr = reinterpret_cast<const uint32_t*>(&L.x[ch][0][0]) + (o >> 2);
+                const uint32_t* yr = reinterpret_cast<const uint32_t*>(&L.y[ch][0][0]) + (o >> 2);
                 Moments ring[7];
                 uint32_t t[5] = {0u, 0u, 0u, 0u, 0u};
                 for (int k0 = 0; k0 < nrs; k0 += 7) {
@@ -2400,7 +2446,7 @@ __device__ void metrics_tile(const TileArgs& a, const FrameRec& F, const TileCoo
                     for (int j = 0; j < 7; ++j) {
                         const int k = k0 + j;
                         if (k < nrs) {
-                            const Moments h = row_moments<C>(L.x[k] + sh, L.y[k] + sh, q);
+                            const Moments h = row_moments(xr + k * kRowW, yr + k * kRowW, o & 3u);
 #pragma unroll
                             for (int m = 0; m < 5; ++m)
                                 t[m] += h.s[m] - (k >= 7 ? ring[j].s[m] : 0u);
@@ -2439,9 +2485,9 @@ __device__ void metrics_tile(const TileArgs& a, const FrameRec& F, const TileCoo
 }
 
 template <int C>
-__global__ __launch_bounds__(kMaxThreads) void k_metrics(TileArgs a)
+__global__ __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(C < 4 ? 5 : 4))) void k_metrics(TileArgs a)
 {
-    __shared__ MetLds L;
+    __shared__ MetLds<C> L;
     extern __shared__ __align__(16) uint8_t lds[];
     run_tiles(a, lds, [&](const FrameRec& F, const TileCoord& tc) { metrics_tile<C>(a, F, tc, L); });
 }
