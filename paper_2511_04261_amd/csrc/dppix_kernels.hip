@@ -2229,12 +2229,15 @@ __device__ __forceinline__ uint32_t sq_diff16(const v4u& x, const v4u& y)
 }
 
 struct Moments {
-    uint32_t s[5];   // sum x, sum y, sum x^2, sum y^2, sum xy
+    uint32_t s[4];   // sum x | sum y << 16, sum x^2, sum y^2, sum xy
 };
 
 // The five moments of the 7 taps that start `a` bytes into the word xr[0]
 // (and yr[0]) of a plane row: the taps as two words (the second one's top
-// byte cleared), byte sums and byte products by 4-way dot products.
+// byte cleared), byte sums and byte products by 4-way dot products.  The two
+// byte sums (at most 7 * 255 each) share a word, and so do their window sums
+// (at most 49 * 255): a window update adds and subtracts both at once, and
+// neither half carries into the other.
 __device__ __forceinline__ Moments row_moments(const uint32_t* xr, const uint32_t* yr, uint32_t a)
 {
     const uint32_t x0 = __builtin_amdgcn_alignbyte(xr[1], xr[0], a);
@@ -2243,31 +2246,34 @@ __device__ __forceinline__ Moments row_moments(const uint32_t* xr, const uint32_
     const uint32_t y1 = __builtin_amdgcn_alignbyte(yr[2], yr[1], a) & 0x00FFFFFFu;
     constexpr uint32_t one = 0x01010101u;
     Moments m;
-    m.s[0] = __builtin_amdgcn_udot4(x1, one, __builtin_amdgcn_udot4(x0, one, 0u, false), false);
-    m.s[1] = __builtin_amdgcn_udot4(y1, one, __builtin_amdgcn_udot4(y0, one, 0u, false), false);
-    m.s[2] = __builtin_amdgcn_udot4(x1, x1, __builtin_amdgcn_udot4(x0, x0, 0u, false), false);
-    m.s[3] = __builtin_amdgcn_udot4(y1, y1, __builtin_amdgcn_udot4(y0, y0, 0u, false), false);
-    m.s[4] = __builtin_amdgcn_udot4(x1, y1, __builtin_amdgcn_udot4(x0, y0, 0u, false), false);
+    const uint32_t sx = __builtin_amdgcn_udot4(x1, one, __builtin_amdgcn_udot4(x0, one, 0u, false), false);
+    const uint32_t sy = __builtin_amdgcn_udot4(y1, one, __builtin_amdgcn_udot4(y0, one, 0u, false), false);
+    m.s[0] = sx | (sy << 16);
+    m.s[1] = __builtin_amdgcn_udot4(x1, x1, __builtin_amdgcn_udot4(x0, x0, 0u, false), false);
+    m.s[2] = __builtin_amdgcn_udot4(y1, y1, __builtin_amdgcn_udot4(y0, y0, 0u, false), false);
+    m.s[3] = __builtin_amdgcn_udot4(x1, y1, __builtin_amdgcn_udot4(x0, y0, 0u, false), false);
     return m;
 }
 
 // Every factor of a product here is below 2^24 (s0, s1 <= 49 * 255, s4 and
 // s2 + s3 <= 2 * 49 * 255^2), so the 24-bit multiplier forms them exactly at
-// full rate.  The quotient: the hardware reciprocal refined by two Newton
-// steps (the denominator is a normal number of at most 2^62, so no scaling
-// is needed), times the numerator.
-__device__ __forceinline__ double ssim_window(const uint32_t (&t)[5])
+// full rate.  The quotient: the hardware reciprocal refined by one Newton
+// step, which squares its relative error (the mean of the windows is held to
+// 1e-9 of the oracle's; the denominator is a normal number of at most 2^62,
+// so no scaling is needed), times the numerator.  t[0] packs sum x (low
+// half) and sum y (high half), each at most 49 * 255; t[1..3] are sum x^2,
+// sum y^2 and sum xy.
+__device__ __forceinline__ double ssim_window(const uint32_t (&t)[4])
 {
     const double c1 = (0.01 * 255.0) * (0.01 * 255.0), c2 = (0.03 * 255.0) * (0.03 * 255.0);
-    const uint32_t s0 = t[0], s1 = t[1];
+    const uint32_t s0 = t[0] & 0xFFFFu, s1 = t[0] >> 16;
     const int32_t p01 = (int32_t)__umul24(s0, s1), q = (int32_t)(__umul24(s0, s0) + __umul24(s1, s1));
     const double A = (double)(2 * p01) + 2401.0 * c1;
-    const double B = (double)(2 * ((int32_t)__umul24(49u, t[4]) - p01)) + 2352.0 * c2;
+    const double B = (double)(2 * ((int32_t)__umul24(49u, t[3]) - p01)) + 2352.0 * c2;
     const double D = (double)q + 2401.0 * c1;
-    const double E = (double)((int32_t)__umul24(49u, t[2] + t[3]) - q) + 2352.0 * c2;
+    const double E = (double)((int32_t)__umul24(49u, t[1] + t[2]) - q) + 2352.0 * c2;
     const double num = A * B, den = D * E;
     double r = __builtin_amdgcn_rcp(den);
-    r = fma(r, fma(-den, r, 1.0), r);
     r = fma(r, fma(-den, r, 1.0), r);
     return num * r;
 }
@@ -2440,7 +2446,7 @@ __device__ void metrics_tile(const TileArgs& a, const FrameRec& F, const TileCoo
                 const uint32_t* xr = reinterpret_cast<const uint32_t*>(&L.x[ch][0][0]) + (o >> 2);
                 const uint32_t* yr = reinterpret_cast<const uint32_t*>(&L.y[ch][0][0]) + (o >> 2);
                 Moments ring[7];
-                uint32_t t[5] = {0u, 0u, 0u, 0u, 0u};
+                uint32_t t[4] = {0u, 0u, 0u, 0u};
                 for (int k0 = 0; k0 < nrs; k0 += 7) {
 #pragma unroll
                     for (int j = 0; j < 7; ++j) {
@@ -2448,8 +2454,8 @@ __device__ void metrics_tile(const TileArgs& a, const FrameRec& F, const TileCoo
                         if (k < nrs) {
                             const Moments h = row_moments(xr + k * kRowW, yr + k * kRowW, o & 3u);
 #pragma unroll
-                            for (int m = 0; m < 5; ++m)
-                                t[m] += h.s[m] - (k >= 7 ? ring[j].s[m] : 0u);
+                            for (int m = 0; m < 4; ++m)
+                                t[m] = (t[m] + h.s[m]) - (k >= 7 ? ring[j].s[m] : 0u);
                             ring[j] = h;
                             if (k >= 6)
                                 ssim_acc += ssim_window(t);
