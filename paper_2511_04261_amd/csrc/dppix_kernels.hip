@@ -1685,6 +1685,16 @@ __device__ void forward_tile_f32(const TileArgs& a, const FrameRec& F, const Til
 // Each launch covers one group of frames sharing layout and channel count
 // (scheduling indices [sched_offset, sched_offset + n_tiles)), so every kernel
 // instantiation carries only its own path.
+// The tile of this workgroup, for kernels that are never launched as a
+// resident grid (the persistent branch would only hold scalar registers).
+template <typename Body>
+__device__ __forceinline__ void run_one_tile(const TileArgs& a, Body body)
+{
+    FrameRec F;
+    const TileCoord tc = tile_of(a, blockIdx.x, F);
+    body(F, tc);
+}
+
 template <typename Body>
 __device__ __forceinline__ void run_tiles(const TileArgs& a, uint8_t* lds, Body body)
 {
@@ -2161,7 +2171,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_edge_mask(TileArgs a)
 {
     __shared__ __align__(16) uint16_t S[(kLabRows + 2) * kLabStride];
     extern __shared__ __align__(16) uint8_t lds[];
-    run_tiles(a, lds, [&](const FrameRec& F, const TileCoord& tc) { edge_tile<C>(a, F, tc, S); });
+    run_one_tile(a, [&](const FrameRec& F, const TileCoord& tc) { edge_tile<C>(a, F, tc, S); });
 }
 
 // ==========================================================================
@@ -2495,7 +2505,7 @@ __global__ __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(C <
 {
     __shared__ MetLds<C> L;
     extern __shared__ __align__(16) uint8_t lds[];
-    run_tiles(a, lds, [&](const FrameRec& F, const TileCoord& tc) { metrics_tile<C>(a, F, tc, L); });
+    run_one_tile(a, [&](const FrameRec& F, const TileCoord& tc) { metrics_tile<C>(a, F, tc, L); });
 }
 
 // One thread per frame: MSE = sum of squared errors / (H W C); SSIM = sum of
