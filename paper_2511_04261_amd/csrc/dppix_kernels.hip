@@ -51,6 +51,7 @@ typedef __attribute__((address_space(1))) v4u g_v4u;
 typedef __attribute__((address_space(1))) v4f g_v4f;
 typedef __attribute__((address_space(1))) const uint8_t g_u8;
 typedef __attribute__((address_space(1))) uint8_t g_u8w;
+typedef __attribute__((address_space(1))) uint16_t g_u16w;
 typedef __attribute__((address_space(1))) const float g_f32;
 typedef __attribute__((address_space(1))) float g_f32w;
 
@@ -2143,6 +2144,8 @@ __device__ void edge_tile(const TileArgs& a, const FrameRec& F, const TileCoord&
         const int rows = min(kLabRows, y1 - cy);
         for (int cx = xa; cx < xb; cx += kLabCols) {
             const int cols = min(kLabCols, xb - cx);
+            // every pair of the chunk starts on an even byte of the mask
+            const bool even = ((reinterpret_cast<uintptr_t>(out) | (uintptr_t)W | (uintptr_t)cx) & 1) == 0;
             stage_label_sums<C>(img, pitch, H, W, pad, cy, rows, cx, cols, aligned, S);
             lds_barrier();
             const int np = (cols + 1) >> 1;
@@ -2151,7 +2154,12 @@ __device__ void edge_tile(const TileArgs& a, const FrameRec& F, const TileCoord&
             if (L.split < L.splits && ya < yb) {
                 for (int p = L.pl; p < np; p += L.step) {
                     g_u8w* o = (g_u8w*)(out + (int64_t)cy * W + cx + 2 * p);
-                    if (2 * p + 1 < cols)
+                    if (2 * p + 1 < cols && even)
+                        label_pair(S, p, ya, yb, thr, [&](int y, uint32_t d) {
+                            // both labels of the pair in one 16-bit store
+                            *(g_u16w*)(o + (int64_t)y * W) = (uint16_t)(((d >> 15) & 1u) | ((d >> 31) << 8));
+                        });
+                    else if (2 * p + 1 < cols)
                         label_pair(S, p, ya, yb, thr, [&](int y, uint32_t d) {
                             o[(int64_t)y * W] = (uint8_t)((d >> 15) & 1u);
                             o[(int64_t)y * W + 1] = (uint8_t)(d >> 31);
