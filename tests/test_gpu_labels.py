@@ -111,3 +111,29 @@ def test_plan_labels_rejects_bad_arguments(dev):
                   device=dev)
     with pytest.raises(dp.DppixError):
         f32.plan_labels([torch.zeros((3, 16, 16), dtype=torch.float32, device=dev)], 10)
+
+
+@pytest.mark.parametrize("H,W,C,b,K", [(40, 203, 3, 5, 7), (33, 250, 1, 3, 9), (21, 96, 4, 5, 3)])
+def test_edge_mask_tiles_starting_on_odd_columns(dev, H, W, C, b, K):
+    """An odd cell size with an odd tile width starts every other tile on an
+    odd mask column (the labels of a pixel pair then go out byte by byte);
+    the masks equal the oracle's, and the path planned from them matches the
+    oracle driven by the oracle's mask."""
+    say("case: edge mask, odd tile starts", H, W, C, b, K)
+    r = np.random.Generator(np.random.PCG64(H * W + K))
+    img = synth.gradient_image(r, H, W, C)
+    img[H // 3: 2 * H // 3, W // 4: W // 2] = 240
+    fp = dp.FrameParams(H, W, C, dp.U8_HWC, b=b, sb=b, m=16, eps_bg=1.0, eps_fg=0.3, tau=2, seed=9,
+                        tile_cells=K)
+    plan = dp.Plan([fp], device=dev)
+    ti = torch.from_numpy(img).to(dev)
+    masks = plan.edge_masks([ti], 30)
+    out = torch.empty_like(ti)
+    plan.plan(masks)
+    plan.forward([ti], out=[out])
+    torch.cuda.synchronize()
+    want_mask = oracle.edge_mask(img, 30, fp.pad_mode)
+    assert np.array_equal(masks[0].cpu().numpy(), want_mask)
+    want = oracle.forward(img, want_mask, oracle_params(fp))
+    compare_frame(plan.store_host()[0], want, out.cpu().numpy(), "odd tile starts %dx%dx%d b%d K%d" % (H, W, C, b, K))
+    plan.close()
